@@ -1,0 +1,536 @@
+"""Pins of the FP64 oracle against facts the paper and mathematics fix.
+
+None of these tests compares the oracle with itself: each checks a closed
+form, an invariant, a textbook special case or a convergence rate.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import Discretisation, physics, reference
+from workloads import configs, fields, meshes
+from workloads.configs import Workload
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _state(d, fn):
+    return [np.ascontiguousarray(np.transpose(fn(b, g.xu), (1, 2, 0)))
+            for b, g in enumerate(d.geoms)]
+
+
+def _integral(d, r):
+    """sum over blocks of W_rho J_rho r[rho, alpha, n] -> per field."""
+    return sum(np.einsum("r,rn,ran->a", rf.W, g.detJ.T, rb)
+               for rf, g, rb in zip(d.refs, d.geoms, r))
+
+
+# --------------------------------------------------------------------------
+# T-1 Gauss-Legendre rules (golden closed forms)
+# --------------------------------------------------------------------------
+def _golden_gl():
+    rows = {}
+    with open(os.path.join(GOLDEN, "gauss_legendre.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            n, x, w = line.split()
+            env = {"sqrt": math.sqrt}
+            rows.setdefault(int(n), []).append((eval(x, env), eval(w, env)))
+    return rows
+
+
+def test_gauss_legendre_closed_forms():
+    for n, pts in _golden_gl().items():
+        x, w = reference.gauss_legendre(n)
+        ex = np.array(sorted(pts))
+        assert np.max(np.abs(x - ex[:, 0])) < 1e-15
+        assert np.max(np.abs(w - ex[:, 1])) < 1e-15
+
+
+@pytest.mark.parametrize("n", range(1, 9))
+def test_gauss_legendre_exactness(n):
+    x, w = reference.gauss_legendre(n)
+    assert abs(w.sum() - 2.0) < 1e-14
+    for k in range(2 * n):
+        exact = 0.0 if k % 2 else 2.0 / (k + 1)
+        assert abs(np.sum(w * x ** k) - exact) < 1e-14
+
+
+# --------------------------------------------------------------------------
+# T-2 nodal basis and polynomial exactness of the interpolation operators
+# --------------------------------------------------------------------------
+def _monomials(etype, p, D):
+    if etype == "tri":
+        return [(a, b) for a in range(p + 1) for b in range(p + 1 - a)]
+    import itertools
+    return list(itertools.product(range(p + 1), repeat=D))
+
+
+@pytest.mark.parametrize("etype,p", [(e, p) for e in ("quad", "tri", "hex") for p in (1, 2, 3, 4)])
+def test_basis_exactness(etype, p):
+    r = reference.ref_element(etype, p)
+    D = r.ndims
+    assert np.max(np.abs(r.basis(r.upts) - np.eye(r.nupts))) < 1e-13
+    for e in _monomials(etype, p, D):
+        fu = np.prod([r.upts[:, d] ** e[d] for d in range(D)], axis=0)
+        ff = np.prod([r.fpts[:, d] ** e[d] for d in range(D)], axis=0)
+        assert np.max(np.abs(r.L_f @ fu - ff)) < 1e-12
+        for i in range(D):
+            dfu = e[i] * np.prod([r.upts[:, d] ** (e[d] - (d == i)) if (e[d] - (d == i)) >= 0
+                                  else 0 * r.upts[:, d] for d in range(D)], axis=0)
+            assert np.max(np.abs(r.D_u[i] @ fu - dfu)) < 1e-11
+
+
+# --------------------------------------------------------------------------
+# T-3 DG correction functions
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("etype,p", [(e, p) for e in ("quad", "tri", "hex") for p in (1, 2, 3, 4)])
+def test_lifting_integrals(etype, p):
+    """sum_rho W_rho (div g_sigma)(x_rho) = face weight omega_sigma, and the
+    interior-minus-normal-trace operator M1 - M3 M2 integrates to zero."""
+    r = reference.ref_element(etype, p)
+    assert np.max(np.abs(r.W @ r.divg - r.fweight)) < 1e-13
+    D = r.ndims
+    M1 = np.concatenate([r.D_u[i] for i in range(D)], axis=1)         # (Nu, D Nu)
+    M2 = np.concatenate([r.fnorm[:, i:i + 1] * r.L_f for i in range(D)], axis=1)
+    M1p = M1 - r.divg @ M2
+    assert np.max(np.abs(r.W @ M1p)) < 1e-12
+    # face weights of the reference faces: quad/hex 2 (or 4), triangle 2, 2, 2 sqrt 2
+    per_face = np.bincount(r.fface, weights=r.fweight)
+    if etype == "tri":
+        assert np.allclose(per_face, [2, 2 * math.sqrt(2), 2], atol=1e-14)
+    else:
+        assert np.allclose(per_face, 2.0 ** (D - 1), atol=1e-14)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+def test_dg_correction_is_radau_derivative(p):
+    """For tensor GL points the DG correction divergence at solution points
+    equals the derivative of Huynh's right-Radau polynomial
+    g_R = (P_p + P_{p+1})/2 on a xi=+1 face (and -g_L' on xi=-1 with
+    g_L = (-1)^p (P_p - P_{p+1})/2), non-zero only along the face-normal line."""
+    r = reference.ref_element("quad", p)
+    L = np.polynomial.legendre.Legendre
+    gR = 0.5 * (L.basis(p) + L.basis(p + 1))
+    gL = 0.5 * (-1) ** p * (L.basis(p) - L.basis(p + 1))
+    x = r.gl_nodes
+    n1 = p + 1
+    for sigma in range(r.nfpts):
+        f = r.fface[sigma]
+        col = r.divg[:, sigma].reshape(n1, n1)                       # [j, i]
+        xf = r.fpts[sigma]
+        if f in (1, 3):          # xi = +-1 faces: varies along i at fixed j
+            j = int(np.argmin(np.abs(x - xf[1])))
+            line = col[j, :]
+            other = np.delete(col, j, axis=0)
+        else:
+            i = int(np.argmin(np.abs(x - xf[0])))
+            line = col[:, i]
+            other = np.delete(col, i, axis=1)
+        assert np.max(np.abs(other)) < 1e-12
+        if f in (1, 2):
+            expect = gR.deriv()(x)
+        else:
+            expect = -gL.deriv()(x)
+        assert np.max(np.abs(line - expect)) < 1e-11
+
+
+# --------------------------------------------------------------------------
+# T-5 free-stream preservation and T-6 discrete conservation
+# --------------------------------------------------------------------------
+def _fs(d, vel):
+    return _state(d, lambda b, x: fields.uniform(x, vel=vel, p=1.3))
+
+
+def _mixed(n=6, order=3, seed=0, system="euler"):
+    rng = np.random.default_rng(seed)
+    m = meshes.mixed_mesh(n, n, order=order, split=rng.random(n * n) < 0.5,
+                          diag=rng.integers(0, 2, n * n))
+    return Workload("mixed", m, system, mu=0.02,
+                    ic=lambda b, x: fields.isentropic_vortex(x))
+
+
+def _curved_quads(n, order, amp=0.2):
+    mesh = meshes.quad_mesh(n, n, (0, 0), (1, 1), order=order, geom_order=2,
+                            mapping=meshes.sine_perturbation(amp / 2, 1.0))
+    return Workload("cq", mesh, "euler", ic=lambda b, x: fields.uniform(x))
+
+
+def _general_curved_hexes(n, order):
+    """Q2 hexes under a map whose Jacobian is not a rank-one update of the
+    identity, so the adjugate is not polynomial of low degree."""
+    def f(X):
+        s = np.sin(2 * np.pi * X[..., 0]) * np.sin(2 * np.pi * X[..., 1]) * np.sin(2 * np.pi * X[..., 2])
+        out = X.copy()
+        out[..., 0] += 0.06 * s
+        out[..., 1] += 0.06 * s * np.cos(2 * np.pi * X[..., 0])
+        out[..., 2] += 0.06 * s * np.cos(2 * np.pi * X[..., 1])
+        return out
+    mesh = meshes.hex_mesh(n, n, n, order=order, geom_order=2, mapping=f)
+    return Workload("gch", mesh, "euler", ic=lambda b, x: fields.uniform(x))
+
+
+@pytest.mark.parametrize("case", ["quad", "tri_mixed", "hex", "hex_ns", "curved_quad_p2",
+                                  "curved_hex_p4", "general_curved_hex_p4",
+                                  "general_curved_hex_p2"])
+def test_free_stream_preservation(case):
+    if case == "quad":
+        w = configs.vortex_quads(5, 3)
+    elif case == "tri_mixed":
+        w = _mixed(5, 3)
+    elif case == "hex":
+        w = configs.curved_freestream_hexes(3, 3, amp=0.0)
+    elif case == "hex_ns":
+        w = configs.taylor_green_hexes(3, 2)
+    elif case == "curved_quad_p2":
+        w = _curved_quads(4, 2)
+    elif case == "curved_hex_p4":
+        w = configs.curved_freestream_hexes(4, 4)
+    elif case == "general_curved_hex_p4":
+        w = _general_curved_hexes(4, 4)
+    else:
+        w = _general_curved_hexes(4, 2)
+    d = Discretisation(w)
+    r = d.rhs(_fs(d, (0.9, -0.4, 0.3)))
+    # round-off relative to flux magnitude / smallest element size
+    scale = 10.0 * max(np.max(1.0 / g.detJ) for g in d.geoms) ** (1.0 / d.ndims)
+    assert max(np.abs(x).max() for x in r) < 1e-13 * scale
+
+
+def test_free_stream_negative_control():
+    """Q2 hexes with a general map at p=1: the GL rule of the equivalent weak
+    form (exact to degree 2p+1 = 3 per direction) cannot integrate the degree-4
+    adjugate terms, so a uniform state is not preserved.  (From p=2 on the
+    products stay within degree 2p+1 and the test above holds.)"""
+    d = Discretisation(_general_curved_hexes(4, 1))
+    r = d.rhs(_fs(d, (0.9, -0.4, 0.3)))
+    assert max(np.abs(x).max() for x in r) > 1e-6
+
+
+@pytest.mark.parametrize("case", ["vortex", "tgv", "mixed_euler", "mixed_ns", "curved"])
+def test_discrete_conservation(case):
+    rng = np.random.default_rng(7)
+    if case == "vortex":
+        w = configs.vortex_quads(6, 3)
+    elif case == "tgv":
+        w = configs.taylor_green_hexes(3, 3)
+    elif case == "mixed_euler":
+        w = _mixed(5, 2)
+    elif case == "mixed_ns":
+        w = _mixed(5, 3, system="ns")
+    else:
+        w = configs.curved_freestream_hexes(4, 4)
+    d = Discretisation(w)
+    u = d.initial_state(w)
+    # any state: add a random perturbation
+    u = [x * (1 + 0.01 * rng.standard_normal(x.shape)) for x in u]
+    r = d.rhs(u)
+    tot = _integral(d, r)
+    ref = sum(np.einsum("r,rn,ran->a", rf.W, g.detJ.T, np.abs(rb))
+              for rf, g, rb in zip(d.refs, d.geoms, r))
+    assert np.all(np.abs(tot) <= 1e-13 * ref)
+
+
+# --------------------------------------------------------------------------
+# T-7 Rusanov: consistency, antisymmetry, rotation invariance, L/R swap
+# --------------------------------------------------------------------------
+def _rand_states(rng, D, m):
+    rho = rng.uniform(0.5, 2.0, m)
+    v = rng.uniform(-1, 1, (D, m))
+    p = rng.uniform(0.5, 2.0, m)
+    E = p / 0.4 + 0.5 * rho * np.sum(v * v, 0)
+    return np.concatenate([rho[None], rho * v, E[None]])
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_rusanov_properties(D):
+    rng = np.random.default_rng(D)
+    m = 64
+    uL, uR = _rand_states(rng, D, m), _rand_states(rng, D, m)
+    n = rng.standard_normal((D, m))
+    n /= np.linalg.norm(n, axis=0)
+    g = 1.4
+    # consistency
+    f = physics.inviscid_flux(uL, g)
+    assert np.allclose(physics.rusanov(uL, uL, n, g), sum(n[j] * f[j] for j in range(D)),
+                       rtol=0, atol=1e-13)
+    # conservation antisymmetry, bitwise
+    assert np.array_equal(physics.rusanov(uL, uR, n, g), -physics.rusanov(uR, uL, -n, g))
+    # rotation invariance of the normal flux: R^T F(R u) = F(u) in the momenta
+    Q, _ = np.linalg.qr(rng.standard_normal((D, D)))
+
+    def rot(u):
+        out = u.copy()
+        out[1:1 + D] = Q @ u[1:1 + D]
+        return out
+    Fr = physics.rusanov(rot(uL), rot(uR), Q @ n, g)
+    F = physics.rusanov(uL, uR, n, g)
+    back = Fr.copy()
+    back[1:1 + D] = Q.T @ Fr[1:1 + D]
+    assert np.allclose(back, F, atol=1e-12)
+
+
+def test_swapping_left_right_leaves_euler_rhs_unchanged():
+    w = configs.vortex_quads(5, 3)
+    d1 = Discretisation(w)
+    u = d1.initial_state(w)
+    pairs = w.mesh.pairs.copy()
+    sw = pairs.copy()
+    for a, b in (("lblock", "rblock"), ("lelem", "relem"), ("lface", "rface")):
+        sw[a], sw[b] = pairs[b], pairs[a]
+    sw["shift"] = -pairs["shift"]
+    w2 = Workload("sw", meshes.Mesh(2, w.mesh.blocks, sw, info=w.mesh.info), "euler",
+                  ic=w.ic)
+    d2 = Discretisation(w2)
+    assert np.array_equal(d1.rhs(u)[0], d2.rhs(u)[0])
+
+
+# --------------------------------------------------------------------------
+# T-8 / T-10 truncation: du/dt -> -div f(u(x)) at order >= p
+# --------------------------------------------------------------------------
+def _exact_euler_rhs(fn, x, gamma=1.4):
+    """-sum_j d/dx_j f_j(u(x)) by complex-step differentiation of the
+    analytic field (Squire & Trapp)."""
+    D = x.shape[-1]
+    h = 1e-30
+    out = 0.0
+    for j in range(D):
+        xc = x.astype(complex)
+        xc[..., j] += 1j * h
+        u = np.moveaxis(fn(xc), -1, 0)                                 # (NV, ...)
+        f = physics.inviscid_flux(u, gamma)
+        out = out - np.imag(f[j]) / h
+    return np.moveaxis(out, 0, -1)                                     # (..., NV)
+
+
+def _trunc_errors(make, ic, ns, box=None):
+    errs = []
+    for n in ns:
+        w = make(n)
+        d = Discretisation(w)
+        g = d.geoms[0]
+        u = d.initial_state(w)
+        r = d.rhs(u)[0]
+        ex = np.transpose(_exact_euler_rhs(ic, g.xu), (1, 2, 0))
+        wq = d.refs[0].W[:, None] * g.detJ.T
+        e2 = wq[:, None, :] * (r - ex) ** 2
+        if box is not None:
+            sel = box(g.xu).T
+            e2 = e2 * sel[:, None, :]
+        errs.append(math.sqrt(e2.sum()))
+    return np.array(errs)
+
+
+def test_vortex_truncation_order():
+    ic = lambda x: fields.isentropic_vortex(x)
+    box = lambda x: (np.abs(x[..., 0]) <= 2) & (np.abs(x[..., 1]) <= 2)
+    e = _trunc_errors(lambda n: configs.vortex_quads(n, 3), ic, [10, 20, 40], box)
+    rates = np.log2(e[:-1] / e[1:])
+    assert rates[-1] >= 2.8, (e, rates)
+
+
+def test_curved_truncation_order():
+    w0 = configs.curved_freestream_hexes(4, 4, eps=0.05)
+    modes = w0.info["modes"]
+    ic = lambda x: fields.perturbed_freestream(x, modes)
+    e = _trunc_errors(lambda n: configs.curved_freestream_hexes(n, 4, eps=0.05), ic, [8, 12])
+    rate = math.log(e[0] / e[1]) / math.log(1.5)
+    assert rate >= 3.8, (e, rate)
+
+
+# --------------------------------------------------------------------------
+# T-11 Taylor-Green initial dissipation rate (golden closed form)
+# --------------------------------------------------------------------------
+def test_taylor_green_dissipation():
+    gold = {}
+    with open(os.path.join(GOLDEN, "taylor_green.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split()
+                gold[k] = eval(v, {"pi": math.pi})
+    vals = []
+    for n in (4, 8):
+        w = configs.taylor_green_hexes(n, 3)
+        d = Discretisation(w)
+        u = d.initial_state(w)[0]
+        r = d.rhs([u])[0]
+        W, J = d.refs[0].W, d.geoms[0].detJ.T
+        rho, m = u[:, 0], u[:, 1:4]
+        v = m / rho[:, None]
+        Ek = np.einsum("r,rn,rn->", W, J, 0.5 * np.sum(m * v, 1))
+        dEk = np.einsum("r,rn,rn->", W, J, np.sum(v * r[:, 1:4], 1) - 0.5 * np.sum(v * v, 1) * r[:, 0])
+        assert abs(Ek - gold["Ek0"]) < 1e-10 * gold["Ek0"]
+        vals.append(dEk)
+    exact = gold["dEkdt0_times_Re"] / w.info["Re"]
+    assert abs(vals[1] - exact) < 2e-3 * abs(exact)
+    assert abs(vals[1] - exact) < 0.25 * abs(vals[0] - exact)
+
+
+# --------------------------------------------------------------------------
+# T-12 classical RK4 on a linear ODE
+# --------------------------------------------------------------------------
+def test_rk4_linear_amplification():
+    d = Discretisation(configs.vortex_quads(3, 1))
+    lam = -0.7 + 2.3j
+    d.rhs = lambda s: [lam * x for x in s]
+    u = [np.ones((4, 4, 9), dtype=complex)]
+    for dt in (0.1, 0.37):
+        z = lam * dt
+        amp = sum(z ** k / math.factorial(k) for k in range(5))
+        out = d.rk4_step(u, dt)[0]
+        assert np.allclose(out, amp, rtol=0, atol=1e-15)
+
+
+def test_vortex_advection_rk4_order():
+    """100 RK4 steps of dt=1e-3: the vortex translates by (0.1, 0); the error
+    in the box converges at a rate above p."""
+    errs = []
+    for n in (10, 20, 40):
+        w = configs.vortex_quads(n, 3)
+        d = Discretisation(w)
+        u = d.rk4(d.initial_state(w), 1e-3, 100)[0]
+        x = d.geoms[0].xu
+        ex = np.transpose(fields.isentropic_vortex(x, shift=(0.1, 0.0)), (1, 2, 0))
+        sel = ((np.abs(x[..., 0]) <= 2) & (np.abs(x[..., 1]) <= 2)).T
+        wq = d.refs[0].W[:, None] * d.geoms[0].detJ.T
+        errs.append(math.sqrt(np.sum((wq * (u[:, 0] - ex[:, 0]) ** 2)[sel])))
+    errs = np.array(errs)
+    rates = np.log2(errs[:-1] / errs[1:])
+    assert rates[-1] >= 3.5, (errs, rates)
+
+
+# --------------------------------------------------------------------------
+# Set-up errors
+# --------------------------------------------------------------------------
+def test_mismatched_faces_rejected():
+    w = configs.vortex_quads(4, 2)
+    bad = w.mesh.pairs.copy()
+    bad["shift"][0, 1] += 0.3
+    w.mesh = meshes.Mesh(2, w.mesh.blocks, bad, info=w.mesh.info)
+    with pytest.raises(ValueError):
+        Discretisation(w)
+
+
+def test_inverted_element_rejected():
+    w = configs.vortex_quads(4, 2)
+    nodes = w.mesh.blocks[0].nodes.copy()
+    nodes[0] = nodes[0][[1, 0, 3, 2]]
+    w.mesh.blocks[0] = meshes.Block("quad", 2, 1, nodes)
+    with pytest.raises(ValueError):
+        Discretisation(w)
+
+
+# --------------------------------------------------------------------------
+# Navier-Stokes viscous terms against closed forms (2-D periodic box)
+#
+# The RHS truncation of the LDG second-derivative terms converges at p-1, so
+# each case asserts a rate >= 1.8 at p=3 and an error far below the size of
+# the viscous term itself (a wrong coefficient would leave an O(1) fraction).
+# --------------------------------------------------------------------------
+MU, PR = 0.05, 0.72
+
+
+def _ns_box(n, p, ic):
+    mesh = meshes.quad_mesh(n, n, (0.0, 0.0), (1.0, 1.0), order=p)
+    return Workload("nsbox", mesh, "ns", mu=MU, prandtl=PR, ic=lambda b, x: ic(x))
+
+
+def _ns_errors(ic, viscous, p=3, ns=(16, 32)):
+    errs = []
+    for n in ns:
+        w = _ns_box(n, p, ic)
+        d = Discretisation(w)
+        r = d.rhs(d.initial_state(w))[0]
+        x = d.geoms[0].xu
+        ex = _exact_euler_rhs(ic, x) + viscous(x)
+        ex = np.transpose(ex, (1, 2, 0))
+        wq = d.refs[0].W[:, None] * d.geoms[0].detJ.T
+        errs.append(math.sqrt(np.sum(wq[:, None, :] * (r - ex) ** 2)))
+    return np.array(errs)
+
+
+A, K = 0.2, 2 * np.pi
+
+
+def _prim(rho, v, p):
+    return lambda x: fields.primitive_to_conserved(rho(x), v(x), p(x))
+
+
+def test_ns_shear_layer_closed_form():
+    """rho = p = 1, v = (0, a sin kx): viscous part of du/dt is
+    (0, 0, -mu a k^2 sin kx, mu a^2 k^2 cos 2kx) (stress and viscous work)."""
+    one = lambda x: np.ones(x.shape[:-1])
+    ic = _prim(one, lambda x: np.stack([0 * x[..., 0], A * np.sin(K * x[..., 0])], -1), one)
+
+    def visc(x):
+        out = np.zeros(x.shape[:-1] + (4,))
+        out[..., 2] = -MU * A * K * K * np.sin(K * x[..., 0])
+        out[..., 3] = MU * A * A * K * K * np.cos(2 * K * x[..., 0])
+        return out
+    e = _ns_errors(ic, visc)
+    assert e[1] < 1e-2 * MU * A * K * K, e
+    assert math.log2(e[0] / e[1]) >= 1.8, e
+
+
+def test_ns_compression_closed_form():
+    """rho = p = 1, v = (a sin kx, 0): the bulk term -2/3 mu div v makes
+    tau_xx = 4/3 mu a k cos kx, so the viscous part of du/dt is
+    (0, -4/3 mu a k^2 sin kx, 0, 4/3 mu a^2 k^2 cos 2kx)."""
+    one = lambda x: np.ones(x.shape[:-1])
+    ic = _prim(one, lambda x: np.stack([A * np.sin(K * x[..., 0]), 0 * x[..., 0]], -1), one)
+
+    def visc(x):
+        out = np.zeros(x.shape[:-1] + (4,))
+        out[..., 1] = -4.0 / 3.0 * MU * A * K * K * np.sin(K * x[..., 0])
+        out[..., 3] = 4.0 / 3.0 * MU * A * A * K * K * np.cos(2 * K * x[..., 0])
+        return out
+    e = _ns_errors(ic, visc)
+    assert e[1] < 1e-2 * MU * A * K * K, e
+    assert math.log2(e[0] / e[1]) >= 1.8, e
+
+
+def test_ns_heat_conduction_closed_form():
+    """v = 0, p = 1, p/rho = 1 + a sin kx: the viscous part of du/dt is the
+    heat term (0, 0, 0, -mu gamma/(Pr (gamma-1)) a k^2 sin kx)."""
+    one = lambda x: np.ones(x.shape[:-1])
+    ic = _prim(lambda x: 1.0 / (1.0 + 0.5 * A * np.sin(K * x[..., 0])),
+               lambda x: np.zeros(x.shape), one)
+    kappa = MU * 1.4 / (PR * 0.4)
+
+    def visc(x):
+        out = np.zeros(x.shape[:-1] + (4,))
+        out[..., 3] = -kappa * 0.5 * A * K * K * np.sin(K * x[..., 0])
+        return out
+    e = _ns_errors(ic, visc)
+    assert e[1] < 1e-2 * kappa * 0.5 * A * K * K, e
+    assert math.log2(e[0] / e[1]) >= 1.8, e
+
+
+@pytest.mark.parametrize("beta", [0.5, -0.5])
+def test_ldg_compact_stencil(beta):
+    """With beta = +-1/2 the LDG scheme has a compact stencil (paper's
+    Navier-Stokes section): a perturbation in one element reaches its face
+    neighbours and, through the gradient of a neighbour, at most the diagonal
+    neighbours of a Cartesian grid -- never an element two cells away."""
+    n = 7
+    one = lambda x: np.ones(x.shape[:-1])
+    ic = _prim(lambda x: 1 + 0.1 * np.sin(K * x[..., 0]) * np.cos(K * x[..., 1]),
+               lambda x: np.stack([0.3 * np.sin(K * x[..., 1]), 0.2 * np.cos(K * x[..., 0])], -1),
+               one)
+    w = _ns_box(n, 2, ic)
+    w.ldg_beta = beta
+    d = Discretisation(w)
+    u = d.initial_state(w)
+    r0 = d.rhs(u)[0]
+    e = 3 + n * 3
+    u2 = [u[0].copy()]
+    u2[0][:, :, e] *= 1.01
+    changed = np.nonzero(np.abs(d.rhs(u2)[0] - r0).max(axis=(0, 1)) > 1e-13)[0]
+    i, j = e % n, e // n
+    faces = {e, (i + 1) % n + n * j, (i - 1) % n + n * j, i + n * ((j + 1) % n), i + n * ((j - 1) % n)}
+    block = {(i + a) % n + n * ((j + b) % n) for a in (-1, 0, 1) for b in (-1, 0, 1)}
+    got = set(changed.tolist())
+    assert faces <= got <= block

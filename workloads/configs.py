@@ -1,0 +1,158 @@
+"""The five seeded workloads (and scaled-down variants for tests).
+
+A workload is a mesh (from :mod:`workloads.meshes`), the physical parameters,
+the RK4 time step and an initial-condition callback.  The callback receives a
+block index and the physical coordinates of that block's solution points,
+shape (nelem, nupts, ndims), and returns conserved variables of shape
+(nelem, nupts, nvars).  Whoever places the solution points (library or
+oracle) supplies the coordinates.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable
+
+import numpy as np
+
+from . import fields, meshes
+
+
+@dataclass
+class Workload:
+    name: str
+    mesh: meshes.Mesh
+    system: str                      # "euler" | "ns"
+    gamma: float = 1.4
+    mu: float = 0.0
+    prandtl: float = 0.72
+    ldg_beta: float = 0.5
+    ldg_tau: float = 0.1
+    dt: float = 1e-3
+    nsteps: int = 100
+    ic: Callable = None              # (block, coords) -> (nelem, nupts, nvars)
+    dt_per_problem: np.ndarray | None = None
+    info: dict = field(default_factory=dict)
+
+    @property
+    def nvars(self):
+        return self.mesh.ndims + 2
+
+
+def vortex_quads(n=20, order=3, nsteps=100, dt=1e-3):
+    """Isentropic vortex (strength 5, R=1, free stream (1,0)) on periodic
+    n x n straight quads covering [-5,5]^2."""
+    mesh = meshes.quad_mesh(n, n, (-5.0, -5.0), (5.0, 5.0), order=order)
+    return Workload(f"vortex_quad{n}x{n}_p{order}", mesh, "euler", dt=dt,
+                    nsteps=nsteps,
+                    ic=lambda b, x: fields.isentropic_vortex(x))
+
+
+def taylor_green_hexes(n=16, order=3, nsteps=100, dt=3e-4, Re=1600.0, Ma=0.1):
+    """Navier-Stokes Taylor-Green vortex on periodic [0,2pi]^3, n^3 hexes."""
+    L = 2.0 * np.pi
+    mesh = meshes.hex_mesh(n, n, n, (0.0, 0.0, 0.0), (L, L, L), order=order)
+    return Workload(f"tgv_hex{n}^3_p{order}", mesh, "ns", mu=1.0 / Re,
+                    prandtl=0.71, ldg_beta=0.5, ldg_tau=0.1, dt=dt,
+                    nsteps=nsteps, ic=lambda b, x: fields.taylor_green(x, Ma=Ma),
+                    info=dict(Re=Re, Ma=Ma))
+
+
+def curved_freestream_hexes(n=48, order=4, seed=3, nsteps=10, dt=2e-4,
+                            eps=0.05, amp=0.1):
+    """Euler on [0,1]^3 with n^3 quadratic (Q2) hexes whose nodes are moved by
+    amp*sin(2pi X)sin(2pi Y)sin(2pi Z)(1,1,1); uniform stream plus smooth
+    random modes of amplitude eps drawn from ``seed``."""
+    mesh = meshes.hex_mesh(n, n, n, order=order, geom_order=2,
+                           mapping=meshes.sine_perturbation(amp, 1.0))
+    modes = fields.freestream_modes(3, seed, eps=eps)
+    return Workload(f"curved_hex{n}^3_q2_p{order}", mesh, "euler", dt=dt,
+                    nsteps=nsteps,
+                    ic=lambda b, x: fields.perturbed_freestream(x, modes),
+                    info=dict(modes=modes))
+
+
+def batched_vortices(nproblems=512, seed=4, nmin=50, nmax=5000, nsteps=20,
+                     dt=1e-3):
+    """Many independent periodic 2-D Euler problems in one mesh.
+
+    Per problem, in draw order: target element count log-uniform in
+    [nmin, nmax]; order p in {2,3,4}; split fraction f ~ U[0.25,0.75]; the
+    grid side n = max(3, round(sqrt(N/(1+f)))); floor(f n^2) cells chosen by
+    permutation, each split along a random diagonal; vortex centre ~ U[-2,2]^2
+    and strength ~ U[2,5].  Elements are grouped into blocks by (type, p)
+    with per-element problem ids.
+    """
+    rng = np.random.default_rng(seed)
+    groups = {}          # (etype, p) -> list of node arrays / problem ids
+    recs = []
+    probs = []
+    for prob in range(nproblems):
+        N = np.exp(rng.uniform(np.log(nmin), np.log(nmax)))
+        p = int(rng.integers(2, 5))
+        f = rng.uniform(0.25, 0.75)
+        n = max(3, int(round(np.sqrt(N / (1.0 + f)))))
+        perm = rng.permutation(n * n)
+        nsplit = int(np.floor(f * n * n))
+        split = np.zeros(n * n, bool)
+        split[perm[:nsplit]] = True
+        diag = rng.integers(0, 2, size=n * n).astype(np.int32)
+        centre = rng.uniform(-2.0, 2.0, size=2)
+        S = rng.uniform(2.0, 5.0)
+        probs.append(dict(p=p, n=n, centre=centre, S=S))
+        qn, tn, pairs = meshes.mixed_quad_tri_mesh(n, n, split=split, diag=diag)
+        keys = {0: ("quad", p), 1: ("tri", p)}
+        offs = {}
+        for code, arr in ((0, qn), (1, tn)):
+            g = groups.setdefault(keys[code], dict(nodes=[], prob=[], count=0))
+            offs[code] = g["count"]
+            if len(arr):
+                g["nodes"].append(arr)
+                g["prob"].append(np.full(len(arr), prob, np.int32))
+                g["count"] += len(arr)
+        recs.append((pairs, keys, offs))
+    order = sorted(groups.keys(), key=lambda k: (k[0] != "quad", k[1]))
+    bidx = {k: i for i, k in enumerate(order)}
+    blocks = []
+    for k in order:
+        g = groups[k]
+        blocks.append(meshes.Block(k[0], k[1], 1, np.concatenate(g["nodes"]),
+                                   np.concatenate(g["prob"])))
+    allp = []
+    for pairs, keys, offs in recs:
+        q = pairs.copy()
+        for side in ("l", "r"):
+            code = pairs[side + "block"]
+            q[side + "block"] = np.where(code == 0, bidx[keys[0]], bidx.get(keys[1], -1))
+            q[side + "elem"] = pairs[side + "elem"] + np.where(code == 0, offs[0], offs[1])
+        allp.append(q)
+    mesh = meshes.Mesh(2, blocks, np.concatenate(allp), nproblems=nproblems,
+                       info=dict(problems=probs, h=min(10.0 / pr["n"] for pr in probs)))
+
+    def ic(b, x):
+        blk = blocks[b]
+        out = np.empty(x.shape[:-1] + (4,))
+        for prob in np.unique(blk.problem):
+            sel = blk.problem == prob
+            pr = probs[prob]
+            out[sel] = fields.isentropic_vortex(x[sel], S=pr["S"], centre=pr["centre"])
+        return out
+
+    return Workload(f"batched{nproblems}_vortex", mesh, "euler", dt=dt,
+                    nsteps=nsteps, ic=ic,
+                    dt_per_problem=np.full(nproblems, dt))
+
+
+def adjoint_tgv(n=24, order=3, nsteps=200, dt=2e-4, ckpt=20):
+    w = taylor_green_hexes(n=n, order=order, nsteps=nsteps, dt=dt)
+    w.name = f"adjoint_tgv_hex{n}^3_p{order}"
+    w.info["ckpt"] = ckpt
+    return w
+
+
+CONFIGS = {
+    "cfg1": lambda: vortex_quads(20, 3),
+    "cfg2": lambda: taylor_green_hexes(16, 3),
+    "cfg3": lambda: curved_freestream_hexes(48, 4),
+    "cfg4": lambda: batched_vortices(512),
+    "cfg5": lambda: adjoint_tgv(24, 3),
+}
