@@ -1,0 +1,195 @@
+/*
+ * fr.h -- C ABI of the MI355X flux reconstruction right-hand-side library.
+ *
+ * The library evaluates the semi-discrete FR right-hand side du/dt of the
+ * compressible Euler and Navier-Stokes equations on unstructured quad,
+ * triangle and hexahedral meshes (Witherden, Farrington & Vincent, section 2:
+ * eqs. ufpts, commsoln, transqu, gradufpts, tnormfluxf, commpflux, tdivflux,
+ * negdivconf; physics from section 4 and Appendix B), and advances it with
+ * classical RK4.  Operator applications use the matrix form of Appendix A.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every function returns fr_status; nothing throws across the ABI or
+ *    aborts.  On failure fr_last_error() holds a message.
+ *  - State arrays (u, dudt, lam, ulam) are DEVICE float64 arrays in the
+ *    public layout: element blocks concatenated in input order; block b
+ *    starts at offset[b] and is indexed [rho][alpha][n] with leading
+ *    dimension ld[b] >= nelem (fr_get_layout), i.e. the structure-of-arrays
+ *    packing of the paper's implementation section.  Entries with
+ *    n >= nelem are padding: they are read but never influence real
+ *    entries, and outputs there are written as zero.
+ *  - Field order (rho, rho v_x, rho v_y[, rho v_z], E) (eq. eulerflux).
+ *  - Solution points: tensor Gauss-Legendre with xi fastest in quads and
+ *    hexes; warp-and-blend (alpha = 0) points in triangles, in rows of
+ *    increasing eta.  fr_get_solution_points returns their physical
+ *    coordinates.
+ *  - Calls are stream ordered and asynchronous: they enqueue work on
+ *    `hip_stream` (a hipStream_t; NULL = the default stream) and return.
+ *    Device-side failures surface at the next synchronising call.
+ *  - One context may be used by one host thread at a time.
+ */
+#ifndef FR_H
+#define FR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fr_ctx fr_ctx;
+
+typedef enum {
+  FR_OK = 0,
+  FR_EINVAL = 1,        /* bad argument (null pointer, bad size, bad enum)   */
+  FR_EMESH = 2,         /* det J <= 0, or flux points not paired one-to-one  */
+  FR_EUNSUPPORTED = 3,  /* (element type, order) not built into the library  */
+  FR_ENOMEM = 4,        /* device or host allocation failed                  */
+  FR_EDEVICE = 5,       /* a HIP runtime call failed                         */
+  FR_ENONFINITE = 6     /* check_finite found NaN/Inf in the state           */
+} fr_status;
+
+typedef enum { FR_QUAD = 0, FR_TRI = 1, FR_HEX = 2 } fr_etype;
+typedef enum { FR_EULER = 0, FR_NAVIER_STOKES = 1 } fr_system;
+/* Precision of the operator matrix products and the arrays they read and
+ * write (flux-point solution, gradients, transformed fluxes).  The state,
+ * du/dt, RK registers, metric terms and point-wise arithmetic stay FP64. */
+typedef enum { FR_FP64 = 0, FR_FP32 = 1, FR_BF16X3 = 2 } fr_prec;
+
+typedef struct {
+  int32_t ndims;          /* 2 or 3                                            */
+  int32_t system;         /* fr_system                                         */
+  int32_t prec;           /* fr_prec                                           */
+  int32_t check_finite;   /* 1: fr_rk_step checks the state, FR_ENONFINITE     */
+  double gamma;           /* ratio of specific heats                           */
+  double mu;              /* dynamic viscosity (Navier-Stokes)                 */
+  double prandtl;         /* Prandtl number (Navier-Stokes)                    */
+  double ldg_beta;        /* LDG common-solution bias beta (Navier-Stokes)     */
+  double ldg_tau;         /* LDG penalty tau (Navier-Stokes)                   */
+  int32_t nproblems;      /* independent problems in the mesh (>= 1)           */
+  int32_t reserved;
+} fr_config;
+
+typedef struct {          /* one element block: one type, order, geometry order */
+  int32_t etype;          /* fr_etype                                          */
+  int32_t order;          /* solution order p: quad/tri 1..6, hex 1..4         */
+  int32_t geom_order;     /* 1 (straight) or 2 (quadratic)                     */
+  int32_t reserved;
+  int64_t nelem;          /* >= 1                                              */
+  const double *nodes;    /* HOST [nelem][nnodes][ndims]; nodes tensor-
+                             lexicographic (xi fastest) on {-1,1} or {-1,0,1}
+                             for quads/hexes; triangles v0, v1, v2 then the
+                             v0v1, v1v2, v2v0 midpoints                        */
+  const int32_t *problem; /* HOST [nelem] problem id, or NULL (all problem 0)  */
+} fr_block;
+
+typedef struct {          /* one conforming face pair: x_R + shift == x_L       */
+  int32_t lblock;
+  int32_t lface;          /* quad: 0 eta=-1, 1 xi=+1, 2 eta=+1, 3 xi=-1;
+                             tri: 0 v0v1, 1 v1v2, 2 v2v0; hex: 0 zeta=-1,
+                             1 eta=-1, 2 xi=+1, 3 eta=+1, 4 xi=-1, 5 zeta=+1   */
+  int64_t lelem;
+  int32_t rblock;
+  int32_t rface;
+  int64_t relem;
+  double shift[3];        /* periodic translation, zero otherwise             */
+} fr_facepair;
+
+/* Build a context: reference operators (Appendix A: M0, M3, M4-M6 M0,
+ * M1-M3 M2, M6, block-diagonal M5), per-point metric terms (section 2), the
+ * flux-point pair table (each pair visited once, eq. commsoln) and scratch.
+ * `blocks`, `pairs` and node arrays are host memory, only read during the
+ * call.  Periodic meshes only: every flux point must be paired exactly once,
+ * else FR_EMESH.  On success *out owns all device memory it allocated. */
+fr_status fr_setup_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *blocks,
+                        int64_t npairs, const fr_facepair *pairs, void *hip_stream,
+                        fr_ctx **out);
+
+/* Layout of block `block`: its offset into the state array, leading
+ * dimension, points per element, fields, and the total state length. */
+fr_status fr_get_layout(const fr_ctx *ctx, int32_t block, int64_t *offset, int64_t *ld,
+                        int32_t *nupts, int32_t *nvars, int64_t *total_len);
+
+/* Physical solution-point coordinates of block `block` into HOST memory
+ * `xyz`, shape [nelem][nupts][ndims]. */
+fr_status fr_get_solution_points(const fr_ctx *ctx, int32_t block, double *xyz);
+
+/* Quadrature weights times det J at solution points of block `block` into
+ * HOST memory `wj` [nupts][nelem] (integration of solution fields). */
+fr_status fr_get_quadrature(const fr_ctx *ctx, int32_t block, double *wj);
+
+/* du/dt = -J^-1 div~ f~ (eq. negdivconf) for the device state u.  dudt may
+ * alias u. */
+fr_status fr_rhs(fr_ctx *ctx, const double *u, double *dudt, void *hip_stream);
+
+/* nsteps classical RK4 steps in place on u.  dt_dev: DEVICE float64
+ * [nproblems], one step size per problem (read on the device, so replays of
+ * the captured step graph pick up new values). */
+fr_status fr_rk_step(fr_ctx *ctx, double *u, const double *dt_dev, int32_t nsteps,
+                     void *hip_stream);
+
+/* Vector-Jacobian product of the right-hand side: ulam = (dR/du)(u)^T lam.
+ * ulam must not alias u or lam. */
+fr_status fr_rhs_adjoint(fr_ctx *ctx, const double *u, const double *lam, double *ulam,
+                         void *hip_stream);
+
+/* Adjoint of one RK4 step from u_n: lam_n = (d u_{n+1} / d u_n)^T lam_np1.
+ * Recomputes the four stages internally.  lam_n may alias lam_np1. */
+fr_status fr_rk_step_adjoint(fr_ctx *ctx, const double *u_n, const double *dt_dev,
+                             const double *lam_np1, double *lam_n, void *hip_stream);
+
+/* Integrals of the state by quadrature at the solution points (paper's
+ * validation section: sums of W J times the integrand).  kind must be 0:
+ * out (DEVICE float64) [nproblems][nvars + 1] receives, per problem, the
+ * integral of every conserved field followed by the kinetic energy
+ * |rho v|^2 / (2 rho).  Summation order is fixed (bitwise reproducible). */
+fr_status fr_integrate(fr_ctx *ctx, const double *u, int32_t kind, double *out,
+                       void *hip_stream);
+
+/* Host-only diagnostics (no device use; callable without a GPU).
+ * fr_reference_operator copies one reference-element array of (etype, p)
+ * into HOST memory `out` (capacity `cap` doubles) and stores its shape in
+ * rows/cols.  which: 0 M0 (Nf x Nu), 1 M3 (Nu x Nf), 2 M4 - M6 M0
+ * (D Nu x Nu), 3 M6 (D Nu x Nf), 4 M1 - M3 M2 (Nu x D Nu), 5 solution
+ * points (Nu x D), 6 flux points (Nf x D), 7 reference normals (Nf x D),
+ * 8 quadrature weights W (Nu x 1), 9 face weights omega (Nf x 1), 10 M4
+ * (D Nu x Nu), 11 M1 (Nu x D Nu).  Out-of-range `which` or too small `cap`
+ * gives FR_EINVAL; an unsupported order FR_EUNSUPPORTED.
+ * fr_check_mesh runs the host part of fr_setup_mesh (metric terms and flux
+ * point pairing) and returns its status; npoint_pairs receives the number of
+ * flux-point pairs. */
+fr_status fr_reference_operator(int32_t etype, int32_t order, int32_t which, double *out,
+                                int64_t cap, int32_t *rows, int32_t *cols);
+fr_status fr_check_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *blocks,
+                        int64_t npairs, const fr_facepair *pairs, int64_t *npoint_pairs);
+
+/* Device diagnostics (test support).
+ * fr_debug_stage runs the right-hand-side chain of an FP64 context up to
+ * step `stage` (1: U^f = M0 U, 2: common solution C^f, 3: Q~, 4: Q = J^-T Q~,
+ * 5: Q^f, 6: transformed flux F~, 7: D~ = common normal flux) and copies
+ * that internal array (layout [row][alpha][ld] per block, blocks
+ * concatenated) into the DEVICE buffer `out` of fr_debug_scratch_len
+ * doubles.  fr_debug_gemm computes C = A [B1; B2] with the library's matrix
+ * core kernel: A HOST row-major M x (K1 + K2); B1 (K1 rows), B2 (K2 rows)
+ * DEVICE float64 with row stride ldb; C DEVICE (float64 for FP64, float32
+ * for FP32) M x N, row stride N; N a multiple of 16.  Synchronous. */
+fr_status fr_debug_stage(fr_ctx *ctx, const double *u, int32_t stage, double *out,
+                         void *hip_stream);
+fr_status fr_debug_scratch_len(const fr_ctx *ctx, int32_t stage, int64_t *len);
+fr_status fr_debug_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, const double *A,
+                        const void *B1, const void *B2, int64_t ldb, void *C, int64_t N,
+                        void *hip_stream);
+
+/* Message of the last failure on ctx (ctx NULL: last failed setup on this
+ * thread).  Never NULL. */
+const char *fr_last_error(const fr_ctx *ctx);
+
+/* Release every resource owned by ctx (after synchronising its stream). */
+void fr_destroy(fr_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FR_H */

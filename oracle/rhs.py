@@ -70,6 +70,23 @@ class Discretisation:
         self.magL, self.magR = magL, magR
         self.dt_per_elem = None
 
+    def extended(self):
+        """A copy whose metric terms and normals are held in long double, so
+        ``rhs`` on long-double states evaluates the same formula with 64-bit
+        significands.  Used only to measure the FP64 rounding floor of a
+        case (how far an FP64 evaluation of this formula can sit from the
+        exact value of the same formula)."""
+        import copy
+        e = copy.copy(self)
+        e.geoms = [copy.copy(g) for g in self.geoms]
+        for g in e.geoms:
+            g.S = g.S.astype(np.longdouble)
+            g.detJ = g.detJ.astype(np.longdouble)
+        e.nL = self.nL.astype(np.longdouble)
+        e.magL = self.magL.astype(np.longdouble)
+        e.magR = self.magR.astype(np.longdouble)
+        return e
+
     def _flat(self, b, s, e):
         ne = np.array([g.nelem for g in self.geoms])
         return self.fbase[b] + s * ne[b] + e
@@ -104,7 +121,11 @@ class Discretisation:
         return np.swapaxes(seg, -3, -2)
 
     # -- right-hand side -------------------------------------------------------
-    def rhs(self, state):
+    def rhs(self, state, record=None):
+        """du/dt per block.  If ``record`` is a dict it receives the
+        intermediate arrays of every step, per block: uf, cf, qt, q, qf, ft,
+        df (flux-point arrays as [sigma, alpha, n], vectors as [i, row,
+        alpha, n])."""
         P = self.params
         ns = P["system"] == "ns"
         D = self.ndims
@@ -129,12 +150,19 @@ class Discretisation:
                 # 3. transformed gradient at solution points
                 qt = (_es("irv,van->iran", r.D_u, state[b])
                       + _es("rs,si,san->iran", r.divg, r.fnorm, jump))
+                if record is not None:
+                    record.setdefault("cf", []).append(self._from_flat(CF, b))
+                    record.setdefault("qt", []).append(qt)
                 # 4. physical gradient q_j = (1/J) sum_i S_ij q~_i
                 qb = _es("nrij,iran->jran", g.S, qt) / g.detJ.T[None, :, None, :]
                 q[b] = qb
+                if record is not None:
+                    record.setdefault("q", []).append(qb)
                 # 5. gradient at flux points
                 qfs.append(_es("sr,jran->jsan", r.L_f, qb))
             qf_flat = self._to_flat(qfs)                              # (D, NV, nfp)
+            if record is not None:
+                record["qf"] = qfs
         # 6-7. transformed flux at solution points, its normal component at
         # flux points
         Ft, fperp = [], []
@@ -154,6 +182,10 @@ class Discretisation:
         DF = np.empty_like(UF)
         DF[:, self.gl] = self.magL * F
         DF[:, self.gr] = -self.magR * F
+        if record is not None:
+            record["uf"] = uf
+            record["ft"] = Ft
+            record["df"] = [self._from_flat(DF, b) for b in range(nb)]
         out = []
         for b in range(nb):
             r, g = refs[b], geoms[b]

@@ -1,0 +1,674 @@
+// C ABI of the FR library: context set-up, the right-hand-side kernel chain,
+// RK4 stepping (captured once into a HIP graph and replayed), integrals.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/fr.h"
+#include "kernels.h"
+#include "setup.h"
+
+namespace {
+
+thread_local std::string g_setup_error = "no error";
+
+struct GemmOp {
+  int M = 0, K1 = 0, K2 = 0, KS1 = 0, KS2 = 0, MBW = 1, WM = 1;
+  void *d_A = nullptr;
+};
+
+struct BlockRT {
+  int ref = 0;
+  int etype = 0, order = 0;
+  int64_t nelem = 0, ld = 0;
+  int Nu = 0, Nf = 0;
+  int64_t uoff = 0, ufoff = 0, qfoff = 0, ftoff = 0, part_off = 0;
+  double *d_smat = nullptr, *d_rcpdjac = nullptr, *d_wdjac = nullptr;
+  int32_t *d_prob = nullptr;
+  GemmOp m0, s3, s8;
+  std::vector<double> xu, wdjac_host;
+};
+
+}  // namespace
+
+struct fr_ctx {
+  fr_config cfg{};
+  int D = 0, NV = 0;
+  bool ns = false;
+  int prec = 0;
+  size_t tsize = 8;  // element size of the scratch arrays
+  std::string err = "no error";
+  std::vector<fr::RefOps> refs;
+  std::vector<BlockRT> blocks;
+  int64_t total_len = 0, uf_len = 0, qf_len = 0, ft_len = 0, nelem_total = 0;
+  void *d_uf = nullptr, *d_qf = nullptr, *d_ft = nullptr;
+  double *d_acc = nullptr, *d_stage = nullptr;
+  // pairs
+  int64_t npairs = 0;
+  int32_t *d_lidx = nullptr, *d_ridx = nullptr, *d_lblk = nullptr, *d_rblk = nullptr;
+  double *d_nrm = nullptr, *d_magL = nullptr, *d_magR = nullptr;
+  int64_t *d_blk_ufbase = nullptr, *d_blk_qfbase = nullptr, *d_blk_ld = nullptr,
+          *d_blk_qstride = nullptr;
+  // reductions
+  double *d_part = nullptr;
+  int64_t *d_pstart = nullptr, *d_plist = nullptr;
+  int32_t *d_flag = nullptr;
+  int nproblems = 1;
+  // graph of one RK4 step
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  const double *graph_u = nullptr, *graph_dt = nullptr;
+  std::vector<void *> allocs;
+};
+
+namespace {
+
+struct Fail {
+  fr_status st;
+  std::string msg;
+};
+
+void hip_check(hipError_t e, const char *what) {
+  if (e != hipSuccess)
+    throw Fail{e == hipErrorOutOfMemory ? FR_ENOMEM : FR_EDEVICE,
+               std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+template <typename T>
+T *dev_alloc(fr_ctx *c, size_t n) {
+  void *p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess) throw Fail{FR_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)};
+  c->allocs.push_back(p);
+  hip_check(hipMemset(p, 0, n * sizeof(T)), "hipMemset");
+  return (T *)p;
+}
+
+template <typename T>
+T *dev_upload(fr_ctx *c, const T *h, size_t n, hipStream_t s) {
+  T *d = dev_alloc<T>(c, n);
+  if (n) hip_check(hipMemcpyAsync(d, h, n * sizeof(T), hipMemcpyHostToDevice, s), "upload");
+  hip_check(hipStreamSynchronize(s), "upload sync");
+  return d;
+}
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+void make_op(fr_ctx *c, GemmOp &op, const std::vector<double> &A, int M, int K1, int K2,
+             int64_t N, hipStream_t s) {
+  op.M = M; op.K1 = K1; op.K2 = K2;
+  op.KS1 = (K1 + 3) / 4;
+  op.KS2 = (K2 + 3) / 4;
+  fr::gemm_plan(M, N, c->prec, &op.MBW, &op.WM);
+  int64_t n = fr::gemm_pack_size(M, K1, K2, op.MBW, op.WM, 4);
+  if (c->prec == FR_FP64) {
+    std::vector<double> pk(n);
+    fr::gemm_pack_f64(A.data(), M, K1, K2, op.MBW, op.WM, pk.data());
+    op.d_A = dev_upload(c, pk.data(), n, s);
+  } else {
+    std::vector<float> pk(n);
+    fr::gemm_pack_f32(A.data(), M, K1, K2, op.MBW, op.WM, pk.data());
+    op.d_A = dev_upload(c, pk.data(), n, s);
+  }
+}
+
+// concatenate two row-major matrices side by side: [A (M x K1) | B (M x K2)]
+std::vector<double> hcat(const std::vector<double> &A, int K1, const std::vector<double> &B,
+                         int K2, int M) {
+  std::vector<double> out((size_t)M * (K1 + K2));
+  for (int r = 0; r < M; ++r) {
+    for (int k = 0; k < K1; ++k) out[(size_t)r * (K1 + K2) + k] = A[(size_t)r * K1 + k];
+    for (int k = 0; k < K2; ++k) out[(size_t)r * (K1 + K2) + K1 + k] = B[(size_t)r * K2 + k];
+  }
+  return out;
+}
+
+fr_status fail(fr_ctx *c, fr_status st, const std::string &m) {
+  if (c) c->err = m; else g_setup_error = m;
+  return st;
+}
+
+void *elem(void *base, int64_t off, size_t ts) { return (char *)base + off * ts; }
+
+fr::GemmArgs gemm_args(const GemmOp &op) {
+  fr::GemmArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.Apack = op.d_A; g.M = op.M; g.KS1 = op.KS1; g.KS2 = op.KS2; g.K1 = op.K1; g.K2 = op.K2;
+  g.MBW = op.MBW; g.WM = op.WM;
+  return g;
+}
+
+// The right-hand-side chain.  epi: EPI_NEGDIV writes dudt; EPI_RK applies the
+// RK stage update `rk` with registers (u, acc, stage).
+void rhs_chain(fr_ctx *c, const double *u, double *dudt, int epi, const fr::RkCoef *rk,
+               const double *dt, hipStream_t s, int stop = 99) {
+  const int D = c->D, NV = c->NV;
+  const size_t ts = c->tsize;
+  const int f32 = c->prec != FR_FP64;
+  const int gprec = f32 ? fr::PREC_F32 : fr::PREC_F64;
+  // S1: U^f = M0 U^u
+  for (auto &b : c->blocks) {
+    fr::GemmArgs g = gemm_args(b.m0);
+    g.B1 = u + b.uoff; g.ldb1 = NV * b.ld; g.b1_f32 = 0;
+    g.B2 = nullptr; g.ldb2 = 0; g.b2_f32 = 0;
+    g.C = elem(c->d_uf, b.ufoff, ts); g.ldc = NV * b.ld; g.c_f32 = f32;
+    g.N = NV * b.ld;
+    hip_check(fr::launch_gemm(gprec, fr::EPI_STORE, g, 1, s), "gemm M0");
+  }
+  if (stop <= 1) return;
+  fr::PairArgs pa;
+  std::memset(&pa, 0, sizeof(pa));
+  pa.ndims = D; pa.nvars = NV; pa.npairs = c->npairs;
+  pa.lidx = c->d_lidx; pa.ridx = c->d_ridx;
+  pa.lblk = c->blocks.size() > 1 ? c->d_lblk : nullptr;
+  pa.rblk = c->blocks.size() > 1 ? c->d_rblk : nullptr;
+  pa.nrm = c->d_nrm; pa.magL = c->d_magL; pa.magR = c->d_magR;
+  pa.uf = c->d_uf; pa.uf_f32 = f32; pa.cf = c->d_qf; pa.qf = c->d_qf;
+  pa.blk_ufbase = c->d_blk_ufbase; pa.blk_qfbase = c->d_blk_qfbase;
+  pa.blk_ld = c->d_blk_ld; pa.blk_qstride = c->d_blk_qstride;
+  pa.ld0 = c->blocks[0].ld;
+  pa.qstride0 = (int64_t)c->blocks[0].Nf * NV * c->blocks[0].ld;
+  pa.gamma = c->cfg.gamma; pa.mu = c->cfg.mu; pa.prandtl = c->cfg.prandtl;
+  pa.beta = c->cfg.ldg_beta; pa.tau = c->cfg.ldg_tau;
+  if (c->ns) {
+    // S2: common solution C^f (stored in the Q^f region)
+    hip_check(fr::launch_con_u(pa, s), "con_u");
+    if (stop <= 2) return;
+    for (auto &b : c->blocks) {
+      // S3: Q~ = M6 C^f + (M4 - M6 M0) U^u
+      fr::GemmArgs g = gemm_args(b.s3);
+      g.B1 = elem(c->d_qf, b.qfoff, ts); g.ldb1 = NV * b.ld; g.b1_f32 = f32;
+      g.B2 = u + b.uoff; g.ldb2 = NV * b.ld; g.b2_f32 = 0;
+      g.C = elem(c->d_ft, b.ftoff, ts); g.ldc = NV * b.ld; g.c_f32 = f32;
+      g.N = NV * b.ld;
+      hip_check(fr::launch_gemm(gprec, fr::EPI_STORE, g, 1, s), "gemm M6|M4'");
+      if (stop <= 3) continue;
+      // S4: Q = J^-T Q~ in place
+      fr::PointArgs p;
+      std::memset(&p, 0, sizeof(p));
+      p.ndims = D; p.nvars = NV; p.nupts = b.Nu; p.ld = b.ld; p.nelem = b.nelem;
+      p.smat = b.d_smat; p.rcpdjac = b.d_rcpdjac; p.u = u + b.uoff;
+      p.q = elem(c->d_ft, b.ftoff, ts); p.q_f32 = f32;
+      p.gamma = c->cfg.gamma; p.mu = c->cfg.mu; p.prandtl = c->cfg.prandtl;
+      hip_check(fr::launch_gradcoru(p, s), "gradcoru");
+      if (stop <= 4) continue;
+      // S5: Q^f = blockdiag(M0) Q (one batch per spatial component)
+      fr::GemmArgs g5 = gemm_args(b.m0);
+      g5.B1 = elem(c->d_ft, b.ftoff, ts); g5.ldb1 = NV * b.ld; g5.b1_f32 = f32;
+      g5.b2_f32 = f32;
+      g5.C = elem(c->d_qf, b.qfoff, ts); g5.ldc = NV * b.ld; g5.c_f32 = f32;
+      g5.N = NV * b.ld;
+      g5.sB1 = (int64_t)b.Nu * NV * b.ld;
+      g5.sC = (int64_t)b.Nf * NV * b.ld;
+      hip_check(fr::launch_gemm(gprec, fr::EPI_STORE, g5, D, s), "gemm M5");
+      if (stop <= 5) continue;
+      // S6: transformed flux, overwriting Q
+      hip_check(fr::launch_tflux(p, 1, s), "tflux NS");
+    }
+  } else {
+    for (auto &b : c->blocks) {
+      fr::PointArgs p;
+      std::memset(&p, 0, sizeof(p));
+      p.ndims = D; p.nvars = NV; p.nupts = b.Nu; p.ld = b.ld; p.nelem = b.nelem;
+      p.smat = b.d_smat; p.rcpdjac = b.d_rcpdjac; p.u = u + b.uoff;
+      p.q = elem(c->d_ft, b.ftoff, ts); p.q_f32 = f32;
+      p.gamma = c->cfg.gamma;
+      hip_check(fr::launch_tflux(p, 0, s), "tflux Euler");
+    }
+  }
+  if (stop <= 6) return;
+  // S7: common normal flux, in place over U^f
+  hip_check(fr::launch_comm_flux(pa, c->ns, s), "comm_flux");
+  if (stop <= 7) return;
+  // S8 + S9 (+ S10): R = -J^-1 (M3 D~ + (M1 - M3 M2) F~)
+  for (auto &b : c->blocks) {
+    fr::GemmArgs g = gemm_args(b.s8);
+    g.B1 = elem(c->d_uf, b.ufoff, ts); g.ldb1 = NV * b.ld; g.b1_f32 = f32;
+    g.B2 = elem(c->d_ft, b.ftoff, ts); g.ldb2 = NV * b.ld; g.b2_f32 = f32;
+    g.ldc = NV * b.ld; g.N = NV * b.ld;
+    g.rcpdjac = b.d_rcpdjac; g.ld = b.ld; g.nelem = b.nelem;
+    if (epi == fr::EPI_NEGDIV) {
+      g.out = dudt + b.uoff;
+    } else {
+      g.out = dudt + b.uoff;  // the caller's u register
+      g.acc = c->d_acc + b.uoff;
+      g.stage = c->d_stage + b.uoff;
+      g.dt = dt; g.prob = b.d_prob; g.rk = *rk;
+    }
+    hip_check(fr::launch_gemm(gprec, epi, g, 1, s), "gemm M3|M1'");
+  }
+}
+
+// One classical RK4 step of u in place: k_s = R(stage_s), with
+// acc = u + dt/6 k1 + dt/3 k2 + dt/3 k3 and u <- acc + dt/6 k4.
+void rk4_step(fr_ctx *c, double *u, const double *dt, hipStream_t s) {
+  static const double a_next[4] = {0.5, 0.5, 1.0, 0.0};
+  static const double b[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
+  for (int st = 0; st < 4; ++st) {
+    fr::RkCoef rk;
+    rk.a_next = a_next[st]; rk.b = b[st]; rk.first = st == 0; rk.last = st == 3;
+    rhs_chain(c, st == 0 ? u : c->d_stage, u, fr::EPI_RK, &rk, dt, s);
+  }
+}
+
+void release_graph(fr_ctx *c) {
+  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr; c->graph = nullptr; c->graph_u = nullptr; c->graph_dt = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+fr_status fr_setup_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *blocks,
+                        int64_t npairs, const fr_facepair *pairs, void *hip_stream,
+                        fr_ctx **out) {
+  if (!out) return fail(nullptr, FR_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!cfg || !blocks || nblocks < 1 || npairs < 0 || (npairs > 0 && !pairs))
+    return fail(nullptr, FR_EINVAL, "bad arguments");
+  if (cfg->ndims != 2 && cfg->ndims != 3) return fail(nullptr, FR_EINVAL, "ndims must be 2 or 3");
+  if (cfg->system != FR_EULER && cfg->system != FR_NAVIER_STOKES)
+    return fail(nullptr, FR_EINVAL, "bad system");
+  if (cfg->prec != FR_FP64 && cfg->prec != FR_FP32)
+    return fail(nullptr, FR_EUNSUPPORTED, "precision mode not available");
+  if (!(cfg->gamma > 1.0)) return fail(nullptr, FR_EINVAL, "gamma must exceed 1");
+  if (cfg->system == FR_NAVIER_STOKES && !(cfg->mu >= 0 && cfg->prandtl > 0))
+    return fail(nullptr, FR_EINVAL, "bad viscosity or Prandtl number");
+  std::unique_ptr<fr_ctx> c(new fr_ctx);
+  c->cfg = *cfg;
+  c->D = cfg->ndims; c->NV = cfg->ndims + 2;
+  c->ns = cfg->system == FR_NAVIER_STOKES;
+  c->prec = cfg->prec;
+  c->tsize = cfg->prec == FR_FP64 ? 8 : 4;
+  c->nproblems = cfg->nproblems > 0 ? cfg->nproblems : 1;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int D = c->D, NV = c->NV;
+  try {
+    std::map<std::pair<int, int>, int> refmap;
+    std::vector<fr::BlockGeom> geoms;
+    std::vector<int> block_ref;
+    int64_t uoff = 0, ufoff = 0, qfoff = 0, ftoff = 0, poff = 0;
+    for (int bi = 0; bi < nblocks; ++bi) {
+      const fr_block &B = blocks[bi];
+      if (B.nelem < 1 || !B.nodes) throw Fail{FR_EINVAL, "block without elements or nodes"};
+      if ((B.etype == FR_HEX) != (D == 3) || B.etype < 0 || B.etype > 2)
+        throw Fail{FR_EINVAL, "element type does not match ndims"};
+      auto key = std::make_pair(B.etype, B.order);
+      if (!refmap.count(key)) {
+        refmap[key] = (int)c->refs.size();
+        c->refs.push_back(fr::build_ref(B.etype, B.order));
+      }
+      BlockRT rt;
+      rt.ref = refmap[key];
+      const fr::RefOps &R = c->refs[rt.ref];
+      rt.etype = B.etype; rt.order = B.order;
+      rt.nelem = B.nelem; rt.ld = round_up(B.nelem, 16);
+      rt.Nu = R.nupts; rt.Nf = R.nfpts;
+      geoms.push_back(fr::build_geom(R, B.geom_order, B.nelem, B.nodes, rt.ld));
+      block_ref.push_back(rt.ref);
+      rt.uoff = uoff; uoff += (int64_t)rt.Nu * NV * rt.ld;
+      rt.ufoff = ufoff; ufoff += (int64_t)rt.Nf * NV * rt.ld;
+      rt.qfoff = qfoff; qfoff += (int64_t)D * rt.Nf * NV * rt.ld;
+      rt.ftoff = ftoff; ftoff += (int64_t)D * rt.Nu * NV * rt.ld;
+      rt.part_off = poff; poff += B.nelem;
+      c->blocks.push_back(std::move(rt));
+    }
+    c->total_len = uoff; c->uf_len = ufoff; c->qf_len = c->ns ? qfoff : 0; c->ft_len = ftoff;
+    c->nelem_total = poff;
+    if (ufoff >= (1ll << 31) || qfoff >= (1ll << 31))
+      throw Fail{FR_EUNSUPPORTED, "mesh too large for 32-bit flux-point indices"};
+    // pairs
+    std::vector<fr::FacePairIn> pin(npairs);
+    for (int64_t k = 0; k < npairs; ++k) {
+      const fr_facepair &P = pairs[k];
+      pin[k] = fr::FacePairIn{P.lblock, P.lface, P.lelem, P.rblock, P.rface, P.relem,
+                              {P.shift[0], P.shift[1], P.shift[2]}};
+    }
+    fr::PairTable T = fr::build_pairs(c->refs, geoms, block_ref, D, NV, pin.data(), npairs);
+    c->npairs = T.n;
+    // device data: geometry and operators
+    for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
+      BlockRT &b = c->blocks[bi];
+      fr::BlockGeom &G = geoms[bi];
+      const fr::RefOps &R = c->refs[b.ref];
+      b.d_smat = dev_upload(c.get(), G.smat.data(), G.smat.size(), s);
+      b.d_rcpdjac = dev_upload(c.get(), G.rcpdjac.data(), G.rcpdjac.size(), s);
+      b.d_wdjac = dev_upload(c.get(), G.wdjac.data(), G.wdjac.size(), s);
+      b.xu = std::move(G.xu);
+      b.wdjac_host.resize((size_t)b.Nu * b.nelem);
+      for (int r = 0; r < b.Nu; ++r)
+        for (int64_t n = 0; n < b.nelem; ++n)
+          b.wdjac_host[(size_t)r * b.nelem + n] = G.wdjac[(size_t)r * b.ld + n];
+      if (blocks[bi].problem) {
+        for (int64_t n = 0; n < b.nelem; ++n)
+          if (blocks[bi].problem[n] < 0 || blocks[bi].problem[n] >= c->nproblems)
+            throw Fail{FR_EINVAL, "problem id out of range"};
+        b.d_prob = dev_upload(c.get(), blocks[bi].problem, b.nelem, s);
+      }
+      const int64_t N = (int64_t)NV * b.ld;
+      make_op(c.get(), b.m0, R.M0, R.nfpts, R.nupts, 0, N, s);
+      make_op(c.get(), b.s8, hcat(R.M3, R.nfpts, R.M1p, D * R.nupts, R.nupts), R.nupts,
+              R.nfpts, D * R.nupts, N, s);
+      if (c->ns)
+        make_op(c.get(), b.s3, hcat(R.M6, R.nfpts, R.M4p, R.nupts, D * R.nupts), D * R.nupts,
+                R.nfpts, R.nupts, N, s);
+      G = fr::BlockGeom();
+    }
+    // pair table
+    {
+      std::vector<int32_t> li(T.n), ri(T.n);
+      for (int64_t i = 0; i < T.n; ++i) { li[i] = (int32_t)T.lidx[i]; ri[i] = (int32_t)T.ridx[i]; }
+      c->d_lidx = dev_upload(c.get(), li.data(), T.n, s);
+      c->d_ridx = dev_upload(c.get(), ri.data(), T.n, s);
+      c->d_lblk = dev_upload(c.get(), T.lblk.data(), T.n, s);
+      c->d_rblk = dev_upload(c.get(), T.rblk.data(), T.n, s);
+      c->d_nrm = dev_upload(c.get(), T.nrm.data(), T.nrm.size(), s);
+      c->d_magL = dev_upload(c.get(), T.magL.data(), T.n, s);
+      c->d_magR = dev_upload(c.get(), T.magR.data(), T.n, s);
+      std::vector<int64_t> ub, qb, lds, qs;
+      for (auto &b : c->blocks) {
+        ub.push_back(b.ufoff); qb.push_back(b.qfoff); lds.push_back(b.ld);
+        qs.push_back((int64_t)b.Nf * NV * b.ld);
+      }
+      c->d_blk_ufbase = dev_upload(c.get(), ub.data(), ub.size(), s);
+      c->d_blk_qfbase = dev_upload(c.get(), qb.data(), qb.size(), s);
+      c->d_blk_ld = dev_upload(c.get(), lds.data(), lds.size(), s);
+      c->d_blk_qstride = dev_upload(c.get(), qs.data(), qs.size(), s);
+    }
+    // scratch
+    c->d_uf = c->prec == FR_FP64 ? (void *)dev_alloc<double>(c.get(), c->uf_len)
+                                  : (void *)dev_alloc<float>(c.get(), c->uf_len);
+    c->d_ft = c->prec == FR_FP64 ? (void *)dev_alloc<double>(c.get(), c->ft_len)
+                                  : (void *)dev_alloc<float>(c.get(), c->ft_len);
+    if (c->ns)
+      c->d_qf = c->prec == FR_FP64 ? (void *)dev_alloc<double>(c.get(), c->qf_len)
+                                    : (void *)dev_alloc<float>(c.get(), c->qf_len);
+    c->d_acc = dev_alloc<double>(c.get(), c->total_len);
+    c->d_stage = dev_alloc<double>(c.get(), c->total_len);
+    // reductions: element partials and per-problem element lists
+    c->d_part = dev_alloc<double>(c.get(), (size_t)c->nelem_total * (NV + 1));
+    {
+      std::vector<std::vector<int64_t>> lists(c->nproblems);
+      for (size_t bi = 0; bi < c->blocks.size(); ++bi)
+        for (int64_t n = 0; n < c->blocks[bi].nelem; ++n) {
+          int pr = blocks[bi].problem ? blocks[bi].problem[n] : 0;
+          lists[pr].push_back(c->blocks[bi].part_off + n);
+        }
+      std::vector<int64_t> start(1, 0), flat;
+      for (auto &l : lists) { flat.insert(flat.end(), l.begin(), l.end()); start.push_back(flat.size()); }
+      c->d_pstart = dev_upload(c.get(), start.data(), start.size(), s);
+      c->d_plist = dev_upload(c.get(), flat.data(), flat.size(), s);
+    }
+    c->d_flag = dev_alloc<int32_t>(c.get(), 1);
+    hip_check(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "stream");
+    hip_check(hipDeviceSynchronize(), "setup sync");
+  } catch (const fr::SetupError &e) {
+    fr_destroy(c.release());
+    return fail(nullptr, (fr_status)e.status, e.what());
+  } catch (const Fail &f) {
+    fr_destroy(c.release());
+    return fail(nullptr, f.st, f.msg);
+  } catch (const std::exception &e) {
+    fr_destroy(c.release());
+    return fail(nullptr, FR_ENOMEM, e.what());
+  }
+  *out = c.release();
+  return FR_OK;
+}
+
+fr_status fr_get_layout(const fr_ctx *c, int32_t block, int64_t *offset, int64_t *ld,
+                        int32_t *nupts, int32_t *nvars, int64_t *total_len) {
+  if (!c || block < 0 || block >= (int)c->blocks.size()) return FR_EINVAL;
+  const BlockRT &b = c->blocks[block];
+  if (offset) *offset = b.uoff;
+  if (ld) *ld = b.ld;
+  if (nupts) *nupts = b.Nu;
+  if (nvars) *nvars = c->NV;
+  if (total_len) *total_len = c->total_len;
+  return FR_OK;
+}
+
+fr_status fr_get_solution_points(const fr_ctx *c, int32_t block, double *xyz) {
+  if (!c || !xyz || block < 0 || block >= (int)c->blocks.size()) return FR_EINVAL;
+  const BlockRT &b = c->blocks[block];
+  std::memcpy(xyz, b.xu.data(), b.xu.size() * sizeof(double));
+  return FR_OK;
+}
+
+fr_status fr_get_quadrature(const fr_ctx *c, int32_t block, double *wj) {
+  if (!c || !wj || block < 0 || block >= (int)c->blocks.size()) return FR_EINVAL;
+  const BlockRT &b = c->blocks[block];
+  std::memcpy(wj, b.wdjac_host.data(), b.wdjac_host.size() * sizeof(double));
+  return FR_OK;
+}
+
+fr_status fr_rhs(fr_ctx *c, const double *u, double *dudt, void *hip_stream) {
+  if (!c) return FR_EINVAL;
+  if (!u || !dudt) return fail(c, FR_EINVAL, "null state pointer");
+  try {
+    rhs_chain(c, u, dudt, fr::EPI_NEGDIV, nullptr, nullptr, (hipStream_t)hip_stream);
+  } catch (const Fail &f) {
+    return fail(c, f.st, f.msg);
+  }
+  return FR_OK;
+}
+
+fr_status fr_rk_step(fr_ctx *c, double *u, const double *dt_dev, int32_t nsteps,
+                     void *hip_stream) {
+  if (!c) return FR_EINVAL;
+  if (!u || !dt_dev || nsteps < 0) return fail(c, FR_EINVAL, "bad rk_step arguments");
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    if (nsteps > 0 && (c->graph_u != u || c->graph_dt != dt_dev || !c->graph_exec)) {
+      release_graph(c);
+      hip_check(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "capture");
+      try {
+        rk4_step(c, u, dt_dev, c->cap_stream);
+      } catch (...) {
+        hipGraph_t g;
+        hipStreamEndCapture(c->cap_stream, &g);
+        if (g) hipGraphDestroy(g);
+        throw;
+      }
+      hip_check(hipStreamEndCapture(c->cap_stream, &c->graph), "end capture");
+      hip_check(hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0), "instantiate");
+      c->graph_u = u; c->graph_dt = dt_dev;
+    }
+    for (int i = 0; i < nsteps; ++i) hip_check(hipGraphLaunch(c->graph_exec, s), "graph launch");
+    if (c->cfg.check_finite) {
+      int32_t h = 0;
+      hip_check(hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), s), "memset");
+      hip_check(fr::launch_check_finite(u, c->total_len, c->d_flag, s), "check_finite");
+      hip_check(hipMemcpyAsync(&h, c->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s), "copy");
+      hip_check(hipStreamSynchronize(s), "sync");
+      if (h) return fail(c, FR_ENONFINITE, "state contains NaN or Inf");
+    }
+  } catch (const Fail &f) {
+    return fail(c, f.st, f.msg);
+  }
+  return FR_OK;
+}
+
+fr_status fr_rhs_adjoint(fr_ctx *c, const double *u, const double *lam, double *ulam,
+                         void *hip_stream) {
+  if (!c) return FR_EINVAL;
+  (void)u; (void)lam; (void)ulam; (void)hip_stream;
+  return fail(c, FR_EUNSUPPORTED, "adjoint not available in this build");
+}
+
+fr_status fr_rk_step_adjoint(fr_ctx *c, const double *u_n, const double *dt_dev,
+                             const double *lam_np1, double *lam_n, void *hip_stream) {
+  if (!c) return FR_EINVAL;
+  (void)u_n; (void)dt_dev; (void)lam_np1; (void)lam_n; (void)hip_stream;
+  return fail(c, FR_EUNSUPPORTED, "adjoint not available in this build");
+}
+
+fr_status fr_integrate(fr_ctx *c, const double *u, int32_t kind, double *out, void *hip_stream) {
+  if (!c) return FR_EINVAL;
+  if (!u || !out || kind != 0) return fail(c, FR_EINVAL, "bad integrate arguments");
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    for (auto &b : c->blocks)
+      hip_check(fr::launch_elem_integrals(c->NV, c->D, b.Nu, b.ld, b.nelem, b.d_wdjac, u + b.uoff,
+                                          c->d_part + b.part_off * (c->NV + 1), s),
+                "elem integrals");
+    hip_check(fr::launch_problem_sums(c->NV + 1, c->nproblems, c->d_pstart, c->d_plist,
+                                      c->d_part, out, s),
+              "problem sums");
+  } catch (const Fail &f) {
+    return fail(c, f.st, f.msg);
+  }
+  return FR_OK;
+}
+
+fr_status fr_reference_operator(int32_t etype, int32_t order, int32_t which, double *out,
+                                int64_t cap, int32_t *rows, int32_t *cols) {
+  try {
+    fr::RefOps R = fr::build_ref(etype, order);
+    const int D = R.ndims, Nu = R.nupts, Nf = R.nfpts;
+    const std::vector<double> *v = nullptr;
+    int r = 0, cc = 0;
+    switch (which) {
+      case 0: v = &R.M0; r = Nf; cc = Nu; break;
+      case 1: v = &R.M3; r = Nu; cc = Nf; break;
+      case 2: v = &R.M4p; r = D * Nu; cc = Nu; break;
+      case 3: v = &R.M6; r = D * Nu; cc = Nf; break;
+      case 4: v = &R.M1p; r = Nu; cc = D * Nu; break;
+      case 5: v = &R.upts; r = Nu; cc = D; break;
+      case 6: v = &R.fpts; r = Nf; cc = D; break;
+      case 7: v = &R.fnorm; r = Nf; cc = D; break;
+      case 8: v = &R.W; r = Nu; cc = 1; break;
+      case 9: v = &R.fweight; r = Nf; cc = 1; break;
+      case 10: v = &R.M4; r = D * Nu; cc = Nu; break;
+      case 11: v = &R.M1; r = Nu; cc = D * Nu; break;
+      default: return fail(nullptr, FR_EINVAL, "bad operator id");
+    }
+    if (rows) *rows = r;
+    if (cols) *cols = cc;
+    if (!out) return FR_OK;
+    if (cap < (int64_t)v->size()) return fail(nullptr, FR_EINVAL, "output too small");
+    std::memcpy(out, v->data(), v->size() * sizeof(double));
+  } catch (const fr::SetupError &e) {
+    return fail(nullptr, (fr_status)e.status, e.what());
+  }
+  return FR_OK;
+}
+
+fr_status fr_check_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *blocks,
+                        int64_t npairs, const fr_facepair *pairs, int64_t *npoint_pairs) {
+  if (!cfg || !blocks || nblocks < 1 || npairs < 0 || (npairs > 0 && !pairs))
+    return fail(nullptr, FR_EINVAL, "bad arguments");
+  const int D = cfg->ndims;
+  if (D != 2 && D != 3) return fail(nullptr, FR_EINVAL, "ndims must be 2 or 3");
+  try {
+    std::vector<fr::RefOps> refs;
+    std::map<std::pair<int, int>, int> refmap;
+    std::vector<fr::BlockGeom> geoms;
+    std::vector<int> block_ref;
+    for (int bi = 0; bi < nblocks; ++bi) {
+      const fr_block &B = blocks[bi];
+      if (B.nelem < 1 || !B.nodes) return fail(nullptr, FR_EINVAL, "block without elements");
+      if ((B.etype == FR_HEX) != (D == 3) || B.etype < 0 || B.etype > 2)
+        return fail(nullptr, FR_EINVAL, "element type does not match ndims");
+      auto key = std::make_pair(B.etype, B.order);
+      if (!refmap.count(key)) { refmap[key] = (int)refs.size(); refs.push_back(fr::build_ref(B.etype, B.order)); }
+      block_ref.push_back(refmap[key]);
+      geoms.push_back(fr::build_geom(refs[refmap[key]], B.geom_order, B.nelem, B.nodes,
+                                     round_up(B.nelem, 16)));
+    }
+    std::vector<fr::FacePairIn> pin(npairs);
+    for (int64_t k = 0; k < npairs; ++k) {
+      const fr_facepair &P = pairs[k];
+      pin[k] = fr::FacePairIn{P.lblock, P.lface, P.lelem, P.rblock, P.rface, P.relem,
+                              {P.shift[0], P.shift[1], P.shift[2]}};
+    }
+    fr::PairTable T = fr::build_pairs(refs, geoms, block_ref, D, D + 2, pin.data(), npairs);
+    if (npoint_pairs) *npoint_pairs = T.n;
+  } catch (const fr::SetupError &e) {
+    return fail(nullptr, (fr_status)e.status, e.what());
+  } catch (const std::exception &e) {
+    return fail(nullptr, FR_ENOMEM, e.what());
+  }
+  return FR_OK;
+}
+
+fr_status fr_debug_stage(fr_ctx *c, const double *u, int32_t stage, double *out,
+                         void *hip_stream) {
+  if (!c || !u || !out || stage < 1 || stage > 7) return FR_EINVAL;
+  if (c->prec != FR_FP64) return fail(c, FR_EUNSUPPORTED, "debug stages are FP64 only");
+  if (!c->ns && stage >= 2 && stage <= 5) return fail(c, FR_EINVAL, "no such stage for Euler");
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    rhs_chain(c, u, nullptr, fr::EPI_NEGDIV, nullptr, nullptr, s, stage);
+    const void *src = nullptr;
+    int64_t n = 0;
+    if (stage == 1 || stage == 7) { src = c->d_uf; n = c->uf_len; }
+    else if (stage == 2) { src = c->d_qf; n = c->qf_len; }
+    else if (stage == 5) { src = c->d_qf; n = c->qf_len; }
+    else { src = c->d_ft; n = c->ft_len; }
+    hip_check(hipMemcpyAsync(out, src, n * sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
+  } catch (const Fail &f) {
+    return fail(c, f.st, f.msg);
+  }
+  return FR_OK;
+}
+
+fr_status fr_debug_scratch_len(const fr_ctx *c, int32_t stage, int64_t *len) {
+  if (!c || !len) return FR_EINVAL;
+  *len = (stage == 1 || stage == 7) ? c->uf_len : ((stage == 2 || stage == 5) ? c->qf_len : c->ft_len);
+  return FR_OK;
+}
+
+fr_status fr_debug_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, const double *A,
+                        const void *B1, const void *B2, int64_t ldb, void *C, int64_t N,
+                        void *hip_stream) {
+  if (!A || !B1 || !C || M < 1 || K1 < 1 || K2 < 0 || N < 16 || N % 16 || (K2 && !B2))
+    return fail(nullptr, FR_EINVAL, "bad gemm arguments");
+  if (prec != FR_FP64 && prec != FR_FP32) return fail(nullptr, FR_EUNSUPPORTED, "precision");
+  hipStream_t s = (hipStream_t)hip_stream;
+  fr_ctx tmp;
+  tmp.prec = prec;
+  try {
+    GemmOp op;
+    std::vector<double> Av(A, A + (size_t)M * (K1 + K2));
+    make_op(&tmp, op, Av, M, K1, K2, N, s);
+    fr::GemmArgs g = gemm_args(op);
+    g.B1 = B1; g.ldb1 = ldb; g.b1_f32 = 0;
+    g.B2 = B2; g.ldb2 = ldb; g.b2_f32 = 0;
+    g.C = C; g.ldc = N; g.c_f32 = prec == FR_FP32;
+    g.N = N;
+    hip_check(fr::launch_gemm(prec == FR_FP64 ? fr::PREC_F64 : fr::PREC_F32, fr::EPI_STORE, g, 1, s),
+              "gemm");
+    hip_check(hipStreamSynchronize(s), "sync");
+  } catch (const Fail &f) {
+    for (void *p : tmp.allocs) hipFree(p);
+    return fail(nullptr, f.st, f.msg);
+  }
+  for (void *p : tmp.allocs) hipFree(p);
+  return FR_OK;
+}
+
+const char *fr_last_error(const fr_ctx *c) {
+  return c ? c->err.c_str() : g_setup_error.c_str();
+}
+
+void fr_destroy(fr_ctx *c) {
+  if (!c) return;
+  hipDeviceSynchronize();
+  release_graph(c);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  for (void *p : c->allocs) hipFree(p);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// Device kernels of the FR right-hand side and their host launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace fr {
+
+// ----------------------------------------------------------------------------
+// Operator GEMM  C = A [B1; B2]  (Appendix A form C <- A B), A packed on the
+// host into MFMA fragment order.  Columns are the SoA state columns
+// alpha*ld + n; rows are solution/flux points (times spatial components).
+// ----------------------------------------------------------------------------
+enum GemmEpi {
+  EPI_STORE = 0,   // C[row][col] = acc                         (C of type TC)
+  EPI_NEGDIV = 1,  // out = -rcpdjac[row][n] * acc, 0 for padding  (FP64 out)
+  EPI_RK = 2       // RK4 stage update from k = -rcpdjac * acc      (FP64 regs)
+};
+
+enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };
+
+struct RkCoef {
+  double a_next;    // stage_next = u + a_next * dt * k  (ignored on the last stage)
+  double b;         // acc += b * dt * k
+  int first;        // acc is initialised from u on the first stage
+  int last;         // u = acc + b dt k on the last stage (no stage write)
+};
+
+struct GemmArgs {
+  const void *Apack;      // packed operator (precision dependent element type)
+  int M;                  // rows of A (= rows of C)
+  int KS1, KS2;           // k-steps (of the MFMA K) in each panel
+  int K1, K2;             // true K of each panel
+  int MBW;                // row blocks (16 rows) per wave
+  int WM;                 // waves along M sharing one column tile
+  const void *B1; int64_t ldb1; int b1_f32;   // panel 1 (rows K1), row stride
+  const void *B2; int64_t ldb2; int b2_f32;   // panel 2 (rows K2)
+  void *C; int64_t ldc; int c_f32;            // output (EPI_STORE)
+  int64_t N;              // columns (nvars * ld)
+  int64_t sB1, sC;        // batch strides (blockIdx.y) in elements
+  // epilogue data
+  const double *rcpdjac; int64_t ld; int64_t nelem;
+  double *out;            // EPI_NEGDIV output / EPI_RK: u (in/out)
+  double *acc; double *stage;
+  const double *dt; const int32_t *prob;      // per-problem step size, element -> problem
+  RkCoef rk;
+};
+
+// Pack A (M x (K1 + K2), row-major, panel 2 columns follow panel 1) into the
+// fragment layout the kernel reads; returns element count, writes into dst
+// (may be null to query).  kstep = 4 for FP64/FP32.
+int64_t gemm_pack_size(int M, int K1, int K2, int MBW, int WM, int kstep);
+void gemm_pack_f64(const double *A, int M, int K1, int K2, int MBW, int WM, double *dst);
+void gemm_pack_f32(const double *A, int M, int K1, int K2, int MBW, int WM, float *dst);
+// BF16x3: hi and lo parts interleaved per fragment (see kernel)
+int64_t gemm_pack_size_bf16(int M, int K1, int K2, int MBW, int WM);
+void gemm_pack_bf16x3(const double *A, int M, int K1, int K2, int MBW, int WM, uint16_t *dst);
+
+hipError_t launch_gemm(int prec, int epi, const GemmArgs &g, int batch, hipStream_t s);
+
+// Choose the row split for an M-row operator and N columns.
+void gemm_plan(int M, int64_t N, int prec, int *MBW, int *WM);
+
+// ----------------------------------------------------------------------------
+// Point-wise and interface kernels
+// ----------------------------------------------------------------------------
+struct PointArgs {
+  int ndims, nvars, nupts;
+  int64_t ld, nelem;
+  const double *smat;      // [D][D][Nu][ld]
+  const double *rcpdjac;   // [Nu][ld]
+  const double *u;         // state [Nu][NV][ld]
+  void *q;                 // gradients / transformed flux [D][Nu][NV][ld] (in place)
+  int q_f32;
+  double gamma, mu, prandtl;
+};
+
+// S4: q = J^-T q~ in place
+hipError_t launch_gradcoru(const PointArgs &a, hipStream_t s);
+// S6: f~ = S f(u, q) (Euler reads no q, writes f~ into q's storage)
+hipError_t launch_tflux(const PointArgs &a, int navier_stokes, hipStream_t s);
+
+struct PairArgs {
+  int ndims, nvars;
+  int64_t npairs;
+  const int32_t *lidx, *ridx;      // within-block flux-point index sigma*NV*ld + n
+  const int32_t *lblk, *rblk;      // block of each side (null: single block)
+  const double *nrm;               // [D][npairs]
+  const double *magL, *magR;
+  void *uf; int uf_f32;            // U^f -> D~ in place
+  void *cf;                        // C^f output (con_u)
+  const void *qf;                  // Q^f (NS common flux)
+  const int64_t *blk_ufbase;       // per block: offset into uf/cf
+  const int64_t *blk_qfbase;       // per block: offset into qf
+  const int64_t *blk_ld;           // per block: leading dimension
+  const int64_t *blk_qstride;      // per block: Nf * NV * ld
+  int64_t ld0, qstride0;           // single-block values
+  double gamma, mu, prandtl, beta, tau;
+};
+
+// S2: common solution to both sides
+hipError_t launch_con_u(const PairArgs &a, hipStream_t s);
+// S7: common normal flux, scaled per side, in place over U^f
+hipError_t launch_comm_flux(const PairArgs &a, int navier_stokes, hipStream_t s);
+
+// ----------------------------------------------------------------------------
+// Reductions
+// ----------------------------------------------------------------------------
+// per-element integrals of (u[alpha] for alpha<NV, kinetic energy) into part
+// [nelem][NV+1]
+hipError_t launch_elem_integrals(int nvars, int ndims, int nupts, int64_t ld, int64_t nelem,
+                                 const double *wdjac, const double *u, double *part,
+                                 hipStream_t s);
+// sum part rows per problem in fixed order: CSR (pstart[nprob+1], plist)
+hipError_t launch_problem_sums(int ncomp, int nprob, const int64_t *pstart,
+                               const int64_t *plist, const double *part, double *out,
+                               hipStream_t s);
+// flag[0] = 1 if any u is not finite
+hipError_t launch_check_finite(const double *u, int64_t n, int32_t *flag, hipStream_t s);
+
+}  // namespace fr

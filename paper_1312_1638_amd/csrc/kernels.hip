@@ -1,0 +1,651 @@
+// HIP kernels of the FR right-hand side for gfx950 (CDNA4).
+//
+//  * Operator products (Appendix A) on the matrix cores: one wavefront owns a
+//    16-column strip of the state matrix and MBW 16-row blocks of the
+//    operator; it streams its B strip from HBM exactly once (each lane loads
+//    one element per 4-row k-step: 4 rows x 128 contiguous bytes per load)
+//    and reads the operator from a pre-packed fragment stream that stays in
+//    L2.  Accumulation is FP64 (v_mfma_f64_16x16x4) or FP32
+//    (v_mfma_f32_16x16x4), with fused epilogues for du/dt = -J^-1 R~ and the
+//    RK4 register updates.
+//  * Point-wise kernels (gradient transform, transformed flux) are one thread
+//    per (solution point, element): every access is a unit-stride row of the
+//    SoA state, so a wavefront reads 64 consecutive elements.
+//  * Interface kernels are one thread per flux-point pair (each pair visited
+//    once, same value to both sides), with pair constants stored in pair
+//    order and pairs sorted by their left flux point, so the left side and
+//    the constants are coalesced; workgroups are remapped so that each XCD
+//    processes a contiguous range of pairs.
+#include "kernels.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace fr {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// ============================================================================
+// Operator GEMM
+// ============================================================================
+template <typename T> struct Mma;
+// Output lane layouts differ: register r of lane l holds row 4 r + l / 16 for
+// v_mfma_f64_16x16x4f64 and row 4 (l / 16) + r for v_mfma_f32_16x16x4f32
+// (column l % 16 in both; inputs A[l % 16][l / 16], B[l / 16][l % 16]).
+template <> struct Mma<double> {
+  typedef dbl4 acc_t;
+  static __device__ __forceinline__ int row(int kq, int r) { return 4 * r + kq; }
+  static __device__ __forceinline__ acc_t run(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mma<float> {
+  typedef flt4 acc_t;
+  static __device__ __forceinline__ int row(int kq, int r) { return 4 * kq + r; }
+  static __device__ __forceinline__ acc_t run(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+template <typename T, typename TB>
+__device__ __forceinline__ T load_b(const TB *__restrict__ B, int64_t ldb, int K, int ks, int kq,
+                                    int64_t col) {
+  int k = ks * 4 + kq;
+  return k < K ? (T)B[(int64_t)k * ldb + col] : (T)0;
+}
+
+// Fragment layout of A: [wave row group rg][k-step][row block m][64 lanes],
+// lane l of fragment (m, ks) holding A[16 m' + l % 16][4 ks + l / 16].
+template <typename T, int MBW, int EPI, typename TB1, typename TB2, typename TC>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+  typedef typename Mma<T>::acc_t acc_t;
+  const int lane = threadIdx.x & 63;
+  const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int rg = (int)(gw % g.WM);
+  const int64_t n0 = (gw / g.WM) * 16;
+  if (n0 >= g.N) return;
+  const int col = lane & 15, kq = lane >> 4;
+  const int64_t bcol = n0 + col;
+  const int KS = g.KS1 + g.KS2;
+  const TB1 *__restrict__ B1 = (const TB1 *)g.B1 + (int64_t)blockIdx.y * g.sB1;
+  const TB2 *__restrict__ B2 = (const TB2 *)g.B2;
+  const T *__restrict__ A = (const T *)g.Apack + (int64_t)rg * KS * MBW * 64 + lane;
+
+  acc_t acc[MBW];
+#pragma unroll
+  for (int m = 0; m < MBW; ++m) acc[m] = acc_t{0, 0, 0, 0};
+
+  T bcur = g.KS1 ? load_b<T>(B1, g.ldb1, g.K1, 0, kq, bcol) : load_b<T>(B2, g.ldb2, g.K2, 0, kq, bcol);
+  for (int ks = 0; ks < KS; ++ks) {
+    T bnext = 0;
+    const int kn = ks + 1;
+    if (kn < g.KS1)
+      bnext = load_b<T>(B1, g.ldb1, g.K1, kn, kq, bcol);
+    else if (kn < KS)
+      bnext = load_b<T>(B2, g.ldb2, g.K2, kn - g.KS1, kq, bcol);
+    T a[MBW];
+#pragma unroll
+    for (int m = 0; m < MBW; ++m) a[m] = A[((int64_t)ks * MBW + m) * 64];
+#pragma unroll
+    for (int m = 0; m < MBW; ++m) acc[m] = Mma<T>::run(a[m], bcur, acc[m]);
+    bcur = bnext;
+  }
+
+  // epilogue: lane holds rows 16 m + Mma<T>::row(kq, r), column n0 + col
+  const int64_t colg = n0 + col;
+  int64_t n = 0;
+  if (EPI != EPI_STORE) n = colg - (n0 / g.ld) * g.ld;
+  const bool live = n < g.nelem;
+  double dtv = 0;
+  if (EPI == EPI_RK && live) dtv = g.dt[g.prob ? g.prob[n] : 0];
+#pragma unroll
+  for (int m = 0; m < MBW; ++m) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = (rg * MBW + m) * 16 + Mma<T>::row(kq, r);
+      if (row >= g.M) continue;
+      const double v = (double)acc[m][r];
+      const int64_t idx = (int64_t)row * g.ldc + colg;
+      if (EPI == EPI_STORE) {
+        ((TC *)g.C)[(int64_t)blockIdx.y * g.sC + idx] = (TC)v;
+      } else {
+        const double k = live ? -g.rcpdjac[(int64_t)row * g.ld + n] * v : 0.0;
+        if (EPI == EPI_NEGDIV) {
+          g.out[idx] = k;
+        } else {
+          const double bdt = g.rk.b * dtv * k;
+          if (g.rk.last) {
+            g.out[idx] = g.acc[idx] + bdt;
+          } else {
+            const double u0 = g.out[idx];
+            g.acc[idx] = (g.rk.first ? u0 : g.acc[idx]) + bdt;
+            g.stage[idx] = u0 + g.rk.a_next * dtv * k;
+          }
+        }
+      }
+    }
+  }
+}
+
+int64_t gemm_pack_size(int M, int K1, int K2, int MBW, int WM, int kstep) {
+  int KS = (K1 + kstep - 1) / kstep + (K2 + kstep - 1) / kstep;
+  return (int64_t)WM * KS * MBW * 64;
+}
+
+template <typename T>
+static void gemm_pack(const double *A, int M, int K1, int K2, int MBW, int WM, T *dst) {
+  const int KS1 = (K1 + 3) / 4, KS2 = (K2 + 3) / 4, KS = KS1 + KS2, K = K1 + K2;
+  for (int rg = 0; rg < WM; ++rg)
+    for (int ks = 0; ks < KS; ++ks)
+      for (int m = 0; m < MBW; ++m)
+        for (int l = 0; l < 64; ++l) {
+          int row = (rg * MBW + m) * 16 + (l & 15);
+          int kk = ks < KS1 ? ks * 4 + (l >> 4) : (ks - KS1) * 4 + (l >> 4);
+          bool ok = ks < KS1 ? kk < K1 : kk < K2;
+          int acol = ks < KS1 ? kk : K1 + kk;
+          double v = (row < M && ok) ? A[(int64_t)row * K + acol] : 0.0;
+          dst[(((int64_t)rg * KS + ks) * MBW + m) * 64 + l] = (T)v;
+        }
+}
+
+void gemm_pack_f64(const double *A, int M, int K1, int K2, int MBW, int WM, double *dst) {
+  gemm_pack<double>(A, M, K1, K2, MBW, WM, dst);
+}
+void gemm_pack_f32(const double *A, int M, int K1, int K2, int MBW, int WM, float *dst) {
+  gemm_pack<float>(A, M, K1, K2, MBW, WM, dst);
+}
+
+void gemm_plan(int M, int64_t N, int prec, int *MBW, int *WM) {
+  const int MB = (M + 15) / 16;
+  const int maxw = 12;
+  const int64_t ntile = (N + 15) / 16;
+  int wm = (MB + maxw - 1) / maxw;
+  while (wm < MB && wm * ntile < 4096) ++wm;
+  int mbw = (MB + wm - 1) / wm;
+  wm = (MB + mbw - 1) / mbw;
+  *MBW = mbw;
+  *WM = wm;
+}
+
+// Element types of (B1, B2, C) by precision:
+//   FP64: all double.
+//   FP32 stores: B1 double (state) or float (scratch); B2 double (state) or
+//   float; C float.  FP32 fused epilogues: float scratch in, FP64 out.
+template <typename T, int MBW, int EPI>
+static hipError_t launch_gemm_t(const GemmArgs &g, int batch, hipStream_t s) {
+  const int64_t waves = ((g.N + 15) / 16) * g.WM;
+  dim3 grid((unsigned)((waves + 3) / 4), batch), block(256);
+  if constexpr (sizeof(T) == 8) {
+    gemm_kernel<T, MBW, EPI, double, double, double><<<grid, block, 0, s>>>(g);
+  } else if constexpr (EPI != EPI_STORE) {
+    gemm_kernel<T, MBW, EPI, float, float, double><<<grid, block, 0, s>>>(g);
+  } else {
+    if (!g.b1_f32)
+      gemm_kernel<T, MBW, EPI, double, double, float><<<grid, block, 0, s>>>(g);
+    else if (!g.b2_f32)
+      gemm_kernel<T, MBW, EPI, float, double, float><<<grid, block, 0, s>>>(g);
+    else
+      gemm_kernel<T, MBW, EPI, float, float, float><<<grid, block, 0, s>>>(g);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int EPI>
+static hipError_t launch_gemm_e(const GemmArgs &g, int batch, hipStream_t s) {
+  switch (g.MBW) {
+    case 1: return launch_gemm_t<T, 1, EPI>(g, batch, s);
+    case 2: return launch_gemm_t<T, 2, EPI>(g, batch, s);
+    case 3: return launch_gemm_t<T, 3, EPI>(g, batch, s);
+    case 4: return launch_gemm_t<T, 4, EPI>(g, batch, s);
+    case 5: return launch_gemm_t<T, 5, EPI>(g, batch, s);
+    case 6: return launch_gemm_t<T, 6, EPI>(g, batch, s);
+    case 7: return launch_gemm_t<T, 7, EPI>(g, batch, s);
+    case 8: return launch_gemm_t<T, 8, EPI>(g, batch, s);
+    case 9: return launch_gemm_t<T, 9, EPI>(g, batch, s);
+    case 10: return launch_gemm_t<T, 10, EPI>(g, batch, s);
+    case 11: return launch_gemm_t<T, 11, EPI>(g, batch, s);
+    case 12: return launch_gemm_t<T, 12, EPI>(g, batch, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gemm(int prec, int epi, const GemmArgs &g, int batch, hipStream_t s) {
+  if (g.N <= 0) return hipSuccess;
+  if (prec == PREC_F64) {
+    if (epi == EPI_STORE) return launch_gemm_e<double, EPI_STORE>(g, batch, s);
+    if (epi == EPI_NEGDIV) return launch_gemm_e<double, EPI_NEGDIV>(g, batch, s);
+    return launch_gemm_e<double, EPI_RK>(g, batch, s);
+  }
+  if (prec == PREC_F32) {
+    if (epi == EPI_STORE) return launch_gemm_e<float, EPI_STORE>(g, batch, s);
+    if (epi == EPI_NEGDIV) return launch_gemm_e<float, EPI_NEGDIV>(g, batch, s);
+    return launch_gemm_e<float, EPI_RK>(g, batch, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// BF16x3 packing is provided with its kernel elsewhere; size helper here.
+int64_t gemm_pack_size_bf16(int M, int K1, int K2, int MBW, int WM) {
+  int KS = (K1 + 15) / 16 + (K2 + 15) / 16;
+  return (int64_t)WM * KS * MBW * 64 * 4 * 2;
+}
+
+// ============================================================================
+// Physics (device): Euler flux, viscous flux, Rusanov and LDG fluxes
+// ============================================================================
+template <int D>
+__device__ __forceinline__ void primitives(const double *u, double gamma, double &rho, double *v,
+                                           double &p) {
+  rho = u[0];
+  const double ir = 1.0 / rho;
+  double ke = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) { v[i] = u[1 + i] * ir; ke += u[1 + i] * v[i]; }
+  p = (gamma - 1.0) * (u[D + 1] - 0.5 * ke);
+}
+
+// f[j][alpha] of the Euler equations
+template <int D>
+__device__ __forceinline__ void inviscid_flux(const double *u, double gamma, double f[D][D + 2],
+                                              double &p, double *v) {
+  double rho;
+  primitives<D>(u, gamma, rho, v, p);
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    f[j][0] = u[1 + j];
+#pragma unroll
+    for (int i = 0; i < D; ++i) f[j][1 + i] = u[1 + i] * v[j] + (i == j ? p : 0.0);
+    f[j][D + 1] = (u[D + 1] + p) * v[j];
+  }
+}
+
+// viscous flux fv[j][alpha] from u and q[j][alpha] = d_j u_alpha
+template <int D>
+__device__ __forceinline__ void viscous_flux(const double *u, const double q[D][D + 2],
+                                             double gamma, double mu, double prandtl,
+                                             double fv[D][D + 2]) {
+  double rho, v[D], p;
+  primitives<D>(u, gamma, rho, v, p);
+  const double ir = 1.0 / rho;
+  double dv[D][D];  // dv[j][i] = d_j v_i
+#pragma unroll
+  for (int j = 0; j < D; ++j)
+#pragma unroll
+    for (int i = 0; i < D; ++i) dv[j][i] = (q[j][1 + i] - v[i] * q[j][0]) * ir;
+  double divv = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) divv += dv[k][k];
+  double v2 = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) v2 += v[i] * v[i];
+  const double kappa = mu * gamma / (prandtl * (gamma - 1.0));
+  const double por = p * ir;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    double vdm = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) vdm += v[i] * q[j][1 + i];
+    const double dp = (gamma - 1.0) * (q[j][D + 1] - vdm + 0.5 * v2 * q[j][0]);
+    const double dT = (dp - por * q[j][0]) * ir;
+    double e = kappa * dT;
+    fv[j][0] = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      double tau = mu * (dv[i][j] + dv[j][i]);
+      if (i == j) tau -= 2.0 / 3.0 * mu * divv;
+      fv[j][1 + i] = tau;
+      e += v[i] * tau;
+    }
+    fv[j][D + 1] = e;
+  }
+}
+
+// Rusanov flux (Appendix B) in direction n of the left side
+template <int D>
+__device__ __forceinline__ void rusanov(const double *uL, const double *uR, const double *n,
+                                        double gamma, double *F) {
+  double fL[D][D + 2], fR[D][D + 2], vL[D], vR[D], pL, pR;
+  inviscid_flux<D>(uL, gamma, fL, pL, vL);
+  inviscid_flux<D>(uR, gamma, fR, pR, vR);
+  double vn = 0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) vn += n[j] * (vL[j] + vR[j]);
+  const double s = sqrt(gamma * (pL + pR) / (uL[0] + uR[0])) + 0.5 * fabs(vn);
+#pragma unroll
+  for (int a = 0; a < D + 2; ++a) {
+    double nf = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) nf += n[j] * (fL[j][a] + fR[j][a]);
+    F[a] = 0.5 * nf + 0.5 * s * (uL[a] - uR[a]);
+  }
+}
+
+// ============================================================================
+// Point-wise kernels
+// ============================================================================
+template <int D, typename TQ>
+__global__ __launch_bounds__(256) void gradcoru_kernel(PointArgs a) {
+  constexpr int NV = D + 2;
+  const int64_t plane = (int64_t)a.nupts * a.ld;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= plane) return;
+  const int64_t r = t / a.ld, n = t - r * a.ld;
+  if (n >= a.nelem) return;
+  double S[D][D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) S[i][j] = a.smat[(i * D + j) * plane + t];
+  const double rj = a.rcpdjac[t];
+  TQ *q = (TQ *)a.q;
+  const int64_t rowstride = (int64_t)NV * a.ld, cstride = (int64_t)a.nupts * rowstride;
+  const int64_t base = r * rowstride + n;
+#pragma unroll
+  for (int al = 0; al < NV; ++al) {
+    double qt[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) qt[i] = (double)q[i * cstride + base + al * a.ld];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      double s = 0;
+#pragma unroll
+      for (int i = 0; i < D; ++i) s += S[i][j] * qt[i];
+      q[j * cstride + base + al * a.ld] = (TQ)(rj * s);
+    }
+  }
+}
+
+template <int D, int NS, typename TQ>
+__global__ __launch_bounds__(256) void tflux_kernel(PointArgs a) {
+  constexpr int NV = D + 2;
+  const int64_t plane = (int64_t)a.nupts * a.ld;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= plane) return;
+  const int64_t r = t / a.ld, n = t - r * a.ld;
+  if (n >= a.nelem) return;
+  const int64_t rowstride = (int64_t)NV * a.ld, cstride = (int64_t)a.nupts * rowstride;
+  const int64_t base = r * rowstride + n;
+  double u[NV];
+#pragma unroll
+  for (int al = 0; al < NV; ++al) u[al] = a.u[base + al * a.ld];
+  TQ *q = (TQ *)a.q;
+  double f[D][NV], p, v[D];
+  inviscid_flux<D>(u, a.gamma, f, p, v);
+  if (NS) {
+    double g[D][NV], fv[D][NV];
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+      for (int al = 0; al < NV; ++al) g[j][al] = (double)q[j * cstride + base + al * a.ld];
+    viscous_flux<D>(u, g, a.gamma, a.mu, a.prandtl, fv);
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+      for (int al = 0; al < NV; ++al) f[j][al] -= fv[j][al];
+  }
+  double S[D][D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) S[i][j] = a.smat[(i * D + j) * plane + t];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int al = 0; al < NV; ++al) {
+      double s = 0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) s += S[i][j] * f[j][al];
+      q[i * cstride + base + al * a.ld] = (TQ)s;
+    }
+}
+
+static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+template <typename TQ>
+static hipError_t gradcoru_t(const PointArgs &a, hipStream_t s) {
+  unsigned nb = blocks_for((int64_t)a.nupts * a.ld);
+  if (a.ndims == 2) gradcoru_kernel<2, TQ><<<nb, 256, 0, s>>>(a);
+  else gradcoru_kernel<3, TQ><<<nb, 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+hipError_t launch_gradcoru(const PointArgs &a, hipStream_t s) {
+  return a.q_f32 ? gradcoru_t<float>(a, s) : gradcoru_t<double>(a, s);
+}
+
+template <typename TQ>
+static hipError_t tflux_t(const PointArgs &a, int ns, hipStream_t s) {
+  unsigned nb = blocks_for((int64_t)a.nupts * a.ld);
+  if (a.ndims == 2) {
+    if (ns) tflux_kernel<2, 1, TQ><<<nb, 256, 0, s>>>(a);
+    else tflux_kernel<2, 0, TQ><<<nb, 256, 0, s>>>(a);
+  } else {
+    if (ns) tflux_kernel<3, 1, TQ><<<nb, 256, 0, s>>>(a);
+    else tflux_kernel<3, 0, TQ><<<nb, 256, 0, s>>>(a);
+  }
+  return hipGetLastError();
+}
+hipError_t launch_tflux(const PointArgs &a, int ns, hipStream_t s) {
+  return a.q_f32 ? tflux_t<float>(a, ns, s) : tflux_t<double>(a, ns, s);
+}
+
+// ============================================================================
+// Interface kernels
+// ============================================================================
+// Workgroup id remapped so that XCD x (which receives ids x, x+8, ...)
+// processes the contiguous range [x*per, (x+1)*per) of pair workgroups.
+__device__ __forceinline__ int64_t xcd_block(unsigned nreal) {
+  const unsigned per = gridDim.x / 8;
+  const unsigned b = blockIdx.x;
+  const unsigned m = (b % 8) * per + b / 8;
+  return m < nreal ? (int64_t)m : -1;
+}
+
+struct Side {
+  int64_t base, ld, qbase, qstride;
+};
+
+template <bool MULTI>
+__device__ __forceinline__ Side side_of(const PairArgs &a, const int32_t *blk, int64_t k,
+                                        bool q) {
+  Side s;
+  if (MULTI) {
+    const int b = blk[k];
+    s.base = a.blk_ufbase[b];
+    s.ld = a.blk_ld[b];
+    s.qbase = q ? a.blk_qfbase[b] : 0;
+    s.qstride = q ? a.blk_qstride[b] : 0;
+  } else {
+    s.base = 0; s.ld = a.ld0; s.qbase = 0; s.qstride = a.qstride0;
+  }
+  return s;
+}
+
+template <int D, bool MULTI, typename T>
+__global__ __launch_bounds__(256) void con_u_kernel(PairArgs a, unsigned nreal) {
+  constexpr int NV = D + 2;
+  const int64_t wg = xcd_block(nreal);
+  if (wg < 0) return;
+  const int64_t k = wg * 256 + threadIdx.x;
+  if (k >= a.npairs) return;
+  const Side L = side_of<MULTI>(a, a.lblk, k, true), R = side_of<MULTI>(a, a.rblk, k, true);
+  const int64_t iL = a.lidx[k], iR = a.ridx[k];
+  const T *uf = (const T *)a.uf;
+  T *cf = (T *)a.cf;
+  const double wl = 0.5 - a.beta, wr = 0.5 + a.beta;
+#pragma unroll
+  for (int al = 0; al < NV; ++al) {
+    const double c = wl * (double)uf[L.base + iL + al * L.ld] + wr * (double)uf[R.base + iR + al * R.ld];
+    cf[L.qbase + iL + al * L.ld] = (T)c;
+    cf[R.qbase + iR + al * R.ld] = (T)c;
+  }
+}
+
+template <int D, int NS, bool MULTI, typename T>
+__global__ __launch_bounds__(256) void comm_flux_kernel(PairArgs a, unsigned nreal) {
+  constexpr int NV = D + 2;
+  const int64_t wg = xcd_block(nreal);
+  if (wg < 0) return;
+  const int64_t k = wg * 256 + threadIdx.x;
+  if (k >= a.npairs) return;
+  const Side L = side_of<MULTI>(a, a.lblk, k, NS), R = side_of<MULTI>(a, a.rblk, k, NS);
+  const int64_t iL = a.lidx[k], iR = a.ridx[k];
+  T *uf = (T *)a.uf;
+  double uL[NV], uR[NV], n[D], F[NV];
+#pragma unroll
+  for (int al = 0; al < NV; ++al) {
+    uL[al] = (double)uf[L.base + iL + al * L.ld];
+    uR[al] = (double)uf[R.base + iR + al * R.ld];
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d) n[d] = a.nrm[d * a.npairs + k];
+  rusanov<D>(uL, uR, n, a.gamma, F);
+  if (NS) {
+    const T *qf = (const T *)a.qf;
+    double qL[D][NV], qR[D][NV], fvL[D][NV], fvR[D][NV];
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+      for (int al = 0; al < NV; ++al) {
+        qL[j][al] = (double)qf[L.qbase + j * L.qstride + iL + al * L.ld];
+        qR[j][al] = (double)qf[R.qbase + j * R.qstride + iR + al * R.ld];
+      }
+    viscous_flux<D>(uL, qL, a.gamma, a.mu, a.prandtl, fvL);
+    viscous_flux<D>(uR, qR, a.gamma, a.mu, a.prandtl, fvR);
+    const double wl = 0.5 + a.beta, wr = 0.5 - a.beta;
+#pragma unroll
+    for (int al = 0; al < NV; ++al) {
+      double fv = 0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) fv += n[j] * (wl * fvL[j][al] + wr * fvR[j][al]);
+      F[al] = F[al] - fv + a.tau * (uL[al] - uR[al]);
+    }
+  }
+  const double mL = a.magL[k], mR = a.magR[k];
+#pragma unroll
+  for (int al = 0; al < NV; ++al) {
+    uf[L.base + iL + al * L.ld] = (T)(mL * F[al]);
+    uf[R.base + iR + al * R.ld] = (T)(-mR * F[al]);
+  }
+}
+
+static void pair_grid(int64_t npairs, unsigned &grid, unsigned &nreal) {
+  nreal = (unsigned)((npairs + 255) / 256);
+  grid = (nreal + 7) / 8 * 8;
+}
+
+template <typename T>
+static hipError_t con_u_t(const PairArgs &a, hipStream_t s) {
+  unsigned grid, nreal;
+  pair_grid(a.npairs, grid, nreal);
+  const bool multi = a.lblk != nullptr;
+  if (a.ndims == 2) {
+    if (multi) con_u_kernel<2, true, T><<<grid, 256, 0, s>>>(a, nreal);
+    else con_u_kernel<2, false, T><<<grid, 256, 0, s>>>(a, nreal);
+  } else {
+    if (multi) con_u_kernel<3, true, T><<<grid, 256, 0, s>>>(a, nreal);
+    else con_u_kernel<3, false, T><<<grid, 256, 0, s>>>(a, nreal);
+  }
+  return hipGetLastError();
+}
+hipError_t launch_con_u(const PairArgs &a, hipStream_t s) {
+  if (a.npairs <= 0) return hipSuccess;
+  return a.uf_f32 ? con_u_t<float>(a, s) : con_u_t<double>(a, s);
+}
+
+template <typename T>
+static hipError_t comm_flux_t(const PairArgs &a, int ns, hipStream_t s) {
+  unsigned grid, nreal;
+  pair_grid(a.npairs, grid, nreal);
+  const bool multi = a.lblk != nullptr;
+#define FR_CF(D_, NS_)                                                                    \
+  if (multi) comm_flux_kernel<D_, NS_, true, T><<<grid, 256, 0, s>>>(a, nreal);           \
+  else comm_flux_kernel<D_, NS_, false, T><<<grid, 256, 0, s>>>(a, nreal);
+  if (a.ndims == 2) {
+    if (ns) { FR_CF(2, 1) } else { FR_CF(2, 0) }
+  } else {
+    if (ns) { FR_CF(3, 1) } else { FR_CF(3, 0) }
+  }
+#undef FR_CF
+  return hipGetLastError();
+}
+hipError_t launch_comm_flux(const PairArgs &a, int ns, hipStream_t s) {
+  if (a.npairs <= 0) return hipSuccess;
+  return a.uf_f32 ? comm_flux_t<float>(a, ns, s) : comm_flux_t<double>(a, ns, s);
+}
+
+// ============================================================================
+// Reductions (FP64, fixed summation order)
+// ============================================================================
+__global__ __launch_bounds__(256) void elem_integrals_kernel(int nvars, int ndims, int nupts,
+                                                             int64_t ld, int64_t nelem,
+                                                             const double *wdjac,
+                                                             const double *u, double *part) {
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n >= nelem) return;
+  double s[6] = {0, 0, 0, 0, 0, 0}, ke = 0;
+  for (int r = 0; r < nupts; ++r) {
+    const double w = wdjac[(int64_t)r * ld + n];
+    const double *ur = u + (int64_t)r * nvars * ld + n;
+    double m2 = 0;
+    for (int al = 0; al < nvars; ++al) {
+      const double v = ur[al * ld];
+      s[al] += w * v;
+      if (al >= 1 && al <= ndims) m2 += v * v;
+    }
+    ke += w * 0.5 * m2 / ur[0];
+  }
+  for (int al = 0; al < nvars; ++al) part[n * (nvars + 1) + al] = s[al];
+  part[n * (nvars + 1) + nvars] = ke;
+}
+
+hipError_t launch_elem_integrals(int nvars, int ndims, int nupts, int64_t ld, int64_t nelem,
+                                 const double *wdjac, const double *u, double *part,
+                                 hipStream_t s) {
+  elem_integrals_kernel<<<blocks_for(nelem), 256, 0, s>>>(nvars, ndims, nupts, ld, nelem, wdjac,
+                                                          u, part);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void problem_sums_kernel(int ncomp, const int64_t *pstart,
+                                                           const int64_t *plist,
+                                                           const double *part, double *out) {
+  __shared__ double red[256];
+  const int prob = blockIdx.x;
+  const int64_t b = pstart[prob], e = pstart[prob + 1];
+  for (int c = 0; c < ncomp; ++c) {
+    double s = 0;
+    for (int64_t i = b + threadIdx.x; i < e; i += 256) s += part[plist[i] * ncomp + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(int64_t)prob * ncomp + c] = red[0];
+    __syncthreads();
+  }
+}
+
+hipError_t launch_problem_sums(int ncomp, int nprob, const int64_t *pstart, const int64_t *plist,
+                               const double *part, double *out, hipStream_t s) {
+  problem_sums_kernel<<<nprob, 256, 0, s>>>(ncomp, pstart, plist, part, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void check_finite_kernel(const double *u, int64_t n,
+                                                           int32_t *flag) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    if (!isfinite(u[i])) flag[0] = 1;
+}
+
+hipError_t launch_check_finite(const double *u, int64_t n, int32_t *flag, hipStream_t s) {
+  unsigned nb = (unsigned)std::min<int64_t>(4096, (n + 255) / 256);
+  if (nb == 0) return hipSuccess;
+  check_finite_kernel<<<nb, 256, 0, s>>>(u, n, flag);
+  return hipGetLastError();
+}
+
+}  // namespace fr

@@ -1,0 +1,73 @@
+"""Shared helpers of the GPU parity tests: build the oracle and the library
+on the same seeded workload, evaluate both, compare."""
+import numpy as np
+
+from oracle import Discretisation
+from workloads import configs, fields, meshes
+from workloads.configs import Workload
+
+
+def solver_for(w, prec="fp64", check_finite=False):
+    import paper_1312_1638_amd as P
+    return P.Solver(w.mesh, system=w.system, gamma=w.gamma, mu=w.mu, prandtl=w.prandtl,
+                    ldg_beta=w.ldg_beta, ldg_tau=w.ldg_tau, prec=prec,
+                    check_finite=check_finite, nproblems=w.mesh.nproblems)
+
+
+def rel_l2(a, b):
+    """||a - b|| / ||b|| over every block and field (whole SoA vector)."""
+    num = sum(float(np.sum((x - y) ** 2)) for x, y in zip(a, b))
+    den = sum(float(np.sum(y ** 2)) for y in b)
+    return np.sqrt(num / den)
+
+
+def floor_tolerance(d, u, stated, unit_ratio=1.0, factor=4.0):
+    """Tolerance for du/dt of one case: the stated bar, or `factor` times
+    the FP64 rounding floor of the oracle (its relative L2 distance from a
+    long-double evaluation of the same formula) scaled by the ratio of unit
+    roundoffs of the precision under test.  Returns (tolerance, exact
+    reference, floor)."""
+    ref64 = d.rhs(u)
+    ext = d.extended().rhs([x.astype(np.longdouble) for x in u])
+    ext = [x.astype(np.float64) for x in ext]
+    floor = rel_l2(ref64, ext)
+    return max(stated, factor * floor * unit_ratio), ext, floor
+
+
+FP32_OVER_FP64 = 2.0 ** 29   # unit roundoff ratio 2^-24 / 2^-53
+
+
+def mixed(n=6, order=3, seed=0, system="euler", mu=0.02):
+    rng = np.random.default_rng(seed)
+    m = meshes.mixed_mesh(n, n, order=order, split=rng.random(n * n) < 0.5,
+                          diag=rng.integers(0, 2, n * n))
+    return Workload(f"mixed{n}_p{order}_{system}", m, system, mu=mu,
+                    ic=lambda b, x: fields.isentropic_vortex(x))
+
+
+def perturbed(d, u, seed=0, eps=1e-3):
+    rng = np.random.default_rng(seed)
+    return [x * (1 + eps * rng.standard_normal(x.shape)) for x in u]
+
+
+SMALL = {
+    "vortex7_p3": lambda: configs.vortex_quads(7, 3),
+    "vortex5_p1": lambda: configs.vortex_quads(5, 1),
+    "vortex4_p6": lambda: configs.vortex_quads(4, 6),
+    "mixed6_p3_euler": lambda: mixed(6, 3),
+    "mixed5_p4_euler": lambda: mixed(5, 4, seed=3),
+    "mixed5_p2_ns": lambda: mixed(5, 2, system="ns"),
+    "tgv5_p3": lambda: configs.taylor_green_hexes(5, 3),
+    "tgv3_p4": lambda: configs.taylor_green_hexes(3, 4),
+    "tgv4_p1": lambda: configs.taylor_green_hexes(4, 1),
+    "curved4_p4": lambda: configs.curved_freestream_hexes(4, 4),
+    "curved3_p2_ns": lambda: _curved_ns(),
+}
+
+
+def _curved_ns():
+    w = configs.curved_freestream_hexes(4, 2)
+    w.system = "ns"
+    w.mu = 0.01
+    w.prandtl = 0.71
+    return w

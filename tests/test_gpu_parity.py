@@ -1,0 +1,157 @@
+"""Parity of the HIP library (through the C ABI) with the FP64 oracle.
+
+Tolerances: relative L2 over the whole SoA vector (every block and field).
+u after RK4 steps: 1e-12 (FP64) and 1e-5 (FP32 operator path), the stated
+bars.  du/dt: the stated bar, unless the case is ill-conditioned -- du/dt is
+a small difference of flux derivatives much larger than itself (low-Mach
+energy equation, a perturbed free stream) -- in which case the bar is four
+times the case's measured FP64 rounding floor (the oracle's own distance
+from a long-double evaluation of the same formula), times 2^29 for FP32
+operands.  Errors are then measured against the long-double evaluation.
+"""
+import numpy as np
+import pytest
+
+import frcases as C
+from oracle import Discretisation
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+
+
+def _both(w, prec="fp64", perturb=True):
+    d = Discretisation(w)
+    u = d.initial_state(w)
+    if perturb:
+        u = C.perturbed(d, u)
+    s = C.solver_for(w, prec)
+    return d, s, u
+
+
+@pytest.mark.parametrize("name", sorted(C.SMALL))
+def test_rhs_small(name):
+    w = C.SMALL[name]()
+    d, s, u = _both(w)
+    ref = d.rhs(u)
+    got = s.unpack(s.rhs(s.pack(u)))
+    err = C.rel_l2(got, ref)
+    print(f"{name}: rel L2 {err:.3e}")
+    assert err < 1e-12
+
+
+@pytest.mark.parametrize("name", ["vortex7_p3", "mixed6_p3_euler", "tgv5_p3", "curved4_p4"])
+def test_rhs_small_fp32(name):
+    w = C.SMALL[name]()
+    d, s, u = _both(w, "fp32")
+    tol, ext, floor = C.floor_tolerance(d, u, 1e-5, C.FP32_OVER_FP64)
+    got = s.unpack(s.rhs(s.pack(u)))
+    err = C.rel_l2(got, ext)
+    print(f"{name} fp32: rel L2 {err:.3e} (fp64 floor {floor:.2e}, tol {tol:.2e})")
+    assert err < tol
+
+
+def test_rhs_alias_in_place():
+    w = C.SMALL["mixed5_p2_ns"]()
+    d, s, u = _both(w)
+    t = s.pack(u)
+    s.rhs(t, out=t)
+    assert C.rel_l2(s.unpack(t), d.rhs(u)) < 1e-12
+
+
+def test_padding_is_zero_and_inert():
+    import torch
+    w = configs.vortex_quads(7, 3)       # 49 elements -> ld 64
+    d, s, u = _both(w)
+    t = s.pack(u)
+    blk = s.blocks[0]
+    v = t.view(blk["nupts"], s.nvars, blk["ld"])
+    v[:, :, blk["nelem"]:] = float("nan")
+    out = s.rhs(t)
+    o = out.view(blk["nupts"], s.nvars, blk["ld"])
+    assert torch.all(o[:, :, blk["nelem"]:] == 0)
+    assert C.rel_l2(s.unpack(out), d.rhs(u)) < 1e-12
+
+
+def test_cfg1_rhs_and_100_steps():
+    """Vortex, 20x20 quads, p=3: du/dt and u after 100 RK4 steps, dt=1e-3."""
+    w = configs.CONFIGS["cfg1"]()
+    d, s, u = _both(w, perturb=False)
+    ref = d.rhs(u)
+    t = s.pack(u)
+    e_rhs = C.rel_l2(s.unpack(s.rhs(t)), ref)
+    s.step(t, w.dt, 40)
+    s.step(t, w.dt, 60)           # two replays of the captured step graph
+    ref_u = d.rk4(u, w.dt, 100)
+    e_u = C.rel_l2(s.unpack(t), ref_u)
+    print(f"cfg1: rhs {e_rhs:.3e}  u(100) {e_u:.3e}")
+    assert e_rhs < 1e-12 and e_u < 1e-12
+
+
+def test_cfg2_rhs_and_steps():
+    """Taylor-Green, 16^3 hexes, p=3, Navier-Stokes: du/dt and u after 2 RK4
+    steps (FP64), and the FP32 operator path."""
+    w = configs.CONFIGS["cfg2"]()
+    d, s, u = _both(w, perturb=False)
+    tol64, ext, floor = C.floor_tolerance(d, u, 1e-12)
+    tol32 = max(1e-5, 4 * floor * C.FP32_OVER_FP64)
+    t = s.pack(u)
+    e_rhs = C.rel_l2(s.unpack(s.rhs(t)), ext)
+    s.step(t, w.dt, 2)
+    ref_u = d.rk4(u, w.dt, 2)
+    e_u = C.rel_l2(s.unpack(t), ref_u)
+    s32 = C.solver_for(w, "fp32")
+    t32 = s32.pack(u)
+    e32 = C.rel_l2(s32.unpack(s32.rhs(t32)), ext)
+    s32.step(t32, w.dt, 2)
+    e32u = C.rel_l2(s32.unpack(t32), ref_u)
+    print(f"cfg2: fp64 floor {floor:.2e} | rhs {e_rhs:.3e} (tol {tol64:.1e}) u(2) {e_u:.3e} | "
+          f"fp32 rhs {e32:.3e} (tol {tol32:.1e}) u(2) {e32u:.3e}")
+    assert e_rhs < tol64 and e_u < 1e-12
+    assert e32 < tol32 and e32u < 1e-5
+
+
+def test_rk_graph_replay_matches_single_steps():
+    import torch
+    w = configs.vortex_quads(6, 2)
+    d, s, u = _both(w)
+    a = s.pack(u)
+    b = a.clone()
+    s.step(a, w.dt, 5)
+    for _ in range(5):
+        s.step(b, w.dt, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    # a new dt value is picked up by the captured graph
+    dt = torch.full((1,), 2e-3, dtype=torch.float64, device="cuda")
+    c = s.pack(u)
+    s.step(c, dt, 1)
+    ref = d.rk4(u, 2e-3, 1)
+    assert C.rel_l2(s.unpack(c), ref) < 1e-13
+
+
+def test_integrals_and_conservation():
+    w = C.SMALL["mixed5_p2_ns"]()
+    d, s, u = _both(w)
+    t = s.pack(u)
+    got = s.integrate(t).cpu().numpy()[0]
+    ref = sum(np.einsum("r,rn,ran->a", rf.W, g.detJ.T, ub) for rf, g, ub in zip(d.refs, d.geoms, u))
+    assert np.allclose(got[:-1], ref, rtol=1e-13, atol=0)
+    r = s.integrate(s.rhs(t)).cpu().numpy()[0]
+    scale = sum(np.einsum("r,rn,ran->a", rf.W, g.detJ.T, np.abs(rb))
+                for rf, g, rb in zip(d.refs, d.geoms, d.rhs(u)))
+    assert np.all(np.abs(r[:-1]) < 1e-13 * scale)
+
+
+def test_check_finite():
+    import paper_1312_1638_amd as P
+    w = configs.vortex_quads(4, 2)
+    d = Discretisation(w)
+    u = d.initial_state(w)
+    s = C.solver_for(w, check_finite=True)
+    t = s.pack(u)
+    s.step(t, w.dt, 1)
+    u[0][0, 0, 3] = np.nan
+    t = s.pack(u)
+    with pytest.raises(P.FRError) as e:
+        s.step(t, w.dt, 1)
+    assert e.value.status == P.binding.FR_ENONFINITE

@@ -1,0 +1,83 @@
+"""Step-by-step parity: the matrix-core GEMM on random data, and every
+intermediate array of the right-hand side (U^f, C^f, Q~, Q, Q^f, F~, D~)
+against the oracle's recorded intermediates."""
+import numpy as np
+import pytest
+
+import frcases as C
+from oracle import Discretisation
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("M,K1,K2,N", [(16, 4, 0, 16), (16, 16, 0, 1600), (96, 64, 0, 320),
+                                       (192, 96, 64, 640), (125, 150, 375, 96), (150, 125, 0, 48),
+                                       (7, 3, 5, 32), (375, 150, 125, 64)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gemm_random(M, K1, K2, N, prec):
+    import torch
+    import paper_1312_1638_amd as P
+    rng = np.random.default_rng(M + K1 + K2 + N)
+    A = rng.standard_normal((M, K1 + K2))
+    B1 = rng.standard_normal((K1, N))
+    B2 = rng.standard_normal((K2, N)) if K2 else None
+    dB1 = torch.from_numpy(B1).cuda()
+    dB2 = torch.from_numpy(B2).cuda() if K2 else None
+    got = P.binding.debug_gemm(A, dB1, dB2, prec).double().cpu().numpy()
+    B = B1 if not K2 else np.concatenate([B1, B2])
+    ref = A @ B
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"gemm {M}x{K1}+{K2}x{N} {prec}: max rel {err:.2e}")
+    assert err < (1e-14 if prec == "fp64" else 2e-6)
+
+
+def _split(s, flat, rows_per_block, nvars):
+    """Internal scratch array -> per-block [rows, alpha, n] (padding removed)."""
+    out, off = [], 0
+    for blk, rows in zip(s.blocks, rows_per_block):
+        ld, ne = blk["ld"], blk["nelem"]
+        a = flat[off:off + rows * nvars * ld].reshape(rows, nvars, ld)[:, :, :ne]
+        out.append(a)
+        off += rows * nvars * ld
+    return out
+
+
+@pytest.mark.parametrize("name", ["vortex7_p3", "mixed6_p3_euler", "tgv4_p1", "tgv3_p4",
+                                  "mixed5_p2_ns", "curved3_p2_ns"])
+def test_stage_parity(name):
+    import paper_1312_1638_amd as P
+    w = C.SMALL[name]()
+    d = Discretisation(w)
+    u = C.perturbed(d, d.initial_state(w))
+    rec = {}
+    ref_out = d.rhs(u, rec)
+    s = C.solver_for(w)
+    t = s.pack(u)
+    D, NV = d.ndims, d.nvars
+    nf = [r.nfpts for r in d.refs]
+    nu = [r.nupts for r in d.refs]
+    stages = [(1, "uf", nf, None)]
+    if w.system == "ns":
+        stages += [(2, "cf", nf, None), (3, "qt", [D * n for n in nu], D),
+                   (4, "q", [D * n for n in nu], D), (5, "qf", [D * n for n in nf], D)]
+    stages += [(6, "ft", [D * n for n in nu], D), (7, "df", nf, None)]
+    for st, key, rows, vec in stages:
+        flat = s.debug_stage(t, st).cpu().numpy()
+        if st == 2:
+            # C^f lives in the first N^f rows of each block's Q^f region
+            parts, off = [], 0
+            for blk, r in zip(s.blocks, nf):
+                ld, ne = blk["ld"], blk["nelem"]
+                parts.append(flat[off:off + r * NV * ld].reshape(r, NV, ld)[:, :, :ne])
+                off += D * r * NV * ld
+            got = parts
+        else:
+            got = _split(s, flat, rows, NV)
+        ref = rec[key]
+        if vec:
+            ref = [x.reshape((-1,) + x.shape[2:]) for x in ref]
+        err = C.rel_l2(got, ref)
+        print(f"{name} stage {st} ({key}): rel L2 {err:.3e}", flush=True)
+        assert err < 1e-12, (name, key, err)
+    err = C.rel_l2(s.unpack(s.rhs(t)), ref_out)
+    assert err < 1e-12
