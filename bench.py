@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""Throughput of the FR right-hand side on one MI355X.
+
+One step = one classical RK4 step of the whole hot path: four right-hand-side
+evaluations (interpolation to flux points, common solution, gradients,
+transformed fluxes, common interface fluxes, correction-function divergence),
+the fused FP64 register updates (one captured HIP graph), and the FP64
+conservation / kinetic-energy integrals.  Metric: right-hand-side
+DOF-updates per second, DOF = fields x solution points x elements (the
+paper's unit), four evaluations per step.
+
+Default workload: compressible Navier-Stokes Taylor-Green vortex, Re=1600,
+Ma=0.1, 16^3 periodic hexahedra, p=3 (64 solution points each), FP64.
+Synthetic, seeded inputs; the state is resident in HBM when timing starts.
+
+Prints one JSON line.  Extra keys: per-step kernel times, the FP32 operator
+path, the roofline of the dominant kernel and the CPU oracle baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    # name: (constructor, description)
+    "tgv16": ("taylor_green_hexes", dict(n=16, order=3), "ns"),
+    "tgv48": ("taylor_green_hexes", dict(n=48, order=3), "ns"),
+    "vortex20": ("vortex_quads", dict(n=20, order=3), "euler"),
+    "curved48": ("curved_freestream_hexes", dict(n=48, order=4), "euler"),
+    "curved24": ("curved_freestream_hexes", dict(n=24, order=4), "euler"),
+    "tgv24": ("taylor_green_hexes", dict(n=24, order=3), "ns"),
+}
+
+STEP_NAMES = {1: "interp_M0", 2: "common_solution", 3: "grad_M6_M4p", 4: "grad_transform",
+              5: "grad_interp_M5", 6: "transformed_flux", 7: "common_flux", 8: "div_M3_M1p"}
+
+PEAK_HBM = 8.0e12                                           # B/s
+PEAK_MFMA = {"fp64": 78.6e12, "fp32": 157.3e12}             # dense FLOP/s
+ROCPROF_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def step_model(s, step, ts):
+    """Algorithmic (bytes, flops) of one launch of RHS step `step` over all
+    blocks: each array read once and written once, operators cached."""
+    D, NV = s.ndims, s.nvars
+    byts = flops = 0.0
+    for blk, b in zip(s.blocks, s.mesh.blocks):
+        ne, nu = blk["nelem"], blk["nupts"]
+        nf = s.nfpts[b.etype, b.order]
+        cols = NV * ne
+        if step == 1:
+            flops += 2.0 * nf * nu * cols
+            byts += cols * (nu * 8 + nf * ts)
+        elif step == 3:
+            flops += 2.0 * D * nu * (nf + nu) * cols
+            byts += cols * (nf * ts + nu * 8 + D * nu * ts)
+        elif step == 4:
+            byts += 2.0 * D * nu * cols * ts + (D * D + 1) * nu * ne * 8
+        elif step == 5:
+            flops += 2.0 * D * nf * nu * cols
+            byts += D * cols * (nu + nf) * ts
+        elif step == 6:
+            byts += nu * ne * (NV * 8 + D * D * 8 + D * NV * ts)
+            if s.system == "ns":
+                byts += nu * ne * D * NV * ts
+        elif step == 8:
+            flops += 2.0 * nu * (nf + D * nu) * cols
+            byts += cols * (nf + D * nu) * ts + nu * ne * 8 + nu * cols * 8
+    npairs = s.npairs
+    if step == 2:
+        byts += npairs * (4 * NV * ts + 8)
+    elif step == 7:
+        byts += npairs * (4 * NV * ts + 8 + (D + 2) * 8)
+        if s.system == "ns":
+            byts += npairs * 2 * D * NV * ts
+    return byts, flops
+
+
+def make_solver(workload, prec, P, configs):
+    import numpy as np
+    w = getattr(configs, WORKLOADS[workload][0])(**WORKLOADS[workload][1])
+    s = P.Solver(w.mesh, system=w.system, gamma=w.gamma, mu=w.mu, prandtl=w.prandtl,
+                 ldg_beta=w.ldg_beta, ldg_tau=w.ldg_tau, prec=prec)
+    s.system = w.system
+    s.nfpts = {}
+    for b in w.mesh.blocks:
+        s.nfpts[b.etype, b.order] = P.reference_operator(b.etype, b.order, 6).shape[0]
+    s.npairs = P.check_mesh(w.mesh, w.system)
+    u0 = [np.ascontiguousarray(np.transpose(w.ic(b, s.solution_points(b)), (1, 2, 0)))
+          for b in range(len(w.mesh.blocks))]
+    return w, s, u0
+
+
+def time_steps(s, u, dt, steps, warmup, torch):
+    for _ in range(warmup):
+        s.step(u, dt, 1)
+        s.integrate(u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.step(u, dt, 1)
+        s.integrate(u)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def time_kernels(s, u, torch, nrep=50):
+    """Average launch duration of every RHS step, HIP events on the stream
+    the kernels are launched on (torch's current stream, passed to the
+    library)."""
+    out = {}
+    steps = [1, 6, 7, 8] if s.system == "euler" else [1, 2, 3, 4, 5, 6, 7, 8]
+    stream = torch.cuda.current_stream()
+    for st in steps:
+        s.bench_step(u, st, 2)                           # warm
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        # the bench hook first re-runs the steps before `st` once; time that
+        # alone and subtract it
+        e0.record(stream)
+        s.bench_step(u, st, 0)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        prep = e0.elapsed_time(e1)
+        e0.record(stream)
+        s.bench_step(u, st, nrep)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[st] = (e0.elapsed_time(e1) - prep) / nrep * 1e-3   # seconds per launch
+    return out
+
+
+def cpu_baseline(w, nsteps):
+    """The FP64 oracle on the host: nsteps RK4 steps of the same workload."""
+    import numpy as np
+    from oracle import Discretisation
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = 1
+    d = Discretisation(w)
+    u = d.initial_state(w)
+    t0 = time.perf_counter()
+    d.rk4(u, w.dt, nsteps)
+    el = time.perf_counter() - t0
+    dof = sum(r.nupts * g.nelem for r, g in zip(d.refs, d.geoms)) * d.nvars
+    return dict(value=4.0 * nsteps * dof / el, unit="RHS DOF-updates/s", cores=int(cores),
+                kind="oracle",
+                sample=f"{nsteps} RK4 steps ({4 * nsteps} right-hand sides) of the same "
+                       f"workload, numpy FP64 oracle, {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="tgv16", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-steps", type=int, default=2,
+                    help="RK4 steps of the oracle for the CPU baseline (0: skip)")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(halo exchange across GPUs is designed, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1312_1638_amd as P
+    from workloads import configs
+    assert torch.cuda.is_available(), "needs a HIP device"
+
+    w, s, u0 = make_solver(args.workload, "fp64", P, configs)
+    dof = sum(b["nupts"] * b["nelem"] for b in s.blocks) * s.nvars
+    npts = dof // s.nvars
+    u = s.pack(u0)
+    el = time_steps(s, u, w.dt, args.steps, args.warmup, torch)
+    ms = el / args.steps * 1e3
+    value = 4.0 * dof * args.steps / el
+
+    # per-kernel timing and the dominant kernel's roofline
+    u = s.pack(u0)
+    kt = time_kernels(s, u, torch)
+    dom = max(kt, key=kt.get)
+    byts, flops = step_model(s, dom, 8)
+    ai = flops / byts if byts else 0.0
+    ridge = PEAK_MFMA["fp64"] / PEAK_HBM
+    if flops and ai > ridge:
+        roof = dict(bound="mfma", achieved=flops / kt[dom] / 1e12, peak=PEAK_MFMA["fp64"] / 1e12,
+                    unit="TFLOP/s")
+    else:
+        roof = dict(bound="hbm", achieved=byts / kt[dom] / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["kernel"] = STEP_NAMES[dom]
+    roof["avg_launch_us"] = kt[dom] * 1e6
+    roof["algorithmic_bytes"] = byts
+    roof["algorithmic_flops"] = flops
+    roof["traffic"] = None
+    if os.path.exists(ROCPROF_TRAFFIC):
+        with open(ROCPROF_TRAFFIC) as fh:
+            tr = json.load(fh)
+        key = f"{args.workload}:{STEP_NAMES[dom]}"
+        if key in tr:
+            roof["traffic"] = tr[key]
+    kernels = {}
+    for st, t in sorted(kt.items()):
+        b_, f_ = step_model(s, st, 8)
+        kernels[STEP_NAMES[st]] = dict(us=round(t * 1e6, 2), GBps=round(b_ / t / 1e9, 1),
+                                       TFLOPs=round(f_ / t / 1e12, 2))
+
+    extra = {}
+    if not args.no_fp32:
+        w32, s32, _ = make_solver(args.workload, "fp32", P, configs)
+        u32 = s32.pack(u0)
+        el32 = time_steps(s32, u32, w.dt, args.steps, args.warmup, torch)
+        extra["fp32"] = dict(value=4.0 * dof * args.steps / el32,
+                             ms_per_step=el32 / args.steps * 1e3)
+        s32.close()
+
+    cpu = None
+    if args.cpu_steps > 0:
+        cpu = cpu_baseline(w, args.cpu_steps)
+
+    line = {
+        "metric": "RHS DOF-updates/s",
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "system": w.system, "elements": int(sum(b.nelem for b in w.mesh.blocks)),
+                   "order": int(w.mesh.blocks[0].order), "dof": int(dof), "solution_points": int(npts),
+                   "rhs_per_step": 4, "dt": w.dt, "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+        "points_per_s": value / s.nvars,
+    }
+    line.update(extra)
+    s.close()
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

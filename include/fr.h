@@ -177,6 +177,14 @@ fr_status fr_check_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *b
 fr_status fr_debug_stage(fr_ctx *ctx, const double *u, int32_t stage, double *out,
                          void *hip_stream);
 fr_status fr_debug_scratch_len(const fr_ctx *ctx, int32_t stage, int64_t *len);
+/* Benchmark hook: prepares the inputs of right-hand-side step `step` (as
+ * numbered for fr_debug_stage, plus 8: the final product with du/dt) for
+ * state u, then launches that step's kernels nrep times on hip_stream (step
+ * 7 works in place, so its repeats read the previous repeat's output; the
+ * values are meaningless, the work is the same).  The output of step 8 goes
+ * to internal scratch. */
+fr_status fr_bench_step(fr_ctx *ctx, const double *u, int32_t step, int32_t nrep,
+                        void *hip_stream);
 fr_status fr_debug_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, const double *A,
                         const void *B1, const void *B2, int64_t ldb, void *C, int64_t N,
                         void *hip_stream);

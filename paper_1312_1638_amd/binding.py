@@ -23,7 +23,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 EXPORTS = ("fr_setup_mesh", "fr_get_layout", "fr_get_solution_points", "fr_get_quadrature",
            "fr_rhs", "fr_rk_step", "fr_rhs_adjoint", "fr_rk_step_adjoint", "fr_integrate",
-           "fr_reference_operator", "fr_check_mesh", "fr_debug_stage", "fr_debug_scratch_len",
+           "fr_reference_operator", "fr_check_mesh", "fr_debug_stage", "fr_debug_scratch_len", "fr_bench_step",
            "fr_debug_gemm", "fr_last_error", "fr_destroy")
 
 
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH):
                           ctypes.POINTER(i64)],
         "fr_debug_stage": [vp, dp, i32, dp, vp],
         "fr_debug_scratch_len": [vp, i32, ctypes.POINTER(i64)],
+        "fr_bench_step": [vp, dp, i32, i32, vp],
         "fr_debug_gemm": [i32, i32, i32, i32, dp, dp, dp, i64, dp, i64, vp],
     }
     for name, args in sig.items():
@@ -299,6 +300,11 @@ class Solver:
         _check(self.L.fr_debug_stage(self.ctx, self._ptr(u), stage, out.data_ptr(),
                                      self._stream()), self.ctx)
         return out
+
+    def bench_step(self, u, step, nrep):
+        """Launch right-hand-side step `step` nrep times (after preparing its
+        inputs) on the current stream; for kernel timing."""
+        _check(self.L.fr_bench_step(self.ctx, self._ptr(u), step, nrep, self._stream()), self.ctx)
 
     def integrate(self, u):
         """[nproblems, nvars + 1]: integral of every field, then kinetic energy."""

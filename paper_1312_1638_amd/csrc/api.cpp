@@ -146,105 +146,103 @@ fr::GemmArgs gemm_args(const GemmOp &op) {
   return g;
 }
 
-// The right-hand-side chain.  epi: EPI_NEGDIV writes dudt; EPI_RK applies the
-// RK stage update `rk` with registers (u, acc, stage).
-void rhs_chain(fr_ctx *c, const double *u, double *dudt, int epi, const fr::RkCoef *rk,
-               const double *dt, hipStream_t s, int stop = 99) {
-  const int D = c->D, NV = c->NV;
-  const size_t ts = c->tsize;
-  const int f32 = c->prec != FR_FP64;
-  const int gprec = f32 ? fr::PREC_F32 : fr::PREC_F64;
-  // S1: U^f = M0 U^u
-  for (auto &b : c->blocks) {
-    fr::GemmArgs g = gemm_args(b.m0);
-    g.B1 = u + b.uoff; g.ldb1 = NV * b.ld; g.b1_f32 = 0;
-    g.B2 = nullptr; g.ldb2 = 0; g.b2_f32 = 0;
-    g.C = elem(c->d_uf, b.ufoff, ts); g.ldc = NV * b.ld; g.c_f32 = f32;
-    g.N = NV * b.ld;
-    hip_check(fr::launch_gemm(gprec, fr::EPI_STORE, g, 1, s), "gemm M0");
-  }
-  if (stop <= 1) return;
+fr::PairArgs pair_args(fr_ctx *c) {
   fr::PairArgs pa;
   std::memset(&pa, 0, sizeof(pa));
-  pa.ndims = D; pa.nvars = NV; pa.npairs = c->npairs;
+  const int NV = c->NV;
+  pa.ndims = c->D; pa.nvars = NV; pa.npairs = c->npairs;
   pa.lidx = c->d_lidx; pa.ridx = c->d_ridx;
   pa.lblk = c->blocks.size() > 1 ? c->d_lblk : nullptr;
   pa.rblk = c->blocks.size() > 1 ? c->d_rblk : nullptr;
   pa.nrm = c->d_nrm; pa.magL = c->d_magL; pa.magR = c->d_magR;
-  pa.uf = c->d_uf; pa.uf_f32 = f32; pa.cf = c->d_qf; pa.qf = c->d_qf;
+  pa.uf = c->d_uf; pa.uf_f32 = c->prec != FR_FP64; pa.cf = c->d_qf; pa.qf = c->d_qf;
   pa.blk_ufbase = c->d_blk_ufbase; pa.blk_qfbase = c->d_blk_qfbase;
   pa.blk_ld = c->d_blk_ld; pa.blk_qstride = c->d_blk_qstride;
   pa.ld0 = c->blocks[0].ld;
   pa.qstride0 = (int64_t)c->blocks[0].Nf * NV * c->blocks[0].ld;
   pa.gamma = c->cfg.gamma; pa.mu = c->cfg.mu; pa.prandtl = c->cfg.prandtl;
   pa.beta = c->cfg.ldg_beta; pa.tau = c->cfg.ldg_tau;
-  if (c->ns) {
-    // S2: common solution C^f (stored in the Q^f region)
-    hip_check(fr::launch_con_u(pa, s), "con_u");
-    if (stop <= 2) return;
-    for (auto &b : c->blocks) {
-      // S3: Q~ = M6 C^f + (M4 - M6 M0) U^u
-      fr::GemmArgs g = gemm_args(b.s3);
-      g.B1 = elem(c->d_qf, b.qfoff, ts); g.ldb1 = NV * b.ld; g.b1_f32 = f32;
-      g.B2 = u + b.uoff; g.ldb2 = NV * b.ld; g.b2_f32 = 0;
-      g.C = elem(c->d_ft, b.ftoff, ts); g.ldc = NV * b.ld; g.c_f32 = f32;
-      g.N = NV * b.ld;
-      hip_check(fr::launch_gemm(gprec, fr::EPI_STORE, g, 1, s), "gemm M6|M4'");
-      if (stop <= 3) continue;
-      // S4: Q = J^-T Q~ in place
-      fr::PointArgs p;
-      std::memset(&p, 0, sizeof(p));
-      p.ndims = D; p.nvars = NV; p.nupts = b.Nu; p.ld = b.ld; p.nelem = b.nelem;
-      p.smat = b.d_smat; p.rcpdjac = b.d_rcpdjac; p.u = u + b.uoff;
-      p.q = elem(c->d_ft, b.ftoff, ts); p.q_f32 = f32;
-      p.gamma = c->cfg.gamma; p.mu = c->cfg.mu; p.prandtl = c->cfg.prandtl;
-      hip_check(fr::launch_gradcoru(p, s), "gradcoru");
-      if (stop <= 4) continue;
-      // S5: Q^f = blockdiag(M0) Q (one batch per spatial component)
-      fr::GemmArgs g5 = gemm_args(b.m0);
-      g5.B1 = elem(c->d_ft, b.ftoff, ts); g5.ldb1 = NV * b.ld; g5.b1_f32 = f32;
-      g5.b2_f32 = f32;
-      g5.C = elem(c->d_qf, b.qfoff, ts); g5.ldc = NV * b.ld; g5.c_f32 = f32;
-      g5.N = NV * b.ld;
-      g5.sB1 = (int64_t)b.Nu * NV * b.ld;
-      g5.sC = (int64_t)b.Nf * NV * b.ld;
-      hip_check(fr::launch_gemm(gprec, fr::EPI_STORE, g5, D, s), "gemm M5");
-      if (stop <= 5) continue;
-      // S6: transformed flux, overwriting Q
-      hip_check(fr::launch_tflux(p, 1, s), "tflux NS");
-    }
-  } else {
-    for (auto &b : c->blocks) {
-      fr::PointArgs p;
-      std::memset(&p, 0, sizeof(p));
-      p.ndims = D; p.nvars = NV; p.nupts = b.Nu; p.ld = b.ld; p.nelem = b.nelem;
-      p.smat = b.d_smat; p.rcpdjac = b.d_rcpdjac; p.u = u + b.uoff;
-      p.q = elem(c->d_ft, b.ftoff, ts); p.q_f32 = f32;
-      p.gamma = c->cfg.gamma;
-      hip_check(fr::launch_tflux(p, 0, s), "tflux Euler");
-    }
-  }
-  if (stop <= 6) return;
-  // S7: common normal flux, in place over U^f
-  hip_check(fr::launch_comm_flux(pa, c->ns, s), "comm_flux");
-  if (stop <= 7) return;
-  // S8 + S9 (+ S10): R = -J^-1 (M3 D~ + (M1 - M3 M2) F~)
+  return pa;
+}
+
+fr::PointArgs point_args(fr_ctx *c, const BlockRT &b, const double *u) {
+  fr::PointArgs p;
+  std::memset(&p, 0, sizeof(p));
+  p.ndims = c->D; p.nvars = c->NV; p.nupts = b.Nu; p.ld = b.ld; p.nelem = b.nelem;
+  p.smat = b.d_smat; p.rcpdjac = b.d_rcpdjac; p.u = u + b.uoff;
+  p.q = elem(c->d_ft, b.ftoff, c->tsize); p.q_f32 = c->prec != FR_FP64;
+  p.gamma = c->cfg.gamma; p.mu = c->cfg.mu; p.prandtl = c->cfg.prandtl;
+  return p;
+}
+
+// Steps of the right-hand side (every block):
+//   1  U^f = M0 U                         (S1, GEMM)
+//   2  C^f = common solution               (S2, pairs; Navier-Stokes)
+//   3  Q~ = M6 C^f + (M4 - M6 M0) U        (S3, GEMM; Navier-Stokes)
+//   4  Q = J^-T Q~ in place                (S4; Navier-Stokes)
+//   5  Q^f = blockdiag(M0) Q               (S5, GEMM; Navier-Stokes)
+//   6  F~ = J J^-1 f(U, Q)                 (S6; over Q's storage)
+//   7  D~ = common normal flux, over U^f   (S7, pairs)
+//   8  R = -J^-1 (M3 D~ + (M1 - M3 M2) F~) (S8 + S9, GEMM; + S10 with EPI_RK)
+void run_step(fr_ctx *c, int st, const double *u, double *dudt, int epi, const fr::RkCoef *rk,
+              const double *dt, hipStream_t s) {
+  const int D = c->D, NV = c->NV;
+  const size_t ts = c->tsize;
+  const int f32 = c->prec != FR_FP64;
+  const int gprec = f32 ? fr::PREC_F32 : fr::PREC_F64;
+  if (!c->ns && st >= 2 && st <= 5) return;
+  if (st == 2) { hip_check(fr::launch_con_u(pair_args(c), s), "con_u"); return; }
+  if (st == 7) { hip_check(fr::launch_comm_flux(pair_args(c), c->ns, s), "comm_flux"); return; }
   for (auto &b : c->blocks) {
-    fr::GemmArgs g = gemm_args(b.s8);
-    g.B1 = elem(c->d_uf, b.ufoff, ts); g.ldb1 = NV * b.ld; g.b1_f32 = f32;
-    g.B2 = elem(c->d_ft, b.ftoff, ts); g.ldb2 = NV * b.ld; g.b2_f32 = f32;
-    g.ldc = NV * b.ld; g.N = NV * b.ld;
-    g.rcpdjac = b.d_rcpdjac; g.ld = b.ld; g.nelem = b.nelem;
-    if (epi == fr::EPI_NEGDIV) {
+    const int64_t N = NV * b.ld;
+    if (st == 1) {
+      fr::GemmArgs g = gemm_args(b.m0);
+      g.B1 = u + b.uoff; g.ldb1 = N; g.b1_f32 = 0;
+      g.C = elem(c->d_uf, b.ufoff, ts); g.ldc = N; g.c_f32 = f32;
+      g.N = N;
+      hip_check(fr::launch_gemm(gprec, fr::EPI_STORE, g, 1, s), "gemm M0");
+    } else if (st == 3) {
+      fr::GemmArgs g = gemm_args(b.s3);
+      g.B1 = elem(c->d_qf, b.qfoff, ts); g.ldb1 = N; g.b1_f32 = f32;
+      g.B2 = u + b.uoff; g.ldb2 = N; g.b2_f32 = 0;
+      g.C = elem(c->d_ft, b.ftoff, ts); g.ldc = N; g.c_f32 = f32;
+      g.N = N;
+      hip_check(fr::launch_gemm(gprec, fr::EPI_STORE, g, 1, s), "gemm M6|M4'");
+    } else if (st == 4) {
+      hip_check(fr::launch_gradcoru(point_args(c, b, u), s), "gradcoru");
+    } else if (st == 5) {
+      fr::GemmArgs g = gemm_args(b.m0);
+      g.B1 = elem(c->d_ft, b.ftoff, ts); g.ldb1 = N; g.b1_f32 = f32; g.b2_f32 = f32;
+      g.C = elem(c->d_qf, b.qfoff, ts); g.ldc = N; g.c_f32 = f32;
+      g.N = N;
+      g.sB1 = (int64_t)b.Nu * N;
+      g.sC = (int64_t)b.Nf * N;
+      hip_check(fr::launch_gemm(gprec, fr::EPI_STORE, g, D, s), "gemm M5");
+    } else if (st == 6) {
+      hip_check(fr::launch_tflux(point_args(c, b, u), c->ns, s), "tflux");
+    } else if (st == 8) {
+      fr::GemmArgs g = gemm_args(b.s8);
+      g.B1 = elem(c->d_uf, b.ufoff, ts); g.ldb1 = N; g.b1_f32 = f32;
+      g.B2 = elem(c->d_ft, b.ftoff, ts); g.ldb2 = N; g.b2_f32 = f32;
+      g.ldc = N; g.N = N;
+      g.rcpdjac = b.d_rcpdjac; g.ld = b.ld; g.nelem = b.nelem;
       g.out = dudt + b.uoff;
-    } else {
-      g.out = dudt + b.uoff;  // the caller's u register
-      g.acc = c->d_acc + b.uoff;
-      g.stage = c->d_stage + b.uoff;
-      g.dt = dt; g.prob = b.d_prob; g.rk = *rk;
+      if (epi == fr::EPI_RK) {
+        g.acc = c->d_acc + b.uoff;
+        g.stage = c->d_stage + b.uoff;
+        g.dt = dt; g.prob = b.d_prob; g.rk = *rk;
+      }
+      hip_check(fr::launch_gemm(gprec, epi, g, 1, s), "gemm M3|M1'");
     }
-    hip_check(fr::launch_gemm(gprec, epi, g, 1, s), "gemm M3|M1'");
   }
+}
+
+// The right-hand-side chain, steps 1..min(stop, 8).  epi: EPI_NEGDIV writes
+// dudt; EPI_RK applies the RK stage update `rk` with registers (dudt = u,
+// acc, stage).
+void rhs_chain(fr_ctx *c, const double *u, double *dudt, int epi, const fr::RkCoef *rk,
+               const double *dt, hipStream_t s, int stop = 8) {
+  for (int st = 1; st <= stop && st <= 8; ++st) run_step(c, st, u, dudt, epi, rk, dt, s);
 }
 
 // One classical RK4 step of u in place: k_s = R(stage_s), with
@@ -617,6 +615,23 @@ fr_status fr_debug_stage(fr_ctx *c, const double *u, int32_t stage, double *out,
     else if (stage == 5) { src = c->d_qf; n = c->qf_len; }
     else { src = c->d_ft; n = c->ft_len; }
     hip_check(hipMemcpyAsync(out, src, n * sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
+  } catch (const Fail &f) {
+    return fail(c, f.st, f.msg);
+  }
+  return FR_OK;
+}
+
+fr_status fr_bench_step(fr_ctx *c, const double *u, int32_t step, int32_t nrep,
+                        void *hip_stream) {
+  if (!c || !u || step < 1 || step > 8 || nrep < 0) return FR_EINVAL;
+  if (!c->ns && step >= 2 && step <= 5) return fail(c, FR_EINVAL, "no such step for Euler");
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    rhs_chain(c, u, nullptr, fr::EPI_NEGDIV, nullptr, nullptr, s, step - 1);
+    // step 7 works in place, so its repeats read the previous repeat's
+    // output: the same arithmetic and traffic on other values (timing only)
+    for (int i = 0; i < nrep; ++i)
+      run_step(c, step, u, c->d_acc, fr::EPI_NEGDIV, nullptr, nullptr, s);
   } catch (const Fail &f) {
     return fail(c, f.st, f.msg);
   }

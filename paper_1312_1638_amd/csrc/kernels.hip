@@ -57,11 +57,20 @@ __device__ __forceinline__ T load_b(const TB *__restrict__ B, int64_t ldb, int K
   return k < K ? (T)B[(int64_t)k * ldb + col] : (T)0;
 }
 
+// k-steps per prefetch chunk: enough MFMAs per chunk (KC * MBW of them) to
+// cover the latency of the next chunk's loads, within the register budget.
+template <int MBW> struct Chunk {
+  static constexpr int KC = MBW >= 12 ? 2 : (MBW >= 6 ? 4 : (MBW >= 3 ? 6 : 8));
+};
+
 // Fragment layout of A: [wave row group rg][k-step][row block m][64 lanes],
 // lane l of fragment (m, ks) holding A[16 m' + l % 16][4 ks + l / 16].
+// The k loop runs in chunks of KC k-steps whose A and B fragments are
+// loaded one chunk ahead (double-buffered in registers).
 template <typename T, int MBW, int EPI, typename TB1, typename TB2, typename TC>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   typedef typename Mma<T>::acc_t acc_t;
+  constexpr int KC = Chunk<MBW>::KC;
   const int lane = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int rg = (int)(gw % g.WM);
@@ -69,7 +78,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   if (n0 >= g.N) return;
   const int col = lane & 15, kq = lane >> 4;
   const int64_t bcol = n0 + col;
-  const int KS = g.KS1 + g.KS2;
+  const int KS1 = g.KS1, KS = g.KS1 + g.KS2;
   const TB1 *__restrict__ B1 = (const TB1 *)g.B1 + (int64_t)blockIdx.y * g.sB1;
   const TB2 *__restrict__ B2 = (const TB2 *)g.B2;
   const T *__restrict__ A = (const T *)g.Apack + (int64_t)rg * KS * MBW * 64 + lane;
@@ -78,20 +87,32 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 #pragma unroll
   for (int m = 0; m < MBW; ++m) acc[m] = acc_t{0, 0, 0, 0};
 
-  T bcur = g.KS1 ? load_b<T>(B1, g.ldb1, g.K1, 0, kq, bcol) : load_b<T>(B2, g.ldb2, g.K2, 0, kq, bcol);
-  for (int ks = 0; ks < KS; ++ks) {
-    T bnext = 0;
-    const int kn = ks + 1;
-    if (kn < g.KS1)
-      bnext = load_b<T>(B1, g.ldb1, g.K1, kn, kq, bcol);
-    else if (kn < KS)
-      bnext = load_b<T>(B2, g.ldb2, g.K2, kn - g.KS1, kq, bcol);
-    T a[MBW];
+  T b0[KC], b1[KC], a0[KC][MBW], a1[KC][MBW];
+  auto load = [&](int c, T (&b)[KC], T (&a)[KC][MBW]) {
 #pragma unroll
-    for (int m = 0; m < MBW; ++m) a[m] = A[((int64_t)ks * MBW + m) * 64];
+    for (int kk = 0; kk < KC; ++kk) {
+      const int ks = c * KC + kk;
+      if (ks < KS1) b[kk] = load_b<T>(B1, g.ldb1, g.K1, ks, kq, bcol);
+      else if (ks < KS) b[kk] = load_b<T>(B2, g.ldb2, g.K2, ks - KS1, kq, bcol);
+      else b[kk] = 0;
 #pragma unroll
-    for (int m = 0; m < MBW; ++m) acc[m] = Mma<T>::run(a[m], bcur, acc[m]);
-    bcur = bnext;
+      for (int m = 0; m < MBW; ++m) a[kk][m] = ks < KS ? A[((int64_t)ks * MBW + m) * 64] : (T)0;
+    }
+  };
+  auto compute = [&](const T (&b)[KC], const T (&a)[KC][MBW]) {
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk)
+#pragma unroll
+      for (int m = 0; m < MBW; ++m) acc[m] = Mma<T>::run(a[kk][m], b[kk], acc[m]);
+  };
+  const int nch = (KS + KC - 1) / KC;
+  load(0, b0, a0);
+  for (int c = 0; c < nch; c += 2) {
+    if (c + 1 < nch) load(c + 1, b1, a1);
+    compute(b0, a0);
+    if (c + 1 >= nch) break;
+    if (c + 2 < nch) load(c + 2, b0, a0);
+    compute(b1, a1);
   }
 
   // epilogue: lane holds rows 16 m + Mma<T>::row(kq, r), column n0 + col
@@ -163,7 +184,7 @@ void gemm_plan(int M, int64_t N, int prec, int *MBW, int *WM) {
   const int maxw = 12;
   const int64_t ntile = (N + 15) / 16;
   int wm = (MB + maxw - 1) / maxw;
-  while (wm < MB && wm * ntile < 4096) ++wm;
+  while (wm < MB && wm * ntile < 2048) ++wm;
   int mbw = (MB + wm - 1) / wm;
   wm = (MB + mbw - 1) / mbw;
   *MBW = mbw;
@@ -579,54 +600,67 @@ hipError_t launch_comm_flux(const PairArgs &a, int ns, hipStream_t s) {
 // ============================================================================
 // Reductions (FP64, fixed summation order)
 // ============================================================================
+// Per-element integrals: a workgroup takes 64 elements; its 4 waves split
+// the solution points (rho = wave, wave + 4, ...) and combine in LDS in a
+// fixed order.  part[n][c]: c < nvars the field integrals, c = nvars the
+// kinetic energy.
 __global__ __launch_bounds__(256) void elem_integrals_kernel(int nvars, int ndims, int nupts,
                                                              int64_t ld, int64_t nelem,
                                                              const double *wdjac,
                                                              const double *u, double *part) {
-  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (n >= nelem) return;
-  double s[6] = {0, 0, 0, 0, 0, 0}, ke = 0;
-  for (int r = 0; r < nupts; ++r) {
-    const double w = wdjac[(int64_t)r * ld + n];
-    const double *ur = u + (int64_t)r * nvars * ld + n;
-    double m2 = 0;
-    for (int al = 0; al < nvars; ++al) {
-      const double v = ur[al * ld];
-      s[al] += w * v;
-      if (al >= 1 && al <= ndims) m2 += v * v;
+  __shared__ double red[4][6][64];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t n = (int64_t)blockIdx.x * 64 + tx;
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  if (n < nelem) {
+    for (int r = ty; r < nupts; r += 4) {
+      const double w = wdjac[(int64_t)r * ld + n];
+      const double *ur = u + (int64_t)r * nvars * ld + n;
+      double m2 = 0;
+      for (int al = 0; al < nvars; ++al) {
+        const double v = ur[al * ld];
+        s[al] += w * v;
+        if (al >= 1 && al <= ndims) m2 += v * v;
+      }
+      s[nvars] += w * 0.5 * m2 / ur[0];
     }
-    ke += w * 0.5 * m2 / ur[0];
   }
-  for (int al = 0; al < nvars; ++al) part[n * (nvars + 1) + al] = s[al];
-  part[n * (nvars + 1) + nvars] = ke;
+  for (int c = 0; c <= nvars; ++c) red[ty][c][tx] = s[c];
+  __syncthreads();
+  if (ty == 0 && n < nelem)
+    for (int c = 0; c <= nvars; ++c)
+      part[n * (nvars + 1) + c] = (red[0][c][tx] + red[1][c][tx]) + (red[2][c][tx] + red[3][c][tx]);
 }
 
 hipError_t launch_elem_integrals(int nvars, int ndims, int nupts, int64_t ld, int64_t nelem,
                                  const double *wdjac, const double *u, double *part,
                                  hipStream_t s) {
-  elem_integrals_kernel<<<blocks_for(nelem), 256, 0, s>>>(nvars, ndims, nupts, ld, nelem, wdjac,
-                                                          u, part);
+  elem_integrals_kernel<<<(unsigned)((nelem + 63) / 64), 256, 0, s>>>(nvars, ndims, nupts, ld,
+                                                                      nelem, wdjac, u, part);
   return hipGetLastError();
 }
 
+// One workgroup per problem: strided partial sums of every component at
+// once, then a fixed-shape tree in LDS (bitwise reproducible).
 __global__ __launch_bounds__(256) void problem_sums_kernel(int ncomp, const int64_t *pstart,
                                                            const int64_t *plist,
                                                            const double *part, double *out) {
-  __shared__ double red[256];
+  __shared__ double red[6][256];
   const int prob = blockIdx.x;
   const int64_t b = pstart[prob], e = pstart[prob + 1];
-  for (int c = 0; c < ncomp; ++c) {
-    double s = 0;
-    for (int64_t i = b + threadIdx.x; i < e; i += 256) s += part[plist[i] * ncomp + c];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) out[(int64_t)prob * ncomp + c] = red[0];
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t i = b + threadIdx.x; i < e; i += 256) {
+    const double *p = part + plist[i] * ncomp;
+    for (int c = 0; c < ncomp; ++c) s[c] += p[c];
+  }
+  for (int c = 0; c < ncomp; ++c) red[c][threadIdx.x] = s[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int c = 0; c < ncomp; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
     __syncthreads();
   }
+  if ((int)threadIdx.x < ncomp) out[(int64_t)prob * ncomp + threadIdx.x] = red[threadIdx.x][0];
 }
 
 hipError_t launch_problem_sums(int ncomp, int nprob, const int64_t *pstart, const int64_t *plist,
