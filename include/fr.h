@@ -68,7 +68,8 @@ typedef struct {
   double ldg_beta;        /* LDG common-solution bias beta (Navier-Stokes)     */
   double ldg_tau;         /* LDG penalty tau (Navier-Stokes)                   */
   int32_t nproblems;      /* independent problems in the mesh (>= 1)           */
-  int32_t reserved;
+  int32_t autotune;       /* 1: time every GEMM tile plan at set-up, keep the
+                             fastest (memoised per shape in the process)       */
 } fr_config;
 
 typedef struct {          /* one element block: one type, order, geometry order */
@@ -173,7 +174,8 @@ fr_status fr_check_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *b
  * doubles.  fr_debug_gemm computes C = A [B1; B2] with the library's matrix
  * core kernel: A HOST row-major M x (K1 + K2); B1 (K1 rows), B2 (K2 rows)
  * DEVICE float64 with row stride ldb; C DEVICE (float64 for FP64, float32
- * for FP32) M x N, row stride N; N a multiple of 16.  Synchronous. */
+ * for FP32) M x N, row stride N; N a multiple of 16.  (mbw, nc, wm) forces a
+ * tile plan (mbw = 0: the default plan).  Synchronous. */
 fr_status fr_debug_stage(fr_ctx *ctx, const double *u, int32_t stage, double *out,
                          void *hip_stream);
 fr_status fr_debug_scratch_len(const fr_ctx *ctx, int32_t stage, int64_t *len);
@@ -187,7 +189,23 @@ fr_status fr_bench_step(fr_ctx *ctx, const double *u, int32_t step, int32_t nrep
                         void *hip_stream);
 fr_status fr_debug_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, const double *A,
                         const void *B1, const void *B2, int64_t ldb, void *C, int64_t N,
-                        void *hip_stream);
+                        int32_t mbw, int32_t nc, int32_t wm, void *hip_stream);
+
+/* Performance diagnostics.
+ * fr_measure_ceiling: kind 0 = HBM triad bandwidth (GB/s, 3 x 2 GiB arrays),
+ * 1 = FP64 matrix-core rate, 2 = FP32 matrix-core rate (TFLOP/s,
+ * register-resident v_mfma loops).  Synchronous.
+ * fr_bench_gemm: average time of one launch of the operator GEMM kernel for
+ * an M x (K1 + K2) operator on N columns (batch copies of panel 1) with tile
+ * plan (mbw, nc, wm) (mbw = 0: default plan); operands are internal.
+ * fr_get_gemm_plan: the tile plan a context uses for right-hand-side step
+ * 1, 3, 5 or 8 of `block`. */
+fr_status fr_measure_ceiling(int32_t kind, double *value, void *hip_stream);
+fr_status fr_bench_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, int64_t N,
+                        int32_t mbw, int32_t nc, int32_t wm, int32_t batch, int32_t nrep,
+                        float *ms_per_launch, void *hip_stream);
+fr_status fr_get_gemm_plan(const fr_ctx *ctx, int32_t block, int32_t step, int32_t *mbw,
+                           int32_t *nc, int32_t *wm);
 
 /* Message of the last failure on ctx (ctx NULL: last failed setup on this
  * thread).  Never NULL. */

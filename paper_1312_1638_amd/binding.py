@@ -24,7 +24,8 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 EXPORTS = ("fr_setup_mesh", "fr_get_layout", "fr_get_solution_points", "fr_get_quadrature",
            "fr_rhs", "fr_rk_step", "fr_rhs_adjoint", "fr_rk_step_adjoint", "fr_integrate",
            "fr_reference_operator", "fr_check_mesh", "fr_debug_stage", "fr_debug_scratch_len", "fr_bench_step",
-           "fr_debug_gemm", "fr_last_error", "fr_destroy")
+           "fr_debug_gemm", "fr_measure_ceiling", "fr_bench_gemm", "fr_get_gemm_plan",
+           "fr_last_error", "fr_destroy")
 
 
 class FRError(RuntimeError):
@@ -38,7 +39,7 @@ class FrConfig(ctypes.Structure):
                 ("check_finite", ctypes.c_int32), ("gamma", ctypes.c_double),
                 ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
                 ("ldg_beta", ctypes.c_double), ("ldg_tau", ctypes.c_double),
-                ("nproblems", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("nproblems", ctypes.c_int32), ("autotune", ctypes.c_int32)]
 
 
 class FrBlock(ctypes.Structure):
@@ -84,7 +85,12 @@ def load_library(path: str = LIB_PATH):
         "fr_debug_stage": [vp, dp, i32, dp, vp],
         "fr_debug_scratch_len": [vp, i32, ctypes.POINTER(i64)],
         "fr_bench_step": [vp, dp, i32, i32, vp],
-        "fr_debug_gemm": [i32, i32, i32, i32, dp, dp, dp, i64, dp, i64, vp],
+        "fr_measure_ceiling": [i32, ctypes.POINTER(ctypes.c_double), vp],
+        "fr_bench_gemm": [i32, i32, i32, i32, i64, i32, i32, i32, i32, i32,
+                          ctypes.POINTER(ctypes.c_float), vp],
+        "fr_get_gemm_plan": [vp, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                             ctypes.POINTER(i32)],
+        "fr_debug_gemm": [i32, i32, i32, i32, dp, dp, dp, i64, dp, i64, i32, i32, i32, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -116,7 +122,7 @@ def reference_operator(etype: str, order: int, which: int) -> np.ndarray:
     return out
 
 
-def debug_gemm(A, B1, B2=None, prec="fp64"):
+def debug_gemm(A, B1, B2=None, prec="fp64", plan=(0, 0, 0)):
     """C = A [B1; B2] on the matrix cores (A host numpy, B device float64)."""
     import torch
     L = load_library()
@@ -129,13 +135,33 @@ def debug_gemm(A, B1, B2=None, prec="fp64"):
                     device="cuda")
     _check(L.fr_debug_gemm(PREC[prec], M, K1, K2, A.ctypes.data, B1.data_ptr(),
                            None if B2 is None else B2.data_ptr(), B1.stride(0), C.data_ptr(),
-                           N, torch.cuda.current_stream().cuda_stream))
+                           N, plan[0], plan[1], plan[2], torch.cuda.current_stream().cuda_stream))
     return C
 
 
-def _config(ndims, system, prec, gamma, mu, prandtl, beta, tau, check_finite, nproblems):
+def measure_ceiling(kind):
+    """0: HBM triad GB/s, 1: FP64 MFMA TFLOP/s, 2: FP32 MFMA TFLOP/s (measured)."""
+    import torch
+    v = ctypes.c_double()
+    _check(load_library().fr_measure_ceiling(kind, ctypes.byref(v),
+                                             torch.cuda.current_stream().cuda_stream))
+    return v.value
+
+
+def bench_gemm(prec, M, K1, K2, N, plan=(0, 0, 0), batch=1, nrep=20):
+    """Milliseconds per launch of the operator GEMM kernel."""
+    import torch
+    ms = ctypes.c_float()
+    _check(load_library().fr_bench_gemm(PREC[prec], M, K1, K2, N, plan[0], plan[1], plan[2],
+                                        batch, nrep, ctypes.byref(ms),
+                                        torch.cuda.current_stream().cuda_stream))
+    return ms.value
+
+
+def _config(ndims, system, prec, gamma, mu, prandtl, beta, tau, check_finite, nproblems,
+            autotune=False):
     return FrConfig(ndims, SYSTEM[system], PREC[prec], int(check_finite), gamma, mu, prandtl,
-                    beta, tau, nproblems, 0)
+                    beta, tau, nproblems, int(autotune))
 
 
 def _marshal_mesh(mesh):
@@ -181,7 +207,7 @@ class Solver:
 
     def __init__(self, mesh, system="euler", gamma=1.4, mu=0.0, prandtl=0.72,
                  ldg_beta=0.5, ldg_tau=0.1, prec="fp64", check_finite=False,
-                 nproblems=None):
+                 nproblems=None, autotune=True):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the FR library needs a HIP device")
@@ -193,7 +219,7 @@ class Solver:
         self.nproblems = nproblems or getattr(mesh, "nproblems", 1)
         self.prec = prec
         cfg = _config(mesh.ndims, system, prec, gamma, mu, prandtl, ldg_beta, ldg_tau,
-                      check_finite, self.nproblems)
+                      check_finite, self.nproblems, autotune)
         arr, pairs, keep = _marshal_mesh(mesh)
         ctx = ctypes.c_void_p()
         stream = torch.cuda.current_stream().cuda_stream
@@ -305,6 +331,12 @@ class Solver:
         """Launch right-hand-side step `step` nrep times (after preparing its
         inputs) on the current stream; for kernel timing."""
         _check(self.L.fr_bench_step(self.ctx, self._ptr(u), step, nrep, self._stream()), self.ctx)
+
+    def gemm_plan(self, block, step):
+        m, n, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(self.L.fr_get_gemm_plan(self.ctx, block, step, ctypes.byref(m), ctypes.byref(n),
+                                       ctypes.byref(w)), self.ctx)
+        return (m.value, n.value, w.value)
 
     def integrate(self, u):
         """[nproblems, nvars + 1]: integral of every field, then kinetic energy."""

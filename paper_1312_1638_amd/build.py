@@ -19,7 +19,8 @@ ARCH = "gfx950"
 HIPFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wno-unused-command-line-argument"]
-SOURCES = ["kernels.hip", "api.cpp", "setup.cpp"]
+SOURCES = ["gemm_f64.hip", "gemm_f32.hip", "kernels.hip", "ceilings.hip", "gemm_host.cpp", "api.cpp",
+           "setup.cpp"]
 
 
 def _hipcc():
@@ -39,7 +40,7 @@ def _compile(src):
 
 def build(verbose=True) -> str:
     os.makedirs(OUT, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=3) as ex:
+    with ThreadPoolExecutor(max_workers=min(6, os.cpu_count() or 2)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -19,8 +20,9 @@ namespace {
 thread_local std::string g_setup_error = "no error";
 
 struct GemmOp {
-  int M = 0, K1 = 0, K2 = 0, KS1 = 0, KS2 = 0, MBW = 1, WM = 1;
+  int M = 0, K1 = 0, K2 = 0, KS1 = 0, KS2 = 0, MBW = 1, NC = 1, WM = 1;
   void *d_A = nullptr;
+  std::vector<double> A;  // unpacked operator (kept for re-packing by the tuner)
 };
 
 struct BlockRT {
@@ -31,7 +33,7 @@ struct BlockRT {
   int64_t uoff = 0, ufoff = 0, qfoff = 0, ftoff = 0, part_off = 0;
   double *d_smat = nullptr, *d_rcpdjac = nullptr, *d_wdjac = nullptr;
   int32_t *d_prob = nullptr;
-  GemmOp m0, s3, s8;
+  GemmOp m0, m5, s3, s8;
   std::vector<double> xu, wdjac_host;
 };
 
@@ -102,22 +104,36 @@ T *dev_upload(fr_ctx *c, const T *h, size_t n, hipStream_t s) {
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+void *pack_upload(fr_ctx *c, const GemmOp &op, fr::GemmPlan p, hipStream_t s, bool track) {
+  const int64_t n = fr::gemm_pack_size(op.M, op.K1, op.K2, p.MBW, p.WM, 4);
+  const size_t es = c->prec == FR_FP64 ? 8 : 4;
+  void *d = nullptr;
+  hipError_t e = hipMalloc(&d, n * es);
+  if (e != hipSuccess) throw Fail{FR_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)};
+  if (track) c->allocs.push_back(d);
+  if (c->prec == FR_FP64) {
+    std::vector<double> pk(n);
+    fr::gemm_pack_f64(op.A.data(), op.M, op.K1, op.K2, p.MBW, p.WM, pk.data());
+    hip_check(hipMemcpyAsync(d, pk.data(), n * es, hipMemcpyHostToDevice, s), "upload");
+    hip_check(hipStreamSynchronize(s), "upload sync");
+  } else {
+    std::vector<float> pk(n);
+    fr::gemm_pack_f32(op.A.data(), op.M, op.K1, op.K2, p.MBW, p.WM, pk.data());
+    hip_check(hipMemcpyAsync(d, pk.data(), n * es, hipMemcpyHostToDevice, s), "upload");
+    hip_check(hipStreamSynchronize(s), "upload sync");
+  }
+  return d;
+}
+
 void make_op(fr_ctx *c, GemmOp &op, const std::vector<double> &A, int M, int K1, int K2,
-             int64_t N, hipStream_t s) {
+             int64_t N, hipStream_t s, fr::GemmPlan *force = nullptr) {
   op.M = M; op.K1 = K1; op.K2 = K2;
   op.KS1 = (K1 + 3) / 4;
   op.KS2 = (K2 + 3) / 4;
-  fr::gemm_plan(M, N, c->prec, &op.MBW, &op.WM);
-  int64_t n = fr::gemm_pack_size(M, K1, K2, op.MBW, op.WM, 4);
-  if (c->prec == FR_FP64) {
-    std::vector<double> pk(n);
-    fr::gemm_pack_f64(A.data(), M, K1, K2, op.MBW, op.WM, pk.data());
-    op.d_A = dev_upload(c, pk.data(), n, s);
-  } else {
-    std::vector<float> pk(n);
-    fr::gemm_pack_f32(A.data(), M, K1, K2, op.MBW, op.WM, pk.data());
-    op.d_A = dev_upload(c, pk.data(), n, s);
-  }
+  op.A = A;
+  fr::GemmPlan p = force ? *force : fr::gemm_plan(M, N, c->prec);
+  op.MBW = p.MBW; op.NC = p.NC; op.WM = p.WM;
+  op.d_A = pack_upload(c, op, p, s, true);
 }
 
 // concatenate two row-major matrices side by side: [A (M x K1) | B (M x K2)]
@@ -142,7 +158,7 @@ fr::GemmArgs gemm_args(const GemmOp &op) {
   fr::GemmArgs g;
   std::memset(&g, 0, sizeof(g));
   g.Apack = op.d_A; g.M = op.M; g.KS1 = op.KS1; g.KS2 = op.KS2; g.K1 = op.K1; g.K2 = op.K2;
-  g.MBW = op.MBW; g.WM = op.WM;
+  g.MBW = op.MBW; g.NC = op.NC; g.WM = op.WM;
   return g;
 }
 
@@ -211,7 +227,7 @@ void run_step(fr_ctx *c, int st, const double *u, double *dudt, int epi, const f
     } else if (st == 4) {
       hip_check(fr::launch_gradcoru(point_args(c, b, u), s), "gradcoru");
     } else if (st == 5) {
-      fr::GemmArgs g = gemm_args(b.m0);
+      fr::GemmArgs g = gemm_args(b.m5);
       g.B1 = elem(c->d_ft, b.ftoff, ts); g.ldb1 = N; g.b1_f32 = f32; g.b2_f32 = f32;
       g.C = elem(c->d_qf, b.qfoff, ts); g.ldc = N; g.c_f32 = f32;
       g.N = N;
@@ -243,6 +259,76 @@ void run_step(fr_ctx *c, int st, const double *u, double *dudt, int epi, const f
 void rhs_chain(fr_ctx *c, const double *u, double *dudt, int epi, const fr::RkCoef *rk,
                const double *dt, hipStream_t s, int stop = 8) {
   for (int st = 1; st <= stop && st <= 8; ++st) run_step(c, st, u, dudt, epi, rk, dt, s);
+}
+
+// Time every instantiated plan of each operator product on this mesh (the
+// real scratch arrays as operands, HIP events on the set-up stream) and keep
+// the fastest.  Results are memoised per shape for the process.
+struct TuneKey {
+  int prec, M, K1, K2, batch, epi;
+  int64_t N;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(prec, M, K1, K2, batch, epi, N) < std::tie(o.prec, o.M, o.K1, o.K2, o.batch, o.epi, o.N);
+  }
+};
+std::map<TuneKey, fr::GemmPlan> g_tuned;
+
+void tune_op(fr_ctx *c, GemmOp &op, int step, BlockRT &b, hipStream_t s) {
+  const int batch = step == 5 ? c->D : 1;
+  const int epi = step == 8 ? fr::EPI_NEGDIV : fr::EPI_STORE;
+  const int64_t N = (int64_t)c->NV * b.ld;
+  TuneKey key{c->prec, op.M, op.K1, op.K2, batch, epi, N};
+  fr::GemmPlan best{op.MBW, op.NC, op.WM};
+  auto it = g_tuned.find(key);
+  if (it != g_tuned.end()) {
+    best = it->second;
+  } else {
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "event");
+    hip_check(hipEventCreate(&e1), "event");
+    float best_ms = 1e30f;
+    for (const fr::GemmPlan &p : fr::gemm_candidates(op.M, N, c->prec)) {
+      void *d = pack_upload(c, op, p, s, false);
+      GemmOp trial = op;
+      trial.d_A = d; trial.MBW = p.MBW; trial.NC = p.NC; trial.WM = p.WM;
+      std::swap(*(step == 1 ? &b.m0 : step == 3 ? &b.s3 : step == 5 ? &b.m5 : &b.s8), trial);
+      float ms = 0;
+      try {
+        for (int w = 0; w < 2; ++w) run_step(c, step, c->d_stage, c->d_acc, epi, nullptr, nullptr, s);
+        hip_check(hipEventRecord(e0, s), "record");
+        for (int w = 0; w < 5; ++w) run_step(c, step, c->d_stage, c->d_acc, epi, nullptr, nullptr, s);
+        hip_check(hipEventRecord(e1, s), "record");
+        hip_check(hipEventSynchronize(e1), "sync");
+        hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+      } catch (...) {
+        std::swap(*(step == 1 ? &b.m0 : step == 3 ? &b.s3 : step == 5 ? &b.m5 : &b.s8), trial);
+        hipFree(d);
+        throw;
+      }
+      std::swap(*(step == 1 ? &b.m0 : step == 3 ? &b.s3 : step == 5 ? &b.m5 : &b.s8), trial);
+      hipFree(d);
+      if (ms < best_ms) { best_ms = ms; best = p; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    g_tuned[key] = best;
+  }
+  if (best.MBW != op.MBW || best.NC != op.NC || best.WM != op.WM) {
+    op.d_A = pack_upload(c, op, best, s, true);
+    op.MBW = best.MBW; op.NC = best.NC; op.WM = best.WM;
+  }
+}
+
+void autotune(fr_ctx *c, hipStream_t s) {
+  for (auto &b : c->blocks) {
+    tune_op(c, b.m0, 1, b, s);
+    tune_op(c, b.s8, 8, b, s);
+    if (c->ns) {
+      tune_op(c, b.s3, 3, b, s);
+      tune_op(c, b.m5, 5, b, s);
+    }
+  }
+  hip_check(hipStreamSynchronize(s), "tune sync");
 }
 
 // One classical RK4 step of u in place: k_s = R(stage_s), with
@@ -357,9 +443,11 @@ fr_status fr_setup_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *b
       make_op(c.get(), b.m0, R.M0, R.nfpts, R.nupts, 0, N, s);
       make_op(c.get(), b.s8, hcat(R.M3, R.nfpts, R.M1p, D * R.nupts, R.nupts), R.nupts,
               R.nfpts, D * R.nupts, N, s);
-      if (c->ns)
+      if (c->ns) {
         make_op(c.get(), b.s3, hcat(R.M6, R.nfpts, R.M4p, R.nupts, D * R.nupts), D * R.nupts,
                 R.nfpts, R.nupts, N, s);
+        make_op(c.get(), b.m5, R.M0, R.nfpts, R.nupts, 0, D * N, s);
+      }
       G = fr::BlockGeom();
     }
     // pair table
@@ -408,6 +496,7 @@ fr_status fr_setup_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *b
       c->d_plist = dev_upload(c.get(), flat.data(), flat.size(), s);
     }
     c->d_flag = dev_alloc<int32_t>(c.get(), 1);
+    if (cfg->autotune) autotune(c.get(), s);
     hip_check(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "stream");
     hip_check(hipDeviceSynchronize(), "setup sync");
   } catch (const fr::SetupError &e) {
@@ -646,7 +735,7 @@ fr_status fr_debug_scratch_len(const fr_ctx *c, int32_t stage, int64_t *len) {
 
 fr_status fr_debug_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, const double *A,
                         const void *B1, const void *B2, int64_t ldb, void *C, int64_t N,
-                        void *hip_stream) {
+                        int32_t mbw, int32_t nc, int32_t wm, void *hip_stream) {
   if (!A || !B1 || !C || M < 1 || K1 < 1 || K2 < 0 || N < 16 || N % 16 || (K2 && !B2))
     return fail(nullptr, FR_EINVAL, "bad gemm arguments");
   if (prec != FR_FP64 && prec != FR_FP32) return fail(nullptr, FR_EUNSUPPORTED, "precision");
@@ -656,7 +745,10 @@ fr_status fr_debug_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, const d
   try {
     GemmOp op;
     std::vector<double> Av(A, A + (size_t)M * (K1 + K2));
-    make_op(&tmp, op, Av, M, K1, K2, N, s);
+    fr::GemmPlan p{mbw, nc, wm};
+    if (mbw > 0 && (!fr::gemm_plan_valid(mbw, nc) || wm < 1 || mbw * wm * 16 < M))
+      throw Fail{FR_EINVAL, "bad plan"};
+    make_op(&tmp, op, Av, M, K1, K2, N, s, mbw > 0 ? &p : nullptr);
     fr::GemmArgs g = gemm_args(op);
     g.B1 = B1; g.ldb1 = ldb; g.b1_f32 = 0;
     g.B2 = B2; g.ldb2 = ldb; g.b2_f32 = 0;
@@ -670,6 +762,74 @@ fr_status fr_debug_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, const d
     return fail(nullptr, f.st, f.msg);
   }
   for (void *p : tmp.allocs) hipFree(p);
+  return FR_OK;
+}
+
+fr_status fr_measure_ceiling(int32_t kind, double *value, void *hip_stream) {
+  if (!value || kind < 0 || kind > 2) return fail(nullptr, FR_EINVAL, "bad ceiling kind");
+  hipError_t e = fr::measure_ceiling(kind, value, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return fail(nullptr, FR_EDEVICE, hipGetErrorString(e));
+  return FR_OK;
+}
+
+fr_status fr_bench_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, int64_t N,
+                        int32_t mbw, int32_t nc, int32_t wm, int32_t batch, int32_t nrep,
+                        float *ms_per_launch, void *hip_stream) {
+  if (!ms_per_launch || M < 1 || K1 < 1 || K2 < 0 || N < 16 || N % 16 || nrep < 1 || batch < 1)
+    return fail(nullptr, FR_EINVAL, "bad gemm benchmark arguments");
+  if (prec != FR_FP64 && prec != FR_FP32) return fail(nullptr, FR_EUNSUPPORTED, "precision");
+  hipStream_t s = (hipStream_t)hip_stream;
+  fr_ctx tmp;
+  tmp.prec = prec;
+  const size_t es = prec == FR_FP64 ? 8 : 4;
+  try {
+    GemmOp op;
+    std::vector<double> A((size_t)M * (K1 + K2), 0.5);
+    fr::GemmPlan p{mbw, nc, wm};
+    if (mbw > 0 && (!fr::gemm_plan_valid(mbw, nc) || wm < 1 || mbw * wm * 16 < M))
+      throw Fail{FR_EINVAL, "bad plan"};
+    make_op(&tmp, op, A, M, K1, K2, N, s, mbw > 0 ? &p : nullptr);
+    void *B1 = dev_alloc<char>(&tmp, (size_t)K1 * N * batch * es);
+    void *B2 = dev_alloc<char>(&tmp, (size_t)(K2 ? K2 : 1) * N * es);
+    void *C = dev_alloc<char>(&tmp, (size_t)M * N * batch * es);
+    fr::GemmArgs g = gemm_args(op);
+    g.B1 = B1; g.ldb1 = N; g.b1_f32 = prec != FR_FP64;
+    g.B2 = B2; g.ldb2 = N; g.b2_f32 = prec != FR_FP64;
+    g.C = C; g.ldc = N; g.c_f32 = prec != FR_FP64;
+    g.N = N; g.sB1 = (int64_t)K1 * N; g.sC = (int64_t)M * N;
+    const int gp = prec == FR_FP64 ? fr::PREC_F64 : fr::PREC_F32;
+    for (int w = 0; w < 3; ++w) hip_check(fr::launch_gemm(gp, fr::EPI_STORE, g, batch, s), "gemm");
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "event");
+    hip_check(hipEventCreate(&e1), "event");
+    hip_check(hipEventRecord(e0, s), "record");
+    for (int w = 0; w < nrep; ++w) hip_check(fr::launch_gemm(gp, fr::EPI_STORE, g, batch, s), "gemm");
+    hip_check(hipEventRecord(e1, s), "record");
+    hip_check(hipEventSynchronize(e1), "sync");
+    float ms = 0;
+    hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+    *ms_per_launch = ms / nrep;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+  } catch (const Fail &f) {
+    hipDeviceSynchronize();
+    for (void *q : tmp.allocs) hipFree(q);
+    tmp.allocs.clear();
+    return fail(nullptr, f.st, f.msg);
+  }
+  hipDeviceSynchronize();
+  for (void *q : tmp.allocs) hipFree(q);
+  tmp.allocs.clear();
+  return FR_OK;
+}
+
+fr_status fr_get_gemm_plan(const fr_ctx *c, int32_t block, int32_t step, int32_t *mbw,
+                           int32_t *nc, int32_t *wm) {
+  if (!c || block < 0 || block >= (int)c->blocks.size() || !mbw || !nc || !wm) return FR_EINVAL;
+  const BlockRT &b = c->blocks[block];
+  const GemmOp *op = step == 1 ? &b.m0 : step == 3 ? &b.s3 : step == 5 ? &b.m5 : step == 8 ? &b.s8 : nullptr;
+  if (!op || (!c->ns && (step == 3 || step == 5))) return FR_EINVAL;
+  *mbw = op->MBW; *nc = op->NC; *wm = op->WM;
   return FR_OK;
 }
 

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <vector>
 
 namespace fr {
 
@@ -32,6 +33,7 @@ struct GemmArgs {
   int KS1, KS2;           // k-steps (of the MFMA K) in each panel
   int K1, K2;             // true K of each panel
   int MBW;                // row blocks (16 rows) per wave
+  int NC;                 // 16-column strips per wave
   int WM;                 // waves along M sharing one column tile
   const void *B1; int64_t ldb1; int b1_f32;   // panel 1 (rows K1), row stride
   const void *B2; int64_t ldb2; int b2_f32;   // panel 2 (rows K2)
@@ -57,9 +59,15 @@ int64_t gemm_pack_size_bf16(int M, int K1, int K2, int MBW, int WM);
 void gemm_pack_bf16x3(const double *A, int M, int K1, int K2, int MBW, int WM, uint16_t *dst);
 
 hipError_t launch_gemm(int prec, int epi, const GemmArgs &g, int batch, hipStream_t s);
+hipError_t launch_gemm_f64(int epi, const GemmArgs &g, int batch, hipStream_t s);
+hipError_t launch_gemm_f32(int epi, const GemmArgs &g, int batch, hipStream_t s);
 
-// Choose the row split for an M-row operator and N columns.
-void gemm_plan(int M, int64_t N, int prec, int *MBW, int *WM);
+struct GemmPlan { int MBW, NC, WM; };
+// Default plan for an M-row operator and N columns (no tuning).
+GemmPlan gemm_plan(int M, int64_t N, int prec);
+// Every instantiated plan worth timing for this shape (autotuner).
+std::vector<GemmPlan> gemm_candidates(int M, int64_t N, int prec);
+bool gemm_plan_valid(int MBW, int NC);
 
 // ----------------------------------------------------------------------------
 // Point-wise and interface kernels
@@ -115,6 +123,8 @@ hipError_t launch_elem_integrals(int nvars, int ndims, int nupts, int64_t ld, in
 hipError_t launch_problem_sums(int ncomp, int nprob, const int64_t *pstart,
                                const int64_t *plist, const double *part, double *out,
                                hipStream_t s);
+// measured ceilings: kind 0 HBM triad GB/s, 1 FP64 MFMA TFLOP/s, 2 FP32 MFMA TFLOP/s
+hipError_t measure_ceiling(int kind, double *value, hipStream_t s);
 // flag[0] = 1 if any u is not finite
 hipError_t launch_check_finite(const double *u, int64_t n, int32_t *flag, hipStream_t s);
 

@@ -1,13 +1,6 @@
 // HIP kernels of the FR right-hand side for gfx950 (CDNA4).
 //
-//  * Operator products (Appendix A) on the matrix cores: one wavefront owns a
-//    16-column strip of the state matrix and MBW 16-row blocks of the
-//    operator; it streams its B strip from HBM exactly once (each lane loads
-//    one element per 4-row k-step: 4 rows x 128 contiguous bytes per load)
-//    and reads the operator from a pre-packed fragment stream that stays in
-//    L2.  Accumulation is FP64 (v_mfma_f64_16x16x4) or FP32
-//    (v_mfma_f32_16x16x4), with fused epilogues for du/dt = -J^-1 R~ and the
-//    RK4 register updates.
+//  * Operator products (Appendix A) live in gemm.h / gemm_*.hip.
 //  * Point-wise kernels (gradient transform, transformed flux) are one thread
 //    per (solution point, element): every access is a unit-stride row of the
 //    SoA state, so a wavefront reads 64 consecutive elements.
@@ -24,235 +17,6 @@
 #include <vector>
 
 namespace fr {
-
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-typedef float flt4 __attribute__((ext_vector_type(4)));
-
-// ============================================================================
-// Operator GEMM
-// ============================================================================
-template <typename T> struct Mma;
-// Output lane layouts differ: register r of lane l holds row 4 r + l / 16 for
-// v_mfma_f64_16x16x4f64 and row 4 (l / 16) + r for v_mfma_f32_16x16x4f32
-// (column l % 16 in both; inputs A[l % 16][l / 16], B[l / 16][l % 16]).
-template <> struct Mma<double> {
-  typedef dbl4 acc_t;
-  static __device__ __forceinline__ int row(int kq, int r) { return 4 * r + kq; }
-  static __device__ __forceinline__ acc_t run(double a, double b, acc_t c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-};
-template <> struct Mma<float> {
-  typedef flt4 acc_t;
-  static __device__ __forceinline__ int row(int kq, int r) { return 4 * kq + r; }
-  static __device__ __forceinline__ acc_t run(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-};
-
-template <typename T, typename TB>
-__device__ __forceinline__ T load_b(const TB *__restrict__ B, int64_t ldb, int K, int ks, int kq,
-                                    int64_t col) {
-  int k = ks * 4 + kq;
-  return k < K ? (T)B[(int64_t)k * ldb + col] : (T)0;
-}
-
-// k-steps per prefetch chunk: enough MFMAs per chunk (KC * MBW of them) to
-// cover the latency of the next chunk's loads, within the register budget.
-template <int MBW> struct Chunk {
-  static constexpr int KC = MBW >= 12 ? 2 : (MBW >= 6 ? 4 : (MBW >= 3 ? 6 : 8));
-};
-
-// Fragment layout of A: [wave row group rg][k-step][row block m][64 lanes],
-// lane l of fragment (m, ks) holding A[16 m' + l % 16][4 ks + l / 16].
-// The k loop runs in chunks of KC k-steps whose A and B fragments are
-// loaded one chunk ahead (double-buffered in registers).
-template <typename T, int MBW, int EPI, typename TB1, typename TB2, typename TC>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
-  typedef typename Mma<T>::acc_t acc_t;
-  constexpr int KC = Chunk<MBW>::KC;
-  const int lane = threadIdx.x & 63;
-  const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int rg = (int)(gw % g.WM);
-  const int64_t n0 = (gw / g.WM) * 16;
-  if (n0 >= g.N) return;
-  const int col = lane & 15, kq = lane >> 4;
-  const int64_t bcol = n0 + col;
-  const int KS1 = g.KS1, KS = g.KS1 + g.KS2;
-  const TB1 *__restrict__ B1 = (const TB1 *)g.B1 + (int64_t)blockIdx.y * g.sB1;
-  const TB2 *__restrict__ B2 = (const TB2 *)g.B2;
-  const T *__restrict__ A = (const T *)g.Apack + (int64_t)rg * KS * MBW * 64 + lane;
-
-  acc_t acc[MBW];
-#pragma unroll
-  for (int m = 0; m < MBW; ++m) acc[m] = acc_t{0, 0, 0, 0};
-
-  T b0[KC], b1[KC], a0[KC][MBW], a1[KC][MBW];
-  auto load = [&](int c, T (&b)[KC], T (&a)[KC][MBW]) {
-#pragma unroll
-    for (int kk = 0; kk < KC; ++kk) {
-      const int ks = c * KC + kk;
-      if (ks < KS1) b[kk] = load_b<T>(B1, g.ldb1, g.K1, ks, kq, bcol);
-      else if (ks < KS) b[kk] = load_b<T>(B2, g.ldb2, g.K2, ks - KS1, kq, bcol);
-      else b[kk] = 0;
-#pragma unroll
-      for (int m = 0; m < MBW; ++m) a[kk][m] = ks < KS ? A[((int64_t)ks * MBW + m) * 64] : (T)0;
-    }
-  };
-  auto compute = [&](const T (&b)[KC], const T (&a)[KC][MBW]) {
-#pragma unroll
-    for (int kk = 0; kk < KC; ++kk)
-#pragma unroll
-      for (int m = 0; m < MBW; ++m) acc[m] = Mma<T>::run(a[kk][m], b[kk], acc[m]);
-  };
-  const int nch = (KS + KC - 1) / KC;
-  load(0, b0, a0);
-  for (int c = 0; c < nch; c += 2) {
-    if (c + 1 < nch) load(c + 1, b1, a1);
-    compute(b0, a0);
-    if (c + 1 >= nch) break;
-    if (c + 2 < nch) load(c + 2, b0, a0);
-    compute(b1, a1);
-  }
-
-  // epilogue: lane holds rows 16 m + Mma<T>::row(kq, r), column n0 + col
-  const int64_t colg = n0 + col;
-  int64_t n = 0;
-  if (EPI != EPI_STORE) n = colg - (n0 / g.ld) * g.ld;
-  const bool live = n < g.nelem;
-  double dtv = 0;
-  if (EPI == EPI_RK && live) dtv = g.dt[g.prob ? g.prob[n] : 0];
-#pragma unroll
-  for (int m = 0; m < MBW; ++m) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = (rg * MBW + m) * 16 + Mma<T>::row(kq, r);
-      if (row >= g.M) continue;
-      const double v = (double)acc[m][r];
-      const int64_t idx = (int64_t)row * g.ldc + colg;
-      if (EPI == EPI_STORE) {
-        ((TC *)g.C)[(int64_t)blockIdx.y * g.sC + idx] = (TC)v;
-      } else {
-        const double k = live ? -g.rcpdjac[(int64_t)row * g.ld + n] * v : 0.0;
-        if (EPI == EPI_NEGDIV) {
-          g.out[idx] = k;
-        } else {
-          const double bdt = g.rk.b * dtv * k;
-          if (g.rk.last) {
-            g.out[idx] = g.acc[idx] + bdt;
-          } else {
-            const double u0 = g.out[idx];
-            g.acc[idx] = (g.rk.first ? u0 : g.acc[idx]) + bdt;
-            g.stage[idx] = u0 + g.rk.a_next * dtv * k;
-          }
-        }
-      }
-    }
-  }
-}
-
-int64_t gemm_pack_size(int M, int K1, int K2, int MBW, int WM, int kstep) {
-  int KS = (K1 + kstep - 1) / kstep + (K2 + kstep - 1) / kstep;
-  return (int64_t)WM * KS * MBW * 64;
-}
-
-template <typename T>
-static void gemm_pack(const double *A, int M, int K1, int K2, int MBW, int WM, T *dst) {
-  const int KS1 = (K1 + 3) / 4, KS2 = (K2 + 3) / 4, KS = KS1 + KS2, K = K1 + K2;
-  for (int rg = 0; rg < WM; ++rg)
-    for (int ks = 0; ks < KS; ++ks)
-      for (int m = 0; m < MBW; ++m)
-        for (int l = 0; l < 64; ++l) {
-          int row = (rg * MBW + m) * 16 + (l & 15);
-          int kk = ks < KS1 ? ks * 4 + (l >> 4) : (ks - KS1) * 4 + (l >> 4);
-          bool ok = ks < KS1 ? kk < K1 : kk < K2;
-          int acol = ks < KS1 ? kk : K1 + kk;
-          double v = (row < M && ok) ? A[(int64_t)row * K + acol] : 0.0;
-          dst[(((int64_t)rg * KS + ks) * MBW + m) * 64 + l] = (T)v;
-        }
-}
-
-void gemm_pack_f64(const double *A, int M, int K1, int K2, int MBW, int WM, double *dst) {
-  gemm_pack<double>(A, M, K1, K2, MBW, WM, dst);
-}
-void gemm_pack_f32(const double *A, int M, int K1, int K2, int MBW, int WM, float *dst) {
-  gemm_pack<float>(A, M, K1, K2, MBW, WM, dst);
-}
-
-void gemm_plan(int M, int64_t N, int prec, int *MBW, int *WM) {
-  const int MB = (M + 15) / 16;
-  const int maxw = 12;
-  const int64_t ntile = (N + 15) / 16;
-  int wm = (MB + maxw - 1) / maxw;
-  while (wm < MB && wm * ntile < 2048) ++wm;
-  int mbw = (MB + wm - 1) / wm;
-  wm = (MB + mbw - 1) / mbw;
-  *MBW = mbw;
-  *WM = wm;
-}
-
-// Element types of (B1, B2, C) by precision:
-//   FP64: all double.
-//   FP32 stores: B1 double (state) or float (scratch); B2 double (state) or
-//   float; C float.  FP32 fused epilogues: float scratch in, FP64 out.
-template <typename T, int MBW, int EPI>
-static hipError_t launch_gemm_t(const GemmArgs &g, int batch, hipStream_t s) {
-  const int64_t waves = ((g.N + 15) / 16) * g.WM;
-  dim3 grid((unsigned)((waves + 3) / 4), batch), block(256);
-  if constexpr (sizeof(T) == 8) {
-    gemm_kernel<T, MBW, EPI, double, double, double><<<grid, block, 0, s>>>(g);
-  } else if constexpr (EPI != EPI_STORE) {
-    gemm_kernel<T, MBW, EPI, float, float, double><<<grid, block, 0, s>>>(g);
-  } else {
-    if (!g.b1_f32)
-      gemm_kernel<T, MBW, EPI, double, double, float><<<grid, block, 0, s>>>(g);
-    else if (!g.b2_f32)
-      gemm_kernel<T, MBW, EPI, float, double, float><<<grid, block, 0, s>>>(g);
-    else
-      gemm_kernel<T, MBW, EPI, float, float, float><<<grid, block, 0, s>>>(g);
-  }
-  return hipGetLastError();
-}
-
-template <typename T, int EPI>
-static hipError_t launch_gemm_e(const GemmArgs &g, int batch, hipStream_t s) {
-  switch (g.MBW) {
-    case 1: return launch_gemm_t<T, 1, EPI>(g, batch, s);
-    case 2: return launch_gemm_t<T, 2, EPI>(g, batch, s);
-    case 3: return launch_gemm_t<T, 3, EPI>(g, batch, s);
-    case 4: return launch_gemm_t<T, 4, EPI>(g, batch, s);
-    case 5: return launch_gemm_t<T, 5, EPI>(g, batch, s);
-    case 6: return launch_gemm_t<T, 6, EPI>(g, batch, s);
-    case 7: return launch_gemm_t<T, 7, EPI>(g, batch, s);
-    case 8: return launch_gemm_t<T, 8, EPI>(g, batch, s);
-    case 9: return launch_gemm_t<T, 9, EPI>(g, batch, s);
-    case 10: return launch_gemm_t<T, 10, EPI>(g, batch, s);
-    case 11: return launch_gemm_t<T, 11, EPI>(g, batch, s);
-    case 12: return launch_gemm_t<T, 12, EPI>(g, batch, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_gemm(int prec, int epi, const GemmArgs &g, int batch, hipStream_t s) {
-  if (g.N <= 0) return hipSuccess;
-  if (prec == PREC_F64) {
-    if (epi == EPI_STORE) return launch_gemm_e<double, EPI_STORE>(g, batch, s);
-    if (epi == EPI_NEGDIV) return launch_gemm_e<double, EPI_NEGDIV>(g, batch, s);
-    return launch_gemm_e<double, EPI_RK>(g, batch, s);
-  }
-  if (prec == PREC_F32) {
-    if (epi == EPI_STORE) return launch_gemm_e<float, EPI_STORE>(g, batch, s);
-    if (epi == EPI_NEGDIV) return launch_gemm_e<float, EPI_NEGDIV>(g, batch, s);
-    return launch_gemm_e<float, EPI_RK>(g, batch, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-// BF16x3 packing is provided with its kernel elsewhere; size helper here.
-int64_t gemm_pack_size_bf16(int M, int K1, int K2, int MBW, int WM) {
-  int KS = (K1 + 15) / 16 + (K2 + 15) / 16;
-  return (int64_t)WM * KS * MBW * 64 * 4 * 2;
-}
 
 // ============================================================================
 // Physics (device): Euler flux, viscous flux, Rusanov and LDG fluxes

@@ -31,6 +31,32 @@ def test_gemm_random(M, K1, K2, N, prec):
     assert err < (1e-14 if prec == "fp64" else 2e-6)
 
 
+SHAPES = [(1, 1), (1, 2), (1, 4), (2, 1), (2, 2), (2, 4), (3, 1), (3, 2), (3, 4), (4, 1),
+          (4, 2), (4, 4), (6, 1), (6, 2), (6, 4), (8, 1), (8, 2), (12, 1), (12, 2)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gemm_every_tile_shape(prec):
+    """Every instantiated (row blocks, column strips) shape, with a ragged M,
+    ragged K in both panels and a column count not divisible by the strip
+    width."""
+    import torch
+    import paper_1312_1638_amd as P
+    rng = np.random.default_rng(11)
+    M, K1, K2, N = 150, 37, 22, 16 * 13
+    A = rng.standard_normal((M, K1 + K2))
+    B1 = rng.standard_normal((K1, N))
+    B2 = rng.standard_normal((K2, N))
+    ref = A @ np.concatenate([B1, B2])
+    dB1, dB2 = torch.from_numpy(B1).cuda(), torch.from_numpy(B2).cuda()
+    MB = (M + 15) // 16
+    for mbw, nc in SHAPES:
+        wm = -(-MB // mbw)
+        got = P.binding.debug_gemm(A, dB1, dB2, prec, (mbw, nc, wm)).double().cpu().numpy()
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        assert err < (1e-14 if prec == "fp64" else 2e-6), (mbw, nc, wm, err)
+
+
 def _split(s, flat, rows_per_block, nvars):
     """Internal scratch array -> per-block [rows, alpha, n] (padding removed)."""
     out, off = [], 0
