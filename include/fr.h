@@ -207,6 +207,12 @@ fr_status fr_bench_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, int64_t
 fr_status fr_get_gemm_plan(const fr_ctx *ctx, int32_t block, int32_t step, int32_t *mbw,
                            int32_t *nc, int32_t *wm);
 
+/* Gradient of an integral of fr_integrate with respect to the state: kind 1
+ * (kinetic energy, summed over problems) -> grad (DEVICE, state layout),
+ * W J (-|v|^2 / 2, v, 0) at each solution point. */
+fr_status fr_integrate_grad(fr_ctx *ctx, const double *u, int32_t kind, double *grad,
+                            void *hip_stream);
+
 /* Message of the last failure on ctx (ctx NULL: last failed setup on this
  * thread).  Never NULL. */
 const char *fr_last_error(const fr_ctx *ctx);

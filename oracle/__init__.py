@@ -13,4 +13,4 @@ Every function here is written in the paper's order and notation, in FP64
 (long double where a linear solve needs headroom), with numpy library
 primitives (einsum contractions, a dense solve) as the only building blocks.
 """
-from .rhs import Discretisation  # noqa: F401
+from .rhs import Discretisation, jvp, rk4_jvp  # noqa: F401

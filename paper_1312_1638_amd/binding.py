@@ -24,7 +24,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 EXPORTS = ("fr_setup_mesh", "fr_get_layout", "fr_get_solution_points", "fr_get_quadrature",
            "fr_rhs", "fr_rk_step", "fr_rhs_adjoint", "fr_rk_step_adjoint", "fr_integrate",
            "fr_reference_operator", "fr_check_mesh", "fr_debug_stage", "fr_debug_scratch_len", "fr_bench_step",
-           "fr_debug_gemm", "fr_measure_ceiling", "fr_bench_gemm", "fr_get_gemm_plan",
+           "fr_debug_gemm", "fr_measure_ceiling", "fr_bench_gemm", "fr_get_gemm_plan", "fr_integrate_grad",
            "fr_last_error", "fr_destroy")
 
 
@@ -78,6 +78,7 @@ def load_library(path: str = LIB_PATH):
         "fr_rhs_adjoint": [vp, dp, dp, dp, vp],
         "fr_rk_step_adjoint": [vp, dp, dp, dp, dp, vp],
         "fr_integrate": [vp, dp, i32, dp, vp],
+        "fr_integrate_grad": [vp, dp, i32, dp, vp],
         "fr_reference_operator": [i32, i32, i32, dp, i64, ctypes.POINTER(i32),
                                   ctypes.POINTER(i32)],
         "fr_check_mesh": [ctypes.POINTER(FrConfig), i32, ctypes.POINTER(FrBlock), i64, vp,
@@ -331,6 +332,14 @@ class Solver:
         """Launch right-hand-side step `step` nrep times (after preparing its
         inputs) on the current stream; for kernel timing."""
         _check(self.L.fr_bench_step(self.ctx, self._ptr(u), step, nrep, self._stream()), self.ctx)
+
+    def kinetic_energy_grad(self, u, out=None):
+        """d(sum of kinetic energy integrals)/du, state layout."""
+        if out is None:
+            out = self.empty()
+        _check(self.L.fr_integrate_grad(self.ctx, self._ptr(u), 1, self._ptr(out), self._stream()),
+               self.ctx)
+        return out
 
     def gemm_plan(self, block, step):
         m, n, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

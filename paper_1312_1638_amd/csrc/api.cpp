@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/fr.h"
+#include "adjoint.h"
 #include "kernels.h"
 #include "setup.h"
 
@@ -34,6 +35,9 @@ struct BlockRT {
   double *d_smat = nullptr, *d_rcpdjac = nullptr, *d_wdjac = nullptr;
   int32_t *d_prob = nullptr;
   GemmOp m0, m5, s3, s8;
+  // transposed operators of the adjoint: M3^T, (M1 - M3 M2)^T, M0^T, M6^T,
+  // [(M4 - M6 M0)^T | M0^T]
+  GemmOp t_m3, t_m1, t_m0, t_m6, t_fin;
   std::vector<double> xu, wdjac_host;
 };
 
@@ -67,6 +71,11 @@ struct fr_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   const double *graph_u = nullptr, *graph_dt = nullptr;
+  // adjoint scratch (allocated on first use, FP64 contexts only)
+  bool adj_ready = false;
+  double *d_ufb = nullptr, *d_ftb = nullptr, *d_qfb = nullptr, *d_lt = nullptr;
+  double *d_lc = nullptr, *d_kb = nullptr, *d_w = nullptr, *d_k = nullptr;
+  double *d_st[3] = {nullptr, nullptr, nullptr};
   std::vector<void *> allocs;
 };
 
@@ -331,6 +340,157 @@ void autotune(fr_ctx *c, hipStream_t s) {
   hip_check(hipStreamSynchronize(s), "tune sync");
 }
 
+std::vector<double> transpose(const std::vector<double> &A, int rows, int cols) {
+  std::vector<double> T((size_t)rows * cols);
+  for (int r = 0; r < rows; ++r)
+    for (int c2 = 0; c2 < cols; ++c2) T[(size_t)c2 * rows + r] = A[(size_t)r * cols + c2];
+  return T;
+}
+
+void ensure_adjoint(fr_ctx *c, hipStream_t s) {
+  if (c->adj_ready) return;
+  if (c->prec != FR_FP64) throw Fail{FR_EUNSUPPORTED, "the adjoint is available for FP64 contexts"};
+  const int D = c->D, NV = c->NV;
+  c->d_ufb = dev_alloc<double>(c, c->uf_len);
+  c->d_ftb = dev_alloc<double>(c, c->ft_len);
+  if (c->ns) c->d_qfb = dev_alloc<double>(c, c->qf_len);
+  for (double **p : {&c->d_lt, &c->d_lc, &c->d_kb, &c->d_w, &c->d_k, &c->d_st[0], &c->d_st[1],
+                     &c->d_st[2]})
+    *p = dev_alloc<double>(c, c->total_len);
+  for (auto &b : c->blocks) {
+    const fr::RefOps &R = c->refs[b.ref];
+    const int Nu = R.nupts, Nf = R.nfpts;
+    const int64_t N = (int64_t)NV * b.ld;
+    make_op(c, b.t_m3, transpose(R.M3, Nu, Nf), Nf, Nu, 0, N, s);
+    make_op(c, b.t_m1, transpose(R.M1p, Nu, D * Nu), D * Nu, Nu, 0, N, s);
+    make_op(c, b.t_m0, transpose(R.M0, Nf, Nu), Nu, Nf, 0, c->ns ? D * N : N, s);
+    if (c->ns) {
+      make_op(c, b.t_m6, transpose(R.M6, D * Nu, Nf), Nf, D * Nu, 0, N, s);
+      make_op(c, b.t_fin, hcat(transpose(R.M4p, D * Nu, Nu), D * Nu, transpose(R.M0, Nf, Nu), Nf, Nu),
+              Nu, D * Nu, Nf, N, s);
+    }
+  }
+  c->adj_ready = true;
+}
+
+fr::AdjPairArgs adj_pair_args(fr_ctx *c) {
+  fr::AdjPairArgs a;
+  std::memset(&a, 0, sizeof(a));
+  const int NV = c->NV;
+  a.ndims = c->D; a.nvars = NV; a.npairs = c->npairs;
+  a.lidx = c->d_lidx; a.ridx = c->d_ridx;
+  a.lblk = c->blocks.size() > 1 ? c->d_lblk : nullptr;
+  a.rblk = c->blocks.size() > 1 ? c->d_rblk : nullptr;
+  a.nrm = c->d_nrm; a.magL = c->d_magL; a.magR = c->d_magR;
+  a.uf = (const double *)c->d_uf; a.qf = (const double *)c->d_qf;
+  a.ufb = c->d_ufb; a.qfb = c->d_qfb;
+  a.blk_ufbase = c->d_blk_ufbase; a.blk_qfbase = c->d_blk_qfbase;
+  a.blk_ld = c->d_blk_ld; a.blk_qstride = c->d_blk_qstride;
+  a.ld0 = c->blocks[0].ld;
+  a.qstride0 = (int64_t)c->blocks[0].Nf * NV * c->blocks[0].ld;
+  a.gamma = c->cfg.gamma; a.mu = c->cfg.mu; a.prandtl = c->cfg.prandtl;
+  a.beta = c->cfg.ldg_beta; a.tau = c->cfg.ldg_tau;
+  return a;
+}
+
+void adj_gemm(fr_ctx *c, const GemmOp &op, const double *B1, const double *B2, double *C,
+              int64_t N, int epi, int batch, int64_t sB1, int64_t sC, hipStream_t s) {
+  fr::GemmArgs g = gemm_args(op);
+  g.B1 = B1; g.ldb1 = N; g.B2 = B2; g.ldb2 = N;
+  g.C = C; g.ldc = N; g.N = N; g.sB1 = sB1; g.sC = sC;
+  hip_check(fr::launch_gemm(fr::PREC_F64, epi, g, batch, s), "adjoint gemm");
+}
+
+// ulam = (dR/du)(u)^T lam, the reverse of rhs_chain
+void rhs_adjoint_chain(fr_ctx *c, const double *u, const double *lam, double *ulam,
+                       hipStream_t s) {
+  const int D = c->D, NV = c->NV;
+  // primal intermediates: U^f (and C^f -> Q, Q^f for Navier-Stokes)
+  rhs_chain(c, u, nullptr, fr::EPI_NEGDIV, nullptr, nullptr, s, c->ns ? 5 : 1);
+  double *ft = (double *)c->d_ft;
+  for (auto &b : c->blocks) {
+    const int64_t N = (int64_t)NV * b.ld;
+    hip_check(fr::launch_negscale(NV, b.Nu, b.ld, b.nelem, b.d_rcpdjac, lam + b.uoff,
+                                  c->d_lt + b.uoff, s), "negscale");
+    // D~b = M3^T lt ; F~b = (M1 - M3 M2)^T lt
+    adj_gemm(c, b.t_m3, c->d_lt + b.uoff, nullptr, c->d_ufb + b.ufoff, N, fr::EPI_STORE, 1, 0, 0, s);
+    adj_gemm(c, b.t_m1, c->d_lt + b.uoff, nullptr, c->d_ftb + b.ftoff, N, fr::EPI_STORE, 1, 0, 0, s);
+  }
+  hip_check(fr::launch_comm_flux_vjp(adj_pair_args(c), c->ns, s), "comm_flux_vjp");
+  for (auto &b : c->blocks) {
+    fr::AdjPointArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.ndims = D; a.nvars = NV; a.nupts = b.Nu; a.ld = b.ld; a.nelem = b.nelem;
+    a.smat = b.d_smat; a.rcpdjac = b.d_rcpdjac; a.u = u + b.uoff; a.q = ft + b.ftoff;
+    a.fb = c->d_ftb + b.ftoff; a.ulam = ulam + b.uoff;
+    a.gamma = c->cfg.gamma; a.mu = c->cfg.mu; a.prandtl = c->cfg.prandtl;
+    hip_check(fr::launch_tflux_vjp(a, c->ns, s), "tflux_vjp");
+    const int64_t N = (int64_t)NV * b.ld;
+    if (c->ns) {
+      // Q b += blockdiag(M0)^T Q^f b
+      adj_gemm(c, b.t_m0, c->d_qfb + b.qfoff, nullptr, c->d_ftb + b.ftoff, N, fr::EPI_ADD, D,
+               (int64_t)b.Nf * N, (int64_t)b.Nu * N, s);
+      hip_check(fr::launch_gradcoru_t(a, s), "gradcoru_t");
+      // C^f b = M6^T Q~b (into the first rows of the Q^f b region)
+      adj_gemm(c, b.t_m6, c->d_ftb + b.ftoff, nullptr, c->d_qfb + b.qfoff, N, fr::EPI_STORE, 1,
+               0, 0, s);
+    }
+  }
+  if (c->ns) hip_check(fr::launch_con_u_vjp(adj_pair_args(c), s), "con_u_vjp");
+  for (auto &b : c->blocks) {
+    const int64_t N = (int64_t)NV * b.ld;
+    if (c->ns)
+      adj_gemm(c, b.t_fin, c->d_ftb + b.ftoff, c->d_ufb + b.ufoff, ulam + b.uoff, N, fr::EPI_ADD,
+               1, 0, 0, s);
+    else
+      adj_gemm(c, b.t_m0, c->d_ufb + b.ufoff, nullptr, ulam + b.uoff, N, fr::EPI_ADD, 1, 0, 0, s);
+  }
+}
+
+void axpy_blocks(fr_ctx *c, const double *dt, double coef, const double *x, const double *y,
+                 double *out, hipStream_t s) {
+  for (auto &b : c->blocks)
+    hip_check(fr::launch_axpy_dt((int64_t)b.Nu * c->NV * b.ld, b.ld, b.nelem, b.d_prob, dt, coef,
+                                 x + b.uoff, y ? y + b.uoff : nullptr, out + b.uoff, s),
+              "axpy");
+}
+
+void rk_adj_blocks(fr_ctx *c, const double *dt, double ca, double cb, double *acc, int first,
+                   bool last, hipStream_t s) {
+  for (auto &b : c->blocks)
+    hip_check(fr::launch_rk_adj((int64_t)b.Nu * c->NV * b.ld, b.ld, b.nelem, b.d_prob, dt, ca, cb,
+                                c->d_lc + b.uoff, c->d_w + b.uoff, acc + b.uoff,
+                                last ? nullptr : c->d_kb + b.uoff, first, s),
+              "rk adjoint update");
+}
+
+// lam_n = (d u_{n+1} / d u_n)^T lam_np1 for one classical RK4 step
+void rk4_step_adjoint(fr_ctx *c, const double *u, const double *dt, const double *lam_np1,
+                      double *lam_n, hipStream_t s) {
+  ensure_adjoint(c, s);
+  // stage states u2 = u + dt/2 k1, u3 = u + dt/2 k2, u4 = u + dt k3
+  static const double a[3] = {0.5, 0.5, 1.0};
+  const double *prev = u;
+  for (int i = 0; i < 3; ++i) {
+    rhs_chain(c, prev, c->d_k, fr::EPI_NEGDIV, nullptr, nullptr, s);
+    axpy_blocks(c, dt, a[i], u, c->d_k, c->d_st[i], s);
+    prev = c->d_st[i];
+  }
+  hip_check(hipMemcpyAsync(c->d_lc, lam_np1, c->total_len * sizeof(double),
+                           hipMemcpyDeviceToDevice, s), "copy");
+  // acc = lam; kb = dt/6 lam ; then per stage (from the last): w = J(u_s)^T kb,
+  // acc += w, kb = b_{s-1} dt lam + a_s dt w
+  rk_adj_blocks(c, dt, 1.0 / 6, 0.0, lam_n, 1, false, s);
+  const double *stages[4] = {c->d_st[2], c->d_st[1], c->d_st[0], u};
+  static const double ca[3] = {1.0 / 3, 1.0 / 3, 1.0 / 6};
+  static const double cb[3] = {1.0, 0.5, 0.5};
+  for (int i = 0; i < 4; ++i) {
+    rhs_adjoint_chain(c, stages[i], c->d_kb, c->d_w, s);
+    if (i < 3) rk_adj_blocks(c, dt, ca[i], cb[i], lam_n, 0, false, s);
+    else rk_adj_blocks(c, dt, 0.0, 0.0, lam_n, 0, true, s);
+  }
+}
+
 // One classical RK4 step of u in place: k_s = R(stage_s), with
 // acc = u + dt/6 k1 + dt/3 k2 + dt/3 k3 and u <- acc + dt/6 k4.
 void rk4_step(fr_ctx *c, double *u, const double *dt, hipStream_t s) {
@@ -589,15 +749,29 @@ fr_status fr_rk_step(fr_ctx *c, double *u, const double *dt_dev, int32_t nsteps,
 fr_status fr_rhs_adjoint(fr_ctx *c, const double *u, const double *lam, double *ulam,
                          void *hip_stream) {
   if (!c) return FR_EINVAL;
-  (void)u; (void)lam; (void)ulam; (void)hip_stream;
-  return fail(c, FR_EUNSUPPORTED, "adjoint not available in this build");
+  if (!u || !lam || !ulam || ulam == u || ulam == lam)
+    return fail(c, FR_EINVAL, "bad adjoint arguments (ulam must not alias u or lam)");
+  try {
+    hipStream_t s = (hipStream_t)hip_stream;
+    ensure_adjoint(c, s);
+    rhs_adjoint_chain(c, u, lam, ulam, s);
+  } catch (const Fail &f) {
+    return fail(c, f.st, f.msg);
+  }
+  return FR_OK;
 }
 
 fr_status fr_rk_step_adjoint(fr_ctx *c, const double *u_n, const double *dt_dev,
                              const double *lam_np1, double *lam_n, void *hip_stream) {
   if (!c) return FR_EINVAL;
-  (void)u_n; (void)dt_dev; (void)lam_np1; (void)lam_n; (void)hip_stream;
-  return fail(c, FR_EUNSUPPORTED, "adjoint not available in this build");
+  if (!u_n || !dt_dev || !lam_np1 || !lam_n || lam_n == u_n)
+    return fail(c, FR_EINVAL, "bad step adjoint arguments");
+  try {
+    rk4_step_adjoint(c, u_n, dt_dev, lam_np1, lam_n, (hipStream_t)hip_stream);
+  } catch (const Fail &f) {
+    return fail(c, f.st, f.msg);
+  }
+  return FR_OK;
 }
 
 fr_status fr_integrate(fr_ctx *c, const double *u, int32_t kind, double *out, void *hip_stream) {
@@ -830,6 +1004,21 @@ fr_status fr_get_gemm_plan(const fr_ctx *c, int32_t block, int32_t step, int32_t
   const GemmOp *op = step == 1 ? &b.m0 : step == 3 ? &b.s3 : step == 5 ? &b.m5 : step == 8 ? &b.s8 : nullptr;
   if (!op || (!c->ns && (step == 3 || step == 5))) return FR_EINVAL;
   *mbw = op->MBW; *nc = op->NC; *wm = op->WM;
+  return FR_OK;
+}
+
+fr_status fr_integrate_grad(fr_ctx *c, const double *u, int32_t kind, double *grad,
+                            void *hip_stream) {
+  if (!c) return FR_EINVAL;
+  if (!u || !grad || kind != 1) return fail(c, FR_EINVAL, "bad integrate_grad arguments");
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    for (auto &b : c->blocks)
+      hip_check(fr::launch_ke_grad(c->NV, c->D, b.Nu, b.ld, b.nelem, b.d_wdjac, u + b.uoff,
+                                   grad + b.uoff, s), "ke grad");
+  } catch (const Fail &f) {
+    return fail(c, f.st, f.msg);
+  }
   return FR_OK;
 }
 

@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     const int64_t s0 = n0 + 16 * c;
     const int64_t colg = s0 + col;
     int64_t n = 0;
-    if (EPI != EPI_STORE) n = colg - (s0 / g.ld) * g.ld;
+    if (EPI == EPI_NEGDIV || EPI == EPI_RK) n = colg - (s0 / g.ld) * g.ld;
     const bool live = n < g.nelem;
     double dtv = 0;
     if (EPI == EPI_RK && live) dtv = g.dt[g.prob ? g.prob[n] : 0];
@@ -129,6 +129,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         const int64_t idx = (int64_t)row * g.ldc + colg;
         if (EPI == EPI_STORE) {
           ((TC *)g.C)[(int64_t)blockIdx.y * g.sC + idx] = (TC)v;
+        } else if (EPI == EPI_ADD) {
+          TC *cp = (TC *)g.C + (int64_t)blockIdx.y * g.sC + idx;
+          *cp = (TC)((double)*cp + v);
         } else {
           const double k = live ? -g.rcpdjac[(int64_t)row * g.ld + n] * v : 0.0;
           if (EPI == EPI_NEGDIV) {
@@ -161,7 +164,7 @@ hipError_t launch_gemm_shape(const GemmArgs &g, int batch, hipStream_t s) {
   dim3 grid((unsigned)((waves + 3) / 4), batch), block(256);
   if constexpr (sizeof(T) == 8) {
     gemm_kernel<T, MBW, NC, EPI, double, double, double><<<grid, block, 0, s>>>(g);
-  } else if constexpr (EPI != EPI_STORE) {
+  } else if constexpr (EPI == EPI_NEGDIV || EPI == EPI_RK) {
     gemm_kernel<T, MBW, NC, EPI, float, float, double><<<grid, block, 0, s>>>(g);
   } else {
     if (!g.b1_f32)

@@ -15,7 +15,8 @@ namespace fr {
 enum GemmEpi {
   EPI_STORE = 0,   // C[row][col] = acc                         (C of type TC)
   EPI_NEGDIV = 1,  // out = -rcpdjac[row][n] * acc, 0 for padding  (FP64 out)
-  EPI_RK = 2       // RK4 stage update from k = -rcpdjac * acc      (FP64 regs)
+  EPI_RK = 2,      // RK4 stage update from k = -rcpdjac * acc      (FP64 regs)
+  EPI_ADD = 3      // C[row][col] += acc (FP64 only; adjoint accumulation)
 };
 
 enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };

@@ -16,97 +16,9 @@
 #include <cstring>
 #include <vector>
 
+#include "physics.h"
+
 namespace fr {
-
-// ============================================================================
-// Physics (device): Euler flux, viscous flux, Rusanov and LDG fluxes
-// ============================================================================
-template <int D>
-__device__ __forceinline__ void primitives(const double *u, double gamma, double &rho, double *v,
-                                           double &p) {
-  rho = u[0];
-  const double ir = 1.0 / rho;
-  double ke = 0;
-#pragma unroll
-  for (int i = 0; i < D; ++i) { v[i] = u[1 + i] * ir; ke += u[1 + i] * v[i]; }
-  p = (gamma - 1.0) * (u[D + 1] - 0.5 * ke);
-}
-
-// f[j][alpha] of the Euler equations
-template <int D>
-__device__ __forceinline__ void inviscid_flux(const double *u, double gamma, double f[D][D + 2],
-                                              double &p, double *v) {
-  double rho;
-  primitives<D>(u, gamma, rho, v, p);
-#pragma unroll
-  for (int j = 0; j < D; ++j) {
-    f[j][0] = u[1 + j];
-#pragma unroll
-    for (int i = 0; i < D; ++i) f[j][1 + i] = u[1 + i] * v[j] + (i == j ? p : 0.0);
-    f[j][D + 1] = (u[D + 1] + p) * v[j];
-  }
-}
-
-// viscous flux fv[j][alpha] from u and q[j][alpha] = d_j u_alpha
-template <int D>
-__device__ __forceinline__ void viscous_flux(const double *u, const double q[D][D + 2],
-                                             double gamma, double mu, double prandtl,
-                                             double fv[D][D + 2]) {
-  double rho, v[D], p;
-  primitives<D>(u, gamma, rho, v, p);
-  const double ir = 1.0 / rho;
-  double dv[D][D];  // dv[j][i] = d_j v_i
-#pragma unroll
-  for (int j = 0; j < D; ++j)
-#pragma unroll
-    for (int i = 0; i < D; ++i) dv[j][i] = (q[j][1 + i] - v[i] * q[j][0]) * ir;
-  double divv = 0;
-#pragma unroll
-  for (int k = 0; k < D; ++k) divv += dv[k][k];
-  double v2 = 0;
-#pragma unroll
-  for (int i = 0; i < D; ++i) v2 += v[i] * v[i];
-  const double kappa = mu * gamma / (prandtl * (gamma - 1.0));
-  const double por = p * ir;
-#pragma unroll
-  for (int j = 0; j < D; ++j) {
-    double vdm = 0;
-#pragma unroll
-    for (int i = 0; i < D; ++i) vdm += v[i] * q[j][1 + i];
-    const double dp = (gamma - 1.0) * (q[j][D + 1] - vdm + 0.5 * v2 * q[j][0]);
-    const double dT = (dp - por * q[j][0]) * ir;
-    double e = kappa * dT;
-    fv[j][0] = 0.0;
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      double tau = mu * (dv[i][j] + dv[j][i]);
-      if (i == j) tau -= 2.0 / 3.0 * mu * divv;
-      fv[j][1 + i] = tau;
-      e += v[i] * tau;
-    }
-    fv[j][D + 1] = e;
-  }
-}
-
-// Rusanov flux (Appendix B) in direction n of the left side
-template <int D>
-__device__ __forceinline__ void rusanov(const double *uL, const double *uR, const double *n,
-                                        double gamma, double *F) {
-  double fL[D][D + 2], fR[D][D + 2], vL[D], vR[D], pL, pR;
-  inviscid_flux<D>(uL, gamma, fL, pL, vL);
-  inviscid_flux<D>(uR, gamma, fR, pR, vR);
-  double vn = 0;
-#pragma unroll
-  for (int j = 0; j < D; ++j) vn += n[j] * (vL[j] + vR[j]);
-  const double s = sqrt(gamma * (pL + pR) / (uL[0] + uR[0])) + 0.5 * fabs(vn);
-#pragma unroll
-  for (int a = 0; a < D + 2; ++a) {
-    double nf = 0;
-#pragma unroll
-    for (int j = 0; j < D; ++j) nf += n[j] * (fL[j][a] + fR[j][a]);
-    F[a] = 0.5 * nf + 0.5 * s * (uL[a] - uR[a]);
-  }
-}
 
 // ============================================================================
 // Point-wise kernels

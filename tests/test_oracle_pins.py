@@ -534,3 +534,41 @@ def test_ldg_compact_stencil(beta):
     block = {(i + a) % n + n * ((j + b) % n) for a in (-1, 0, 1) for b in (-1, 0, 1)}
     got = set(changed.tolist())
     assert faces <= got <= block
+
+
+# --------------------------------------------------------------------------
+# Complex-step JVP of the right-hand side and of an RK4 step
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["vortex", "mixed_ns", "tgv"])
+def test_jvp_matches_central_differences(case):
+    from oracle import jvp, rk4_jvp
+    if case == "vortex":
+        w = configs.vortex_quads(4, 3)
+    elif case == "mixed_ns":
+        w = _mixed(4, 2, system="ns")
+    else:
+        w = configs.taylor_green_hexes(2, 2)
+    d = Discretisation(w)
+    u = d.initial_state(w)
+    rng = np.random.default_rng(3)
+    v = [rng.standard_normal(x.shape) * np.abs(x).mean(axis=(0, 2), keepdims=True) for x in u]
+    J = jvp(d, u, v)
+    eps = 1e-6
+    up = d.rhs([a + eps * b for a, b in zip(u, v)])
+    um = d.rhs([a - eps * b for a, b in zip(u, v)])
+    fd = [(a - b) / (2 * eps) for a, b in zip(up, um)]
+    num = np.sqrt(sum(np.sum((a - b) ** 2) for a, b in zip(J, fd)))
+    den = np.sqrt(sum(np.sum(b ** 2) for b in fd))
+    # central differences carry O(eps^2) truncation and O(1e-16 |R| / eps)
+    # rounding error; an incorrect JVP would be off by O(1)
+    assert num / den < 3e-5
+    # linearity in the direction (exact up to rounding)
+    J2 = jvp(d, u, [2.0 * x for x in v])
+    assert max(np.abs(a - 2 * b).max() for a, b in zip(J2, J)) < 1e-9 * max(np.abs(b).max() for b in J)
+    Jr = rk4_jvp(d, u, v, w.dt)
+    upr = d.rk4_step([a + eps * b for a, b in zip(u, v)], w.dt)
+    umr = d.rk4_step([a - eps * b for a, b in zip(u, v)], w.dt)
+    fdr = [(a - b) / (2 * eps) for a, b in zip(upr, umr)]
+    num = np.sqrt(sum(np.sum((a - b) ** 2) for a, b in zip(Jr, fdr)))
+    den = np.sqrt(sum(np.sum(b ** 2) for b in fdr))
+    assert num / den < 1e-6
