@@ -134,6 +134,41 @@ def time_kernels(s, u, torch, nrep=50):
     return out
 
 
+def adjoint_ratio(P, configs, torch, n=24, nsteps=200, ckpt=20):
+    """Wall time of the full gradient of E_k(u_N) with respect to u_0 (forward
+    with checkpoints, segment replay, hand-written RK4 adjoint) over the wall
+    time of the N forward steps: Taylor-Green, n^3 hexes, p=3, FP64."""
+    import numpy as np
+    from paper_1312_1638_amd.autograd import KineticEnergy, integrate_steps
+    w = configs.adjoint_tgv(n=n, order=3, nsteps=nsteps, ckpt=ckpt)
+    s = P.Solver(w.mesh, system=w.system, gamma=w.gamma, mu=w.mu, prandtl=w.prandtl,
+                 ldg_beta=w.ldg_beta, ldg_tau=w.ldg_tau)
+    u0h = [np.ascontiguousarray(np.transpose(w.ic(b, s.solution_points(b)), (1, 2, 0)))
+           for b in range(len(w.mesh.blocks))]
+    u0 = s.pack(u0h)
+    x = u0.clone()
+    s.step(x, w.dt, 2)                      # capture the step graph, warm
+    x.copy_(u0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(x, w.dt, nsteps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    u0g = u0.clone().requires_grad_(True)
+    J = KineticEnergy.apply(integrate_steps(s, u0g, w.dt, 1, 1), s)   # warm the adjoint
+    torch.autograd.grad(J, u0g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = KineticEnergy.apply(integrate_steps(s, u0g, w.dt, nsteps, ckpt), s)
+    (g,) = torch.autograd.grad(J, u0g)
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    s.close()
+    return dict(value=t_grad / t_fwd, unit="gradient wall time / forward wall time",
+                workload=w.name, steps=nsteps, checkpoint_every=ckpt,
+                forward_s=t_fwd, gradient_s=t_grad, objective="kinetic energy at t_N")
+
+
 def cpu_baseline(w, nsteps):
     """The FP64 oracle on the host: nsteps RK4 steps of the same workload."""
     import numpy as np
@@ -164,6 +199,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2,
                     help="RK4 steps of the oracle for the CPU baseline (0: skip)")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -215,12 +251,17 @@ def main():
 
     extra = {}
     if not args.no_fp32:
-        w32, s32, _ = make_solver(args.workload, "fp32", P, configs)
-        u32 = s32.pack(u0)
-        el32 = time_steps(s32, u32, w.dt, args.steps, args.warmup, torch)
-        extra["fp32"] = dict(value=4.0 * dof * args.steps / el32,
-                             ms_per_step=el32 / args.steps * 1e3)
-        s32.close()
+        for prec in ("fp32", "bf16x3"):
+            wr, sr, _ = make_solver(args.workload, prec, P, configs)
+            ur = sr.pack(u0)
+            elr = time_steps(sr, ur, w.dt, args.steps, args.warmup, torch)
+            ktr = time_kernels(sr, sr.pack(u0), torch)
+            extra[prec] = dict(value=4.0 * dof * args.steps / elr, ms_per_step=elr / args.steps * 1e3,
+                               kernels_us={STEP_NAMES[k]: round(v * 1e6, 2) for k, v in ktr.items()})
+            sr.close()
+
+    if not args.no_adjoint:
+        extra["adjoint"] = adjoint_ratio(P, configs, torch)
 
     cpu = None
     if args.cpu_steps > 0:

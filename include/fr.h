@@ -140,6 +140,20 @@ fr_status fr_rhs_adjoint(fr_ctx *ctx, const double *u, const double *lam, double
 fr_status fr_rk_step_adjoint(fr_ctx *ctx, const double *u_n, const double *dt_dev,
                              const double *lam_np1, double *lam_n, void *hip_stream);
 
+/* Stashed RK4 step and its adjoint (checkpointed gradients without
+ * recomputation).  fr_stash_len gives the size (float64 elements) of one
+ * step's stash.  fr_rk_step_stash advances u by one RK4 step like
+ * fr_rk_step (not through the graph) and leaves in `stash` (DEVICE, caller
+ * owned) the four stage states and their primal intermediates.
+ * fr_rk_step_adjoint_stash computes lam_n = (d u_{n+1}/d u_n)^T lam_np1 from
+ * that stash with no recomputation; lam_n may alias lam_np1.  FP64 contexts
+ * only (FR_EUNSUPPORTED otherwise). */
+fr_status fr_stash_len(const fr_ctx *ctx, int64_t *len);
+fr_status fr_rk_step_stash(fr_ctx *ctx, double *u, const double *dt_dev, double *stash,
+                           void *hip_stream);
+fr_status fr_rk_step_adjoint_stash(fr_ctx *ctx, double *stash, const double *dt_dev,
+                                   const double *lam_np1, double *lam_n, void *hip_stream);
+
 /* Integrals of the state by quadrature at the solution points (paper's
  * validation section: sums of W J times the integrand).  kind must be 0:
  * out (DEVICE float64) [nproblems][nvars + 1] receives, per problem, the

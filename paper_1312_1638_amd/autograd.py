@@ -2,9 +2,11 @@
 
 Forward: nsteps classical RK4 steps (the library's captured step graph),
 keeping the state every `ckpt` steps.  Backward: segments from last to
-first; each segment is replayed forward from its checkpoint (states kept in
-device memory), then the hand-written RK4 step adjoint of the library is
-applied step by step in reverse.  Torch holds the tensors; all arithmetic
+first; each segment is replayed forward from its checkpoint with the
+library's stashing step (stage states and primal intermediates of every step
+kept in device memory, ~40 states per step for Navier-Stokes), then the
+hand-written RK4 step adjoint consumes the stash step by step in reverse
+with no recomputation.  Torch holds the tensors; all arithmetic
 runs in the HIP library.
 """
 from __future__ import annotations
@@ -29,16 +31,18 @@ class FRSteps(torch.autograd.Function):
         s, dt, ckpt = ctx.solver, ctx.dt, ctx.ckpt
         lam = lam_out.detach().contiguous().clone()
         work = torch.empty_like(lam)
+        # one segment's stash: stage states and primal intermediates of every
+        # step, written by the replay and read by the step adjoints
+        L = s.stash_len()
+        stash = torch.empty(ckpt * L, dtype=torch.float64, device=lam.device)
         for seg in reversed(range(len(ctx.ckpts))):
             n0 = seg * ckpt
             n1 = min(ctx.nsteps, n0 + ckpt)
-            states = [ctx.ckpts[seg]]
             work.copy_(ctx.ckpts[seg])
-            for _ in range(n0, n1 - 1):
-                s.step(work, dt, 1)
-                states.append(work.clone())
-            for u_n in reversed(states):
-                s.rk_step_adjoint(u_n, dt, lam, out=lam)
+            for i in range(n1 - n0):
+                s.step_stash(work, dt, stash[i * L:(i + 1) * L])
+            for i in reversed(range(n1 - n0)):
+                s.rk_step_adjoint_stash(stash[i * L:(i + 1) * L], dt, lam, out=lam)
         return lam, None, None, None, None
 
 

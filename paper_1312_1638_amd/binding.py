@@ -24,7 +24,8 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 EXPORTS = ("fr_setup_mesh", "fr_get_layout", "fr_get_solution_points", "fr_get_quadrature",
            "fr_rhs", "fr_rk_step", "fr_rhs_adjoint", "fr_rk_step_adjoint", "fr_integrate",
            "fr_reference_operator", "fr_check_mesh", "fr_debug_stage", "fr_debug_scratch_len", "fr_bench_step",
-           "fr_debug_gemm", "fr_measure_ceiling", "fr_bench_gemm", "fr_get_gemm_plan", "fr_integrate_grad",
+           "fr_debug_gemm", "fr_measure_ceiling", "fr_bench_gemm", "fr_get_gemm_plan", "fr_integrate_grad", "fr_stash_len", "fr_rk_step_stash",
+           "fr_rk_step_adjoint_stash",
            "fr_last_error", "fr_destroy")
 
 
@@ -79,6 +80,9 @@ def load_library(path: str = LIB_PATH):
         "fr_rk_step_adjoint": [vp, dp, dp, dp, dp, vp],
         "fr_integrate": [vp, dp, i32, dp, vp],
         "fr_integrate_grad": [vp, dp, i32, dp, vp],
+        "fr_stash_len": [vp, ctypes.POINTER(i64)],
+        "fr_rk_step_stash": [vp, dp, dp, dp, vp],
+        "fr_rk_step_adjoint_stash": [vp, dp, dp, dp, dp, vp],
         "fr_reference_operator": [i32, i32, i32, dp, i64, ctypes.POINTER(i32),
                                   ctypes.POINTER(i32)],
         "fr_check_mesh": [ctypes.POINTER(FrConfig), i32, ctypes.POINTER(FrBlock), i64, vp,
@@ -332,6 +336,28 @@ class Solver:
         """Launch right-hand-side step `step` nrep times (after preparing its
         inputs) on the current stream; for kernel timing."""
         _check(self.L.fr_bench_step(self.ctx, self._ptr(u), step, nrep, self._stream()), self.ctx)
+
+    def stash_len(self):
+        n = ctypes.c_int64()
+        _check(self.L.fr_stash_len(self.ctx, ctypes.byref(n)), self.ctx)
+        return n.value
+
+    def step_stash(self, u, dt, stash):
+        """One RK4 step in place on u, keeping stage states and intermediates."""
+        d = self.dt_tensor(dt)
+        assert stash.dtype == self.torch.float64 and stash.numel() >= self.stash_len()
+        _check(self.L.fr_rk_step_stash(self.ctx, self._ptr(u), d.data_ptr(), stash.data_ptr(),
+                                       self._stream()), self.ctx)
+        return u
+
+    def rk_step_adjoint_stash(self, stash, dt, lam, out=None):
+        if out is None:
+            out = self.empty()
+        d = self.dt_tensor(dt)
+        _check(self.L.fr_rk_step_adjoint_stash(self.ctx, stash.data_ptr(), d.data_ptr(),
+                                               self._ptr(lam), self._ptr(out), self._stream()),
+               self.ctx)
+        return out
 
     def kinetic_energy_grad(self, u, out=None):
         """d(sum of kinetic energy integrals)/du, state layout."""

@@ -72,7 +72,14 @@ struct fr_ctx {
   hipGraphExec_t graph_exec = nullptr;
   const double *graph_u = nullptr, *graph_dt = nullptr;
   // adjoint scratch (allocated on first use, FP64 contexts only)
-  bool adj_ready = false;
+  // arrays the right-hand-side chain uses (default: the scratch above, with
+  // D~ over U^f and F~ over Q as the paper aliases them; the stash path points
+  // U^f, Q^f, Q into caller memory and the outputs into scratch)
+  struct Bufs {
+    void *uf, *qf, *ft, *df, *fto;
+    double *stage_out;
+  } cur{};
+  bool adj_ready = false, adj_tuned = false;
   double *d_ufb = nullptr, *d_ftb = nullptr, *d_qfb = nullptr, *d_lt = nullptr;
   double *d_lc = nullptr, *d_kb = nullptr, *d_w = nullptr, *d_k = nullptr;
   double *d_st[3] = {nullptr, nullptr, nullptr};
@@ -114,8 +121,10 @@ T *dev_upload(fr_ctx *c, const T *h, size_t n, hipStream_t s) {
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 void *pack_upload(fr_ctx *c, const GemmOp &op, fr::GemmPlan p, hipStream_t s, bool track) {
-  const int64_t n = fr::gemm_pack_size(op.M, op.K1, op.K2, p.MBW, p.WM, 4);
-  const size_t es = c->prec == FR_FP64 ? 8 : 4;
+  const bool bf = c->prec == FR_BF16X3;
+  const int64_t n = bf ? fr::gemm_pack_size_bf16(op.M, op.K1, op.K2, p.MBW, p.WM)
+                       : fr::gemm_pack_size(op.M, op.K1, op.K2, p.MBW, p.WM, 4);
+  const size_t es = c->prec == FR_FP64 ? 8 : (bf ? 2 : 4);
   void *d = nullptr;
   hipError_t e = hipMalloc(&d, n * es);
   if (e != hipSuccess) throw Fail{FR_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)};
@@ -123,6 +132,11 @@ void *pack_upload(fr_ctx *c, const GemmOp &op, fr::GemmPlan p, hipStream_t s, bo
   if (c->prec == FR_FP64) {
     std::vector<double> pk(n);
     fr::gemm_pack_f64(op.A.data(), op.M, op.K1, op.K2, p.MBW, p.WM, pk.data());
+    hip_check(hipMemcpyAsync(d, pk.data(), n * es, hipMemcpyHostToDevice, s), "upload");
+    hip_check(hipStreamSynchronize(s), "upload sync");
+  } else if (bf) {
+    std::vector<uint16_t> pk(n);
+    fr::gemm_pack_bf16x3(op.A.data(), op.M, op.K1, op.K2, p.MBW, p.WM, pk.data());
     hip_check(hipMemcpyAsync(d, pk.data(), n * es, hipMemcpyHostToDevice, s), "upload");
     hip_check(hipStreamSynchronize(s), "upload sync");
   } else {
@@ -137,8 +151,9 @@ void *pack_upload(fr_ctx *c, const GemmOp &op, fr::GemmPlan p, hipStream_t s, bo
 void make_op(fr_ctx *c, GemmOp &op, const std::vector<double> &A, int M, int K1, int K2,
              int64_t N, hipStream_t s, fr::GemmPlan *force = nullptr) {
   op.M = M; op.K1 = K1; op.K2 = K2;
-  op.KS1 = (K1 + 3) / 4;
-  op.KS2 = (K2 + 3) / 4;
+  const int kstep = c->prec == FR_BF16X3 ? 32 : 4;
+  op.KS1 = (K1 + kstep - 1) / kstep;
+  op.KS2 = (K2 + kstep - 1) / kstep;
   op.A = A;
   fr::GemmPlan p = force ? *force : fr::gemm_plan(M, N, c->prec);
   op.MBW = p.MBW; op.NC = p.NC; op.WM = p.WM;
@@ -180,7 +195,8 @@ fr::PairArgs pair_args(fr_ctx *c) {
   pa.lblk = c->blocks.size() > 1 ? c->d_lblk : nullptr;
   pa.rblk = c->blocks.size() > 1 ? c->d_rblk : nullptr;
   pa.nrm = c->d_nrm; pa.magL = c->d_magL; pa.magR = c->d_magR;
-  pa.uf = c->d_uf; pa.uf_f32 = c->prec != FR_FP64; pa.cf = c->d_qf; pa.qf = c->d_qf;
+  pa.uf = c->cur.uf; pa.uf_f32 = c->prec != FR_FP64; pa.cf = c->cur.qf; pa.qf = c->cur.qf;
+  pa.dfout = c->cur.df != c->cur.uf ? c->cur.df : nullptr;
   pa.blk_ufbase = c->d_blk_ufbase; pa.blk_qfbase = c->d_blk_qfbase;
   pa.blk_ld = c->d_blk_ld; pa.blk_qstride = c->d_blk_qstride;
   pa.ld0 = c->blocks[0].ld;
@@ -195,7 +211,8 @@ fr::PointArgs point_args(fr_ctx *c, const BlockRT &b, const double *u) {
   std::memset(&p, 0, sizeof(p));
   p.ndims = c->D; p.nvars = c->NV; p.nupts = b.Nu; p.ld = b.ld; p.nelem = b.nelem;
   p.smat = b.d_smat; p.rcpdjac = b.d_rcpdjac; p.u = u + b.uoff;
-  p.q = elem(c->d_ft, b.ftoff, c->tsize); p.q_f32 = c->prec != FR_FP64;
+  p.q = elem(c->cur.ft, b.ftoff, c->tsize); p.q_f32 = c->prec != FR_FP64;
+  p.fout = c->cur.fto != c->cur.ft ? elem(c->cur.fto, b.ftoff, c->tsize) : nullptr;
   p.gamma = c->cfg.gamma; p.mu = c->cfg.mu; p.prandtl = c->cfg.prandtl;
   return p;
 }
@@ -214,7 +231,8 @@ void run_step(fr_ctx *c, int st, const double *u, double *dudt, int epi, const f
   const int D = c->D, NV = c->NV;
   const size_t ts = c->tsize;
   const int f32 = c->prec != FR_FP64;
-  const int gprec = f32 ? fr::PREC_F32 : fr::PREC_F64;
+  const int gprec = c->prec == FR_FP64 ? fr::PREC_F64
+                    : (c->prec == FR_FP32 ? fr::PREC_F32 : fr::PREC_BF16X3);
   if (!c->ns && st >= 2 && st <= 5) return;
   if (st == 2) { hip_check(fr::launch_con_u(pair_args(c), s), "con_u"); return; }
   if (st == 7) { hip_check(fr::launch_comm_flux(pair_args(c), c->ns, s), "comm_flux"); return; }
@@ -223,22 +241,22 @@ void run_step(fr_ctx *c, int st, const double *u, double *dudt, int epi, const f
     if (st == 1) {
       fr::GemmArgs g = gemm_args(b.m0);
       g.B1 = u + b.uoff; g.ldb1 = N; g.b1_f32 = 0;
-      g.C = elem(c->d_uf, b.ufoff, ts); g.ldc = N; g.c_f32 = f32;
+      g.C = elem(c->cur.uf, b.ufoff, ts); g.ldc = N; g.c_f32 = f32;
       g.N = N;
       hip_check(fr::launch_gemm(gprec, fr::EPI_STORE, g, 1, s), "gemm M0");
     } else if (st == 3) {
       fr::GemmArgs g = gemm_args(b.s3);
-      g.B1 = elem(c->d_qf, b.qfoff, ts); g.ldb1 = N; g.b1_f32 = f32;
+      g.B1 = elem(c->cur.qf, b.qfoff, ts); g.ldb1 = N; g.b1_f32 = f32;
       g.B2 = u + b.uoff; g.ldb2 = N; g.b2_f32 = 0;
-      g.C = elem(c->d_ft, b.ftoff, ts); g.ldc = N; g.c_f32 = f32;
+      g.C = elem(c->cur.ft, b.ftoff, ts); g.ldc = N; g.c_f32 = f32;
       g.N = N;
       hip_check(fr::launch_gemm(gprec, fr::EPI_STORE, g, 1, s), "gemm M6|M4'");
     } else if (st == 4) {
       hip_check(fr::launch_gradcoru(point_args(c, b, u), s), "gradcoru");
     } else if (st == 5) {
       fr::GemmArgs g = gemm_args(b.m5);
-      g.B1 = elem(c->d_ft, b.ftoff, ts); g.ldb1 = N; g.b1_f32 = f32; g.b2_f32 = f32;
-      g.C = elem(c->d_qf, b.qfoff, ts); g.ldc = N; g.c_f32 = f32;
+      g.B1 = elem(c->cur.ft, b.ftoff, ts); g.ldb1 = N; g.b1_f32 = f32; g.b2_f32 = f32;
+      g.C = elem(c->cur.qf, b.qfoff, ts); g.ldc = N; g.c_f32 = f32;
       g.N = N;
       g.sB1 = (int64_t)b.Nu * N;
       g.sC = (int64_t)b.Nf * N;
@@ -247,14 +265,14 @@ void run_step(fr_ctx *c, int st, const double *u, double *dudt, int epi, const f
       hip_check(fr::launch_tflux(point_args(c, b, u), c->ns, s), "tflux");
     } else if (st == 8) {
       fr::GemmArgs g = gemm_args(b.s8);
-      g.B1 = elem(c->d_uf, b.ufoff, ts); g.ldb1 = N; g.b1_f32 = f32;
-      g.B2 = elem(c->d_ft, b.ftoff, ts); g.ldb2 = N; g.b2_f32 = f32;
+      g.B1 = elem(c->cur.df, b.ufoff, ts); g.ldb1 = N; g.b1_f32 = f32;
+      g.B2 = elem(c->cur.fto, b.ftoff, ts); g.ldb2 = N; g.b2_f32 = f32;
       g.ldc = N; g.N = N;
       g.rcpdjac = b.d_rcpdjac; g.ld = b.ld; g.nelem = b.nelem;
       g.out = dudt + b.uoff;
       if (epi == fr::EPI_RK) {
         g.acc = c->d_acc + b.uoff;
-        g.stage = c->d_stage + b.uoff;
+        g.stage = c->cur.stage_out ? c->cur.stage_out + b.uoff : nullptr;
         g.dt = dt; g.prob = b.d_prob; g.rk = *rk;
       }
       hip_check(fr::launch_gemm(gprec, epi, g, 1, s), "gemm M3|M1'");
@@ -371,6 +389,7 @@ void ensure_adjoint(fr_ctx *c, hipStream_t s) {
     }
   }
   c->adj_ready = true;
+  c->adj_tuned = !c->cfg.autotune;
 }
 
 fr::AdjPairArgs adj_pair_args(fr_ctx *c) {
@@ -401,13 +420,86 @@ void adj_gemm(fr_ctx *c, const GemmOp &op, const double *B1, const double *B2, d
   hip_check(fr::launch_gemm(fr::PREC_F64, epi, g, batch, s), "adjoint gemm");
 }
 
+// Autotune one transposed operator of the adjoint with its real operands.
+void tune_adj(fr_ctx *c, GemmOp &op, const double *B1, const double *B2, double *C, int64_t N,
+              int epi, int batch, int64_t sB1, int64_t sC, hipStream_t s) {
+  TuneKey key{c->prec, op.M, op.K1, op.K2, batch, 10 + epi, N};
+  fr::GemmPlan best{op.MBW, op.NC, op.WM};
+  auto it = g_tuned.find(key);
+  if (it != g_tuned.end()) {
+    best = it->second;
+  } else {
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "event");
+    hip_check(hipEventCreate(&e1), "event");
+    float best_ms = 1e30f;
+    for (const fr::GemmPlan &p : fr::gemm_candidates(op.M, batch * N, c->prec)) {
+      GemmOp trial = op;
+      trial.d_A = pack_upload(c, op, p, s, false);
+      trial.MBW = p.MBW; trial.NC = p.NC; trial.WM = p.WM;
+      float ms = 0;
+      try {
+        for (int w = 0; w < 2; ++w) adj_gemm(c, trial, B1, B2, C, N, epi, batch, sB1, sC, s);
+        hip_check(hipEventRecord(e0, s), "record");
+        for (int w = 0; w < 5; ++w) adj_gemm(c, trial, B1, B2, C, N, epi, batch, sB1, sC, s);
+        hip_check(hipEventRecord(e1, s), "record");
+        hip_check(hipEventSynchronize(e1), "sync");
+        hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+      } catch (...) {
+        hipFree(trial.d_A);
+        throw;
+      }
+      hipFree(trial.d_A);
+      if (ms < best_ms) { best_ms = ms; best = p; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    g_tuned[key] = best;
+  }
+  if (best.MBW != op.MBW || best.NC != op.NC || best.WM != op.WM) {
+    op.d_A = pack_upload(c, op, best, s, true);
+    op.MBW = best.MBW; op.NC = best.NC; op.WM = best.WM;
+  }
+}
+
 // ulam = (dR/du)(u)^T lam, the reverse of rhs_chain
-void rhs_adjoint_chain(fr_ctx *c, const double *u, const double *lam, double *ulam,
-                       hipStream_t s) {
+struct Primal {
+  const double *uf, *qf, *q;  // U^f, Q^f, Q of the state (null: recompute)
+};
+
+void tune_adjoint_ops(fr_ctx *c, hipStream_t s) {
   const int D = c->D, NV = c->NV;
-  // primal intermediates: U^f (and C^f -> Q, Q^f for Navier-Stokes)
-  rhs_chain(c, u, nullptr, fr::EPI_NEGDIV, nullptr, nullptr, s, c->ns ? 5 : 1);
-  double *ft = (double *)c->d_ft;
+  for (auto &b : c->blocks) {
+    const int64_t N = (int64_t)NV * b.ld;
+    tune_adj(c, b.t_m3, c->d_lt + b.uoff, nullptr, c->d_ufb + b.ufoff, N, fr::EPI_STORE, 1, 0, 0, s);
+    tune_adj(c, b.t_m1, c->d_lt + b.uoff, nullptr, c->d_ftb + b.ftoff, N, fr::EPI_STORE, 1, 0, 0, s);
+    if (c->ns) {
+      tune_adj(c, b.t_m0, c->d_qfb + b.qfoff, nullptr, c->d_ftb + b.ftoff, N, fr::EPI_ADD, D,
+               (int64_t)b.Nf * N, (int64_t)b.Nu * N, s);
+      tune_adj(c, b.t_m6, c->d_ftb + b.ftoff, nullptr, c->d_qfb + b.qfoff, N, fr::EPI_STORE, 1, 0,
+               0, s);
+      tune_adj(c, b.t_fin, c->d_ftb + b.ftoff, c->d_ufb + b.ufoff, c->d_w + b.uoff, N,
+               fr::EPI_ADD, 1, 0, 0, s);
+    } else {
+      tune_adj(c, b.t_m0, c->d_ufb + b.ufoff, nullptr, c->d_w + b.uoff, N, fr::EPI_ADD, 1, 0, 0, s);
+    }
+  }
+  hip_check(hipStreamSynchronize(s), "tune sync");
+}
+
+void rhs_adjoint_chain(fr_ctx *c, const double *u, const double *lam, double *ulam,
+                       hipStream_t s, Primal pr = Primal{nullptr, nullptr, nullptr}) {
+  const int D = c->D, NV = c->NV;
+  if (!c->adj_tuned) {
+    c->adj_tuned = true;
+    tune_adjoint_ops(c, s);
+  }
+  if (!pr.uf) {
+    // primal intermediates: U^f (and C^f -> Q, Q^f for Navier-Stokes)
+    rhs_chain(c, u, nullptr, fr::EPI_NEGDIV, nullptr, nullptr, s, c->ns ? 5 : 1);
+    pr = Primal{(const double *)c->d_uf, (const double *)c->d_qf, (const double *)c->d_ft};
+  }
+  const double *ft = pr.q;
   for (auto &b : c->blocks) {
     const int64_t N = (int64_t)NV * b.ld;
     hip_check(fr::launch_negscale(NV, b.Nu, b.ld, b.nelem, b.d_rcpdjac, lam + b.uoff,
@@ -416,12 +508,16 @@ void rhs_adjoint_chain(fr_ctx *c, const double *u, const double *lam, double *ul
     adj_gemm(c, b.t_m3, c->d_lt + b.uoff, nullptr, c->d_ufb + b.ufoff, N, fr::EPI_STORE, 1, 0, 0, s);
     adj_gemm(c, b.t_m1, c->d_lt + b.uoff, nullptr, c->d_ftb + b.ftoff, N, fr::EPI_STORE, 1, 0, 0, s);
   }
-  hip_check(fr::launch_comm_flux_vjp(adj_pair_args(c), c->ns, s), "comm_flux_vjp");
+  {
+    fr::AdjPairArgs pa = adj_pair_args(c);
+    pa.uf = pr.uf; pa.qf = pr.qf;
+    hip_check(fr::launch_comm_flux_vjp(pa, c->ns, s), "comm_flux_vjp");
+  }
   for (auto &b : c->blocks) {
     fr::AdjPointArgs a;
     std::memset(&a, 0, sizeof(a));
     a.ndims = D; a.nvars = NV; a.nupts = b.Nu; a.ld = b.ld; a.nelem = b.nelem;
-    a.smat = b.d_smat; a.rcpdjac = b.d_rcpdjac; a.u = u + b.uoff; a.q = ft + b.ftoff;
+    a.smat = b.d_smat; a.rcpdjac = b.d_rcpdjac; a.u = u + b.uoff; a.q = ft ? ft + b.ftoff : nullptr;
     a.fb = c->d_ftb + b.ftoff; a.ulam = ulam + b.uoff;
     a.gamma = c->cfg.gamma; a.mu = c->cfg.mu; a.prandtl = c->cfg.prandtl;
     hip_check(fr::launch_tflux_vjp(a, c->ns, s), "tflux_vjp");
@@ -491,6 +587,66 @@ void rk4_step_adjoint(fr_ctx *c, const double *u, const double *dt, const double
   }
 }
 
+// Layout of one step's stash: for each stage s = 0..3 its input state, then
+// (FP64) U^f, Q^f and Q of that state (the last two for Navier-Stokes only).
+int64_t stash_stage_len(const fr_ctx *c) {
+  return c->total_len + c->uf_len + (c->ns ? c->qf_len + c->ft_len : 0);
+}
+
+struct StashStage {
+  double *state, *uf, *qf, *q;
+};
+
+StashStage stash_stage(const fr_ctx *c, double *stash, int st) {
+  double *p = stash + st * stash_stage_len(c);
+  StashStage r;
+  r.state = p; p += c->total_len;
+  r.uf = p; p += c->uf_len;
+  r.qf = c->ns ? p : nullptr; if (c->ns) p += c->qf_len;
+  r.q = c->ns ? p : nullptr;
+  return r;
+}
+
+// One RK4 step of u in place that leaves every stage state and its primal
+// intermediates in `stash` (out-of-place flux outputs keep them intact).
+void rk4_step_stash(fr_ctx *c, double *u, const double *dt, double *stash, hipStream_t s) {
+  static const double a_next[4] = {0.5, 0.5, 1.0, 0.0};
+  static const double bw[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
+  const fr_ctx::Bufs saved = c->cur;
+  try {
+    hip_check(hipMemcpyAsync(stash_stage(c, stash, 0).state, u, c->total_len * sizeof(double),
+                             hipMemcpyDeviceToDevice, s), "copy");
+    for (int st = 0; st < 4; ++st) {
+      StashStage S = stash_stage(c, stash, st);
+      c->cur = fr_ctx::Bufs{S.uf, c->ns ? (void *)S.qf : c->d_qf, c->ns ? (void *)S.q : c->d_ft,
+                            c->d_uf, c->d_ft, st < 3 ? stash_stage(c, stash, st + 1).state : nullptr};
+      fr::RkCoef rk;
+      rk.a_next = a_next[st]; rk.b = bw[st]; rk.first = st == 0; rk.last = st == 3;
+      rhs_chain(c, S.state, u, fr::EPI_RK, &rk, dt, s);
+    }
+  } catch (...) {
+    c->cur = saved;
+    throw;
+  }
+  c->cur = saved;
+}
+
+void rk4_step_adjoint_stash(fr_ctx *c, double *stash, const double *dt, const double *lam_np1,
+                            double *lam_n, hipStream_t s) {
+  ensure_adjoint(c, s);
+  hip_check(hipMemcpyAsync(c->d_lc, lam_np1, c->total_len * sizeof(double),
+                           hipMemcpyDeviceToDevice, s), "copy");
+  rk_adj_blocks(c, dt, 1.0 / 6, 0.0, lam_n, 1, false, s);
+  static const double ca[3] = {1.0 / 3, 1.0 / 3, 1.0 / 6};
+  static const double cb[3] = {1.0, 0.5, 0.5};
+  for (int i = 0; i < 4; ++i) {
+    StashStage S = stash_stage(c, stash, 3 - i);
+    rhs_adjoint_chain(c, S.state, c->d_kb, c->d_w, s, Primal{S.uf, S.qf, S.q});
+    if (i < 3) rk_adj_blocks(c, dt, ca[i], cb[i], lam_n, 0, false, s);
+    else rk_adj_blocks(c, dt, 0.0, 0.0, lam_n, 0, true, s);
+  }
+}
+
 // One classical RK4 step of u in place: k_s = R(stage_s), with
 // acc = u + dt/6 k1 + dt/3 k2 + dt/3 k3 and u <- acc + dt/6 k4.
 void rk4_step(fr_ctx *c, double *u, const double *dt, hipStream_t s) {
@@ -523,7 +679,7 @@ fr_status fr_setup_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *b
   if (cfg->ndims != 2 && cfg->ndims != 3) return fail(nullptr, FR_EINVAL, "ndims must be 2 or 3");
   if (cfg->system != FR_EULER && cfg->system != FR_NAVIER_STOKES)
     return fail(nullptr, FR_EINVAL, "bad system");
-  if (cfg->prec != FR_FP64 && cfg->prec != FR_FP32)
+  if (cfg->prec != FR_FP64 && cfg->prec != FR_FP32 && cfg->prec != FR_BF16X3)
     return fail(nullptr, FR_EUNSUPPORTED, "precision mode not available");
   if (!(cfg->gamma > 1.0)) return fail(nullptr, FR_EINVAL, "gamma must exceed 1");
   if (cfg->system == FR_NAVIER_STOKES && !(cfg->mu >= 0 && cfg->prandtl > 0))
@@ -641,6 +797,7 @@ fr_status fr_setup_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *b
                                     : (void *)dev_alloc<float>(c.get(), c->qf_len);
     c->d_acc = dev_alloc<double>(c.get(), c->total_len);
     c->d_stage = dev_alloc<double>(c.get(), c->total_len);
+    c->cur = fr_ctx::Bufs{c->d_uf, c->d_qf, c->d_ft, c->d_uf, c->d_ft, c->d_stage};
     // reductions: element partials and per-problem element lists
     c->d_part = dev_alloc<double>(c.get(), (size_t)c->nelem_total * (NV + 1));
     {
@@ -768,6 +925,37 @@ fr_status fr_rk_step_adjoint(fr_ctx *c, const double *u_n, const double *dt_dev,
     return fail(c, FR_EINVAL, "bad step adjoint arguments");
   try {
     rk4_step_adjoint(c, u_n, dt_dev, lam_np1, lam_n, (hipStream_t)hip_stream);
+  } catch (const Fail &f) {
+    return fail(c, f.st, f.msg);
+  }
+  return FR_OK;
+}
+
+fr_status fr_stash_len(const fr_ctx *c, int64_t *len) {
+  if (!c || !len) return FR_EINVAL;
+  *len = 4 * stash_stage_len(c);
+  return FR_OK;
+}
+
+fr_status fr_rk_step_stash(fr_ctx *c, double *u, const double *dt_dev, double *stash,
+                           void *hip_stream) {
+  if (!c) return FR_EINVAL;
+  if (!u || !dt_dev || !stash) return fail(c, FR_EINVAL, "bad stash step arguments");
+  if (c->prec != FR_FP64) return fail(c, FR_EUNSUPPORTED, "the adjoint is available for FP64 contexts");
+  try {
+    rk4_step_stash(c, u, dt_dev, stash, (hipStream_t)hip_stream);
+  } catch (const Fail &f) {
+    return fail(c, f.st, f.msg);
+  }
+  return FR_OK;
+}
+
+fr_status fr_rk_step_adjoint_stash(fr_ctx *c, double *stash, const double *dt_dev,
+                                   const double *lam_np1, double *lam_n, void *hip_stream) {
+  if (!c) return FR_EINVAL;
+  if (!stash || !dt_dev || !lam_np1 || !lam_n) return fail(c, FR_EINVAL, "bad stash adjoint arguments");
+  try {
+    rk4_step_adjoint_stash(c, stash, dt_dev, lam_np1, lam_n, (hipStream_t)hip_stream);
   } catch (const Fail &f) {
     return fail(c, f.st, f.msg);
   }
@@ -912,7 +1100,8 @@ fr_status fr_debug_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, const d
                         int32_t mbw, int32_t nc, int32_t wm, void *hip_stream) {
   if (!A || !B1 || !C || M < 1 || K1 < 1 || K2 < 0 || N < 16 || N % 16 || (K2 && !B2))
     return fail(nullptr, FR_EINVAL, "bad gemm arguments");
-  if (prec != FR_FP64 && prec != FR_FP32) return fail(nullptr, FR_EUNSUPPORTED, "precision");
+  if (prec != FR_FP64 && prec != FR_FP32 && prec != FR_BF16X3)
+    return fail(nullptr, FR_EUNSUPPORTED, "precision");
   hipStream_t s = (hipStream_t)hip_stream;
   fr_ctx tmp;
   tmp.prec = prec;
@@ -926,9 +1115,11 @@ fr_status fr_debug_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, const d
     fr::GemmArgs g = gemm_args(op);
     g.B1 = B1; g.ldb1 = ldb; g.b1_f32 = 0;
     g.B2 = B2; g.ldb2 = ldb; g.b2_f32 = 0;
-    g.C = C; g.ldc = N; g.c_f32 = prec == FR_FP32;
+    g.C = C; g.ldc = N; g.c_f32 = prec != FR_FP64;
     g.N = N;
-    hip_check(fr::launch_gemm(prec == FR_FP64 ? fr::PREC_F64 : fr::PREC_F32, fr::EPI_STORE, g, 1, s),
+    hip_check(fr::launch_gemm(prec == FR_FP64 ? fr::PREC_F64
+                              : (prec == FR_FP32 ? fr::PREC_F32 : fr::PREC_BF16X3),
+                              fr::EPI_STORE, g, 1, s),
               "gemm");
     hip_check(hipStreamSynchronize(s), "sync");
   } catch (const Fail &f) {
@@ -951,7 +1142,8 @@ fr_status fr_bench_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, int64_t
                         float *ms_per_launch, void *hip_stream) {
   if (!ms_per_launch || M < 1 || K1 < 1 || K2 < 0 || N < 16 || N % 16 || nrep < 1 || batch < 1)
     return fail(nullptr, FR_EINVAL, "bad gemm benchmark arguments");
-  if (prec != FR_FP64 && prec != FR_FP32) return fail(nullptr, FR_EUNSUPPORTED, "precision");
+  if (prec != FR_FP64 && prec != FR_FP32 && prec != FR_BF16X3)
+    return fail(nullptr, FR_EUNSUPPORTED, "precision");
   hipStream_t s = (hipStream_t)hip_stream;
   fr_ctx tmp;
   tmp.prec = prec;
@@ -971,7 +1163,7 @@ fr_status fr_bench_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, int64_t
     g.B2 = B2; g.ldb2 = N; g.b2_f32 = prec != FR_FP64;
     g.C = C; g.ldc = N; g.c_f32 = prec != FR_FP64;
     g.N = N; g.sB1 = (int64_t)K1 * N; g.sC = (int64_t)M * N;
-    const int gp = prec == FR_FP64 ? fr::PREC_F64 : fr::PREC_F32;
+    const int gp = prec == FR_FP64 ? fr::PREC_F64 : (prec == FR_FP32 ? fr::PREC_F32 : fr::PREC_BF16X3);
     for (int w = 0; w < 3; ++w) hip_check(fr::launch_gemm(gp, fr::EPI_STORE, g, batch, s), "gemm");
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "event");

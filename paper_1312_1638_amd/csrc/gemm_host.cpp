@@ -1,6 +1,7 @@
 // Host side of the operator GEMM: packing of operators into fragment order,
 // plan enumeration (for the autotuner), dispatch by precision.
 #include <algorithm>
+#include <cstring>
 
 #include "kernels.h"
 
@@ -85,7 +86,48 @@ hipError_t launch_gemm(int prec, int epi, const GemmArgs &g, int batch, hipStrea
   if (g.N <= 0) return hipSuccess;
   if (prec == PREC_F64) return launch_gemm_f64(epi, g, batch, s);
   if (prec == PREC_F32) return launch_gemm_f32(epi, g, batch, s);
+  if (prec == PREC_BF16X3) return launch_gemm_bf16x3(epi, g, batch, s);
   return hipErrorInvalidValue;
+}
+
+// round-to-nearest-even of an FP32 value to bf16 (bit pattern)
+static uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+static double bf16_to_double(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+int64_t gemm_pack_size_bf16(int M, int K1, int K2, int MBW, int WM) {
+  (void)M;
+  const int KS = (K1 + 31) / 32 + (K2 + 31) / 32;
+  return (int64_t)WM * KS * MBW * 2 * 64 * 8;
+}
+
+void gemm_pack_bf16x3(const double *A, int M, int K1, int K2, int MBW, int WM, uint16_t *dst) {
+  const int KS1 = (K1 + 31) / 32, KS2 = (K2 + 31) / 32, KS = KS1 + KS2, K = K1 + K2;
+  for (int rg = 0; rg < WM; ++rg)
+    for (int ks = 0; ks < KS; ++ks)
+      for (int m = 0; m < MBW; ++m)
+        for (int l = 0; l < 64; ++l)
+          for (int j = 0; j < 8; ++j) {
+            const int row = (rg * MBW + m) * 16 + (l & 15);
+            const int kk = (ks < KS1 ? ks : ks - KS1) * 32 + 8 * (l >> 4) + j;
+            const bool ok = ks < KS1 ? kk < K1 : kk < K2;
+            const int acol = ks < KS1 ? kk : K1 + kk;
+            const double v = (row < M && ok) ? A[(int64_t)row * K + acol] : 0.0;
+            const uint16_t hi = bf16_rne((float)v);
+            const uint16_t lo = bf16_rne((float)(v - bf16_to_double(hi)));
+            const int64_t base = (((int64_t)rg * KS + ks) * MBW + m) * 2;
+            dst[((base + 0) * 64 + l) * 8 + j] = hi;
+            dst[((base + 1) * 64 + l) * 8 + j] = lo;
+          }
 }
 
 }  // namespace fr

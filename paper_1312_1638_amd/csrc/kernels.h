@@ -55,13 +55,14 @@ struct GemmArgs {
 int64_t gemm_pack_size(int M, int K1, int K2, int MBW, int WM, int kstep);
 void gemm_pack_f64(const double *A, int M, int K1, int K2, int MBW, int WM, double *dst);
 void gemm_pack_f32(const double *A, int M, int K1, int K2, int MBW, int WM, float *dst);
-// BF16x3: hi and lo parts interleaved per fragment (see kernel)
+// BF16x3: k-steps of 32; hi and lo bf16 fragments interleaved (see kernel)
 int64_t gemm_pack_size_bf16(int M, int K1, int K2, int MBW, int WM);
 void gemm_pack_bf16x3(const double *A, int M, int K1, int K2, int MBW, int WM, uint16_t *dst);
 
 hipError_t launch_gemm(int prec, int epi, const GemmArgs &g, int batch, hipStream_t s);
 hipError_t launch_gemm_f64(int epi, const GemmArgs &g, int batch, hipStream_t s);
 hipError_t launch_gemm_f32(int epi, const GemmArgs &g, int batch, hipStream_t s);
+hipError_t launch_gemm_bf16x3(int epi, const GemmArgs &g, int batch, hipStream_t s);
 
 struct GemmPlan { int MBW, NC, WM; };
 // Default plan for an M-row operator and N columns (no tuning).
@@ -80,6 +81,7 @@ struct PointArgs {
   const double *rcpdjac;   // [Nu][ld]
   const double *u;         // state [Nu][NV][ld]
   void *q;                 // gradients / transformed flux [D][Nu][NV][ld] (in place)
+  void *fout;              // transformed-flux output (null: over q)
   int q_f32;
   double gamma, mu, prandtl;
 };
@@ -97,6 +99,7 @@ struct PairArgs {
   const double *nrm;               // [D][npairs]
   const double *magL, *magR;
   void *uf; int uf_f32;            // U^f -> D~ in place
+  void *dfout;                     // D~ output (null: over U^f)
   void *cf;                        // C^f output (con_u)
   const void *qf;                  // Q^f (NS common flux)
   const int64_t *blk_ufbase;       // per block: offset into uf/cf

@@ -69,6 +69,7 @@ __global__ __launch_bounds__(256) void tflux_kernel(PointArgs a) {
 #pragma unroll
   for (int al = 0; al < NV; ++al) u[al] = a.u[base + al * a.ld];
   TQ *q = (TQ *)a.q;
+  TQ *qo = a.fout ? (TQ *)a.fout : q;
   double f[D][NV], p, v[D];
   inviscid_flux<D>(u, a.gamma, f, p, v);
   if (NS) {
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(256) void tflux_kernel(PointArgs a) {
       double s = 0;
 #pragma unroll
       for (int j = 0; j < D; ++j) s += S[i][j] * f[j][al];
-      q[i * cstride + base + al * a.ld] = (TQ)s;
+      qo[i * cstride + base + al * a.ld] = (TQ)s;
     }
 }
 
@@ -221,10 +222,11 @@ __global__ __launch_bounds__(256) void comm_flux_kernel(PairArgs a, unsigned nre
     }
   }
   const double mL = a.magL[k], mR = a.magR[k];
+  T *df = a.dfout ? (T *)a.dfout : uf;
 #pragma unroll
   for (int al = 0; al < NV; ++al) {
-    uf[L.base + iL + al * L.ld] = (T)(mL * F[al]);
-    uf[R.base + iR + al * R.ld] = (T)(-mR * F[al]);
+    df[L.base + iL + al * L.ld] = (T)(mL * F[al]);
+    df[R.base + iR + al * R.ld] = (T)(-mR * F[al]);
   }
 }
 

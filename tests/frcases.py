@@ -35,6 +35,9 @@ def floor_tolerance(d, u, stated, unit_ratio=1.0, factor=4.0):
 
 
 FP32_OVER_FP64 = 2.0 ** 29   # unit roundoff ratio 2^-24 / 2^-53
+# BF16x3 products keep ~16 significant bits (hi + lo parts of both operands,
+# the lo*lo term dropped): unit ratio 2^-16 / 2^-53
+BF16X3_OVER_FP64 = 2.0 ** 37
 
 
 def mixed(n=6, order=3, seed=0, system="euler", mu=0.02):

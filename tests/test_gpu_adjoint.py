@@ -160,3 +160,25 @@ def test_gradient_through_steps_matches_oracle_complex_step():
         got = _dot(gh, dirn)
         print(f"direction {k}: adjoint {got:.12e} oracle complex step {ref:.12e} rel {abs(got - ref) / abs(ref):.2e}")
         assert abs(got - ref) <= 1e-10 * abs(ref)
+
+
+@pytest.mark.parametrize("name", ["mixed5_p2_ns", "curved4_p4"])
+def test_stash_path_matches_recompute_path(name):
+    import torch
+    w = C.SMALL[name]()
+    d = Discretisation(w)
+    u = _off_kink(d, d.initial_state(w))
+    s = C.solver_for(w)
+    a = s.pack(u)
+    b = a.clone()
+    stash = torch.empty(s.stash_len(), dtype=torch.float64, device="cuda")
+    s.step(a, 1e-3, 1)
+    s.step_stash(b, 1e-3, stash)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    lam = s.pack(_rand_like(u, 3))
+    l1 = s.rk_step_adjoint(s.pack(u), 1e-3, lam)
+    l2 = s.rk_step_adjoint_stash(stash, 1e-3, lam)
+    err = float(torch.linalg.norm(l1 - l2) / torch.linalg.norm(l1))
+    print(f"{name}: stash vs recompute step adjoint rel {err:.2e}")
+    assert err < 1e-14

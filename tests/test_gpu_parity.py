@@ -50,6 +50,23 @@ def test_rhs_small_fp32(name):
     assert err < tol
 
 
+@pytest.mark.parametrize("name", ["vortex7_p3", "mixed6_p3_euler", "tgv5_p3", "curved4_p4"])
+def test_rhs_small_bf16x3(name):
+    """Split-precision bf16 operator products: du/dt within the error model
+    (~2^-16 relative per product, amplified by the case's conditioning) and
+    u after 5 RK4 steps within 1e-5."""
+    w = C.SMALL[name]()
+    d, s, u = _both(w, "bf16x3")
+    tol, ext, floor = C.floor_tolerance(d, u, 1e-4, C.BF16X3_OVER_FP64)
+    t = s.pack(u)
+    err = C.rel_l2(s.unpack(s.rhs(t)), ext)
+    dt = 1e-4
+    s.step(t, dt, 5)
+    eu = C.rel_l2(s.unpack(t), d.rk4(u, dt, 5))
+    print(f"{name} bf16x3: rhs rel L2 {err:.3e} (tol {tol:.2e}), u(5) {eu:.3e}")
+    assert err < tol and eu < 1e-5
+
+
 def test_rhs_alias_in_place():
     w = C.SMALL["mixed5_p2_ns"]()
     d, s, u = _both(w)

@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 @pytest.mark.parametrize("M,K1,K2,N", [(16, 4, 0, 16), (16, 16, 0, 1600), (96, 64, 0, 320),
                                        (192, 96, 64, 640), (125, 150, 375, 96), (150, 125, 0, 48),
                                        (7, 3, 5, 32), (375, 150, 125, 64)])
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_gemm_random(M, K1, K2, N, prec):
     import torch
     import paper_1312_1638_amd as P
@@ -28,14 +28,17 @@ def test_gemm_random(M, K1, K2, N, prec):
     ref = A @ B
     err = np.abs(got - ref).max() / np.abs(ref).max()
     print(f"gemm {M}x{K1}+{K2}x{N} {prec}: max rel {err:.2e}")
-    assert err < (1e-14 if prec == "fp64" else 2e-6)
+    assert err < {"fp64": 1e-14, "fp32": 2e-6, "bf16x3": 6e-5}[prec]
 
 
 SHAPES = [(1, 1), (1, 2), (1, 4), (2, 1), (2, 2), (2, 4), (3, 1), (3, 2), (3, 4), (4, 1),
           (4, 2), (4, 4), (6, 1), (6, 2), (6, 4), (8, 1), (8, 2), (12, 1), (12, 2)]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+TOL = {"fp64": 1e-14, "fp32": 2e-6, "bf16x3": 6e-5}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_gemm_every_tile_shape(prec):
     """Every instantiated (row blocks, column strips) shape, with a ragged M,
     ragged K in both panels and a column count not divisible by the strip
@@ -54,7 +57,7 @@ def test_gemm_every_tile_shape(prec):
         wm = -(-MB // mbw)
         got = P.binding.debug_gemm(A, dB1, dB2, prec, (mbw, nc, wm)).double().cpu().numpy()
         err = np.abs(got - ref).max() / np.abs(ref).max()
-        assert err < (1e-14 if prec == "fp64" else 2e-6), (mbw, nc, wm, err)
+        assert err < TOL[prec], (mbw, nc, wm, err)
 
 
 def _split(s, flat, rows_per_block, nvars):
