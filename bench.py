@@ -33,6 +33,7 @@ WORKLOADS = {
     "curved48": ("curved_freestream_hexes", dict(n=48, order=4), "euler"),
     "curved24": ("curved_freestream_hexes", dict(n=24, order=4), "euler"),
     "tgv24": ("taylor_green_hexes", dict(n=24, order=3), "ns"),
+    "batched512": ("batched_vortices", dict(nproblems=512), "euler"),
 }
 
 STEP_NAMES = {1: "interp_M0", 2: "common_solution", 3: "grad_M6_M4p", 4: "grad_transform",
@@ -92,6 +93,10 @@ def make_solver(workload, prec, P, configs):
     s.npairs = P.check_mesh(w.mesh, w.system)
     u0 = [np.ascontiguousarray(np.transpose(w.ic(b, s.solution_points(b)), (1, 2, 0)))
           for b in range(len(w.mesh.blocks))]
+    s.bench_dt = w.dt
+    if w.dt_per_problem is not None:
+        import torch
+        s.bench_dt = torch.tensor(w.dt_per_problem, dtype=torch.float64, device="cuda")
     return w, s, u0
 
 
@@ -106,6 +111,11 @@ def time_steps(s, u, dt, steps, warmup, torch):
         s.integrate(u)
     torch.cuda.synchronize()
     return time.perf_counter() - t0
+
+
+def plan_name(plan):
+    mbw, nc, wm = plan
+    return f"sparse-row rpg={nc}" if mbw == 0 else f"mfma {mbw}x{nc} wm={wm}"
 
 
 def time_kernels(s, u, torch, nrep=50):
@@ -215,7 +225,7 @@ def main():
     dof = sum(b["nupts"] * b["nelem"] for b in s.blocks) * s.nvars
     npts = dof // s.nvars
     u = s.pack(u0)
-    el = time_steps(s, u, w.dt, args.steps, args.warmup, torch)
+    el = time_steps(s, u, s.bench_dt, args.steps, args.warmup, torch)
     ms = el / args.steps * 1e3
     value = 4.0 * dof * args.steps / el
 
@@ -248,16 +258,20 @@ def main():
         b_, f_ = step_model(s, st, 8)
         kernels[STEP_NAMES[st]] = dict(us=round(t * 1e6, 2), GBps=round(b_ / t / 1e9, 1),
                                        TFLOPs=round(f_ / t / 1e12, 2))
+        if st in (1, 3, 5, 8):
+            kernels[STEP_NAMES[st]]["plan"] = plan_name(s.gemm_plan(0, st))
 
     extra = {}
     if not args.no_fp32:
         for prec in ("fp32", "bf16x3"):
             wr, sr, _ = make_solver(args.workload, prec, P, configs)
             ur = sr.pack(u0)
-            elr = time_steps(sr, ur, w.dt, args.steps, args.warmup, torch)
+            elr = time_steps(sr, ur, sr.bench_dt, args.steps, args.warmup, torch)
             ktr = time_kernels(sr, sr.pack(u0), torch)
             extra[prec] = dict(value=4.0 * dof * args.steps / elr, ms_per_step=elr / args.steps * 1e3,
-                               kernels_us={STEP_NAMES[k]: round(v * 1e6, 2) for k, v in ktr.items()})
+                               kernels_us={STEP_NAMES[k]: round(v * 1e6, 2) for k, v in ktr.items()},
+                               plans={STEP_NAMES[k]: plan_name(sr.gemm_plan(0, k)) for k in ktr
+                                      if k in (1, 3, 5, 8)})
             sr.close()
 
     if not args.no_adjoint:
@@ -281,7 +295,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "system": w.system, "elements": int(sum(b.nelem for b in w.mesh.blocks)),
-                   "order": int(w.mesh.blocks[0].order), "dof": int(dof), "solution_points": int(npts),
+                   "blocks": [f"{b.etype} p={b.order} x{b.nelem}" for b in w.mesh.blocks],
+                   "problems": int(w.mesh.nproblems), "dof": int(dof), "solution_points": int(npts),
                    "rhs_per_step": 4, "dt": w.dt, "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,

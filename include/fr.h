@@ -189,7 +189,10 @@ fr_status fr_check_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *b
  * core kernel: A HOST row-major M x (K1 + K2); B1 (K1 rows), B2 (K2 rows)
  * DEVICE float64 with row stride ldb; C DEVICE (float64 for FP64, float32
  * for FP32) M x N, row stride N; N a multiple of 16.  (mbw, nc, wm) forces a
- * tile plan (mbw = 0: the default plan).  Synchronous. */
+ * matrix-core tile plan; mbw = 0 with nc > 0 forces the sparse-row kernel
+ * with nc operator rows per workgroup (FR_EINVAL if A is not sparse: at
+ * least half of its entries must be zero, or below 1e-13 of their row's
+ * largest magnitude); mbw = nc = 0: the default plan.  Synchronous. */
 fr_status fr_debug_stage(fr_ctx *ctx, const double *u, int32_t stage, double *out,
                          void *hip_stream);
 fr_status fr_debug_scratch_len(const fr_ctx *ctx, int32_t stage, int64_t *len);
@@ -213,7 +216,8 @@ fr_status fr_debug_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, const d
  * an M x (K1 + K2) operator on N columns (batch copies of panel 1) with tile
  * plan (mbw, nc, wm) (mbw = 0: default plan); operands are internal.
  * fr_get_gemm_plan: the tile plan a context uses for right-hand-side step
- * 1, 3, 5 or 8 of `block`. */
+ * 1, 3, 5 or 8 of `block` (mbw = 0: the sparse-row kernel, nc rows per
+ * workgroup). */
 fr_status fr_measure_ceiling(int32_t kind, double *value, void *hip_stream);
 fr_status fr_bench_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, int64_t N,
                         int32_t mbw, int32_t nc, int32_t wm, int32_t batch, int32_t nrep,

@@ -2,6 +2,7 @@
 // RK4 stepping (captured once into a HIP graph and replayed), integrals.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -24,7 +25,14 @@ struct GemmOp {
   int M = 0, K1 = 0, K2 = 0, KS1 = 0, KS2 = 0, MBW = 1, NC = 1, WM = 1;
   void *d_A = nullptr;
   std::vector<double> A;  // unpacked operator (kept for re-packing by the tuner)
+  fr::SparseOp sp{nullptr, nullptr, 0, 0};  // ELL copy when the operator is sparse
+  double density = 1.0;
 };
+
+// Entries below this fraction of their row's largest magnitude are the
+// rounding residue of structural zeros (the Vandermonde construction does
+// not produce exact zeros); the sparse-row kernel skips them.
+const double kSparseDrop = 1e-13;
 
 struct BlockRT {
   int ref = 0;
@@ -155,9 +163,55 @@ void make_op(fr_ctx *c, GemmOp &op, const std::vector<double> &A, int M, int K1,
   op.KS1 = (K1 + kstep - 1) / kstep;
   op.KS2 = (K2 + kstep - 1) / kstep;
   op.A = A;
+  // ELL copy (sparse-row kernel), FP64 and FP32 contexts
+  {
+    const int K = K1 + K2;
+    std::vector<std::vector<int>> cols(M);
+    size_t nnz = 0;
+    int wmax = 1;
+    for (int r = 0; r < M; ++r) {
+      double mx = 0;
+      for (int k = 0; k < K; ++k) mx = std::max(mx, std::fabs(A[(size_t)r * K + k]));
+      for (int k = 0; k < K; ++k)
+        if (std::fabs(A[(size_t)r * K + k]) > kSparseDrop * mx) cols[r].push_back(k);
+      nnz += cols[r].size();
+      wmax = std::max(wmax, (int)cols[r].size());
+    }
+    op.density = (double)nnz / ((double)M * K);
+    const int W = fr::spop_width(wmax);
+    if (c->prec != FR_BF16X3 && op.density < 0.5 && W > 0) {
+      std::vector<int32_t> ci((size_t)M * W);
+      std::vector<double> va((size_t)M * W, 0.0);
+      for (int r = 0; r < M; ++r) {
+        const int last = cols[r].empty() ? 0 : cols[r].back();
+        for (int e = 0; e < W; ++e) {
+          const bool real = e < (int)cols[r].size();
+          ci[(size_t)r * W + e] = real ? cols[r][e] : last;
+          va[(size_t)r * W + e] = real ? A[(size_t)r * K + cols[r][e]] : 0.0;
+        }
+      }
+      op.sp.colidx = dev_upload(c, ci.data(), ci.size(), s);
+      op.sp.vals = dev_upload(c, va.data(), va.size(), s);
+      op.sp.width = W;
+      op.sp.rpg = 16;
+    }
+  }
   fr::GemmPlan p = force ? *force : fr::gemm_plan(M, N, c->prec);
+  if (p.MBW == 0 && !op.sp.colidx) p = fr::gemm_plan(M, N, c->prec);
   op.MBW = p.MBW; op.NC = p.NC; op.WM = p.WM;
-  op.d_A = pack_upload(c, op, p, s, true);
+  if (p.MBW == 0) {
+    op.sp.rpg = p.NC;
+    op.d_A = nullptr;
+  } else {
+    op.d_A = pack_upload(c, op, p, s, true);
+  }
+}
+
+// Launch an operator product with whichever kernel its plan names.
+hipError_t launch_op(const GemmOp &op, int gprec, int epi, const fr::GemmArgs &g, int batch,
+                     hipStream_t s) {
+  if (op.MBW == 0) return fr::launch_spop(gprec, epi, g, op.sp, batch, s);
+  return fr::launch_gemm(gprec, epi, g, batch, s);
 }
 
 // concatenate two row-major matrices side by side: [A (M x K1) | B (M x K2)]
@@ -243,14 +297,14 @@ void run_step(fr_ctx *c, int st, const double *u, double *dudt, int epi, const f
       g.B1 = u + b.uoff; g.ldb1 = N; g.b1_f32 = 0;
       g.C = elem(c->cur.uf, b.ufoff, ts); g.ldc = N; g.c_f32 = f32;
       g.N = N;
-      hip_check(fr::launch_gemm(gprec, fr::EPI_STORE, g, 1, s), "gemm M0");
+      hip_check(launch_op(b.m0, gprec, fr::EPI_STORE, g, 1, s), "gemm M0");
     } else if (st == 3) {
       fr::GemmArgs g = gemm_args(b.s3);
       g.B1 = elem(c->cur.qf, b.qfoff, ts); g.ldb1 = N; g.b1_f32 = f32;
       g.B2 = u + b.uoff; g.ldb2 = N; g.b2_f32 = 0;
       g.C = elem(c->cur.ft, b.ftoff, ts); g.ldc = N; g.c_f32 = f32;
       g.N = N;
-      hip_check(fr::launch_gemm(gprec, fr::EPI_STORE, g, 1, s), "gemm M6|M4'");
+      hip_check(launch_op(b.s3, gprec, fr::EPI_STORE, g, 1, s), "gemm M6|M4'");
     } else if (st == 4) {
       hip_check(fr::launch_gradcoru(point_args(c, b, u), s), "gradcoru");
     } else if (st == 5) {
@@ -260,7 +314,7 @@ void run_step(fr_ctx *c, int st, const double *u, double *dudt, int epi, const f
       g.N = N;
       g.sB1 = (int64_t)b.Nu * N;
       g.sC = (int64_t)b.Nf * N;
-      hip_check(fr::launch_gemm(gprec, fr::EPI_STORE, g, D, s), "gemm M5");
+      hip_check(launch_op(b.m5, gprec, fr::EPI_STORE, g, D, s), "gemm M5");
     } else if (st == 6) {
       hip_check(fr::launch_tflux(point_args(c, b, u), c->ns, s), "tflux");
     } else if (st == 8) {
@@ -275,7 +329,7 @@ void run_step(fr_ctx *c, int st, const double *u, double *dudt, int epi, const f
         g.stage = c->cur.stage_out ? c->cur.stage_out + b.uoff : nullptr;
         g.dt = dt; g.prob = b.d_prob; g.rk = *rk;
       }
-      hip_check(fr::launch_gemm(gprec, epi, g, 1, s), "gemm M3|M1'");
+      hip_check(launch_op(b.s8, gprec, epi, g, 1, s), "gemm M3|M1'");
     }
   }
 }
@@ -314,10 +368,14 @@ void tune_op(fr_ctx *c, GemmOp &op, int step, BlockRT &b, hipStream_t s) {
     hip_check(hipEventCreate(&e0), "event");
     hip_check(hipEventCreate(&e1), "event");
     float best_ms = 1e30f;
-    for (const fr::GemmPlan &p : fr::gemm_candidates(op.M, N, c->prec)) {
-      void *d = pack_upload(c, op, p, s, false);
+    std::vector<fr::GemmPlan> cands = fr::gemm_candidates(op.M, N, c->prec);
+    if (op.sp.colidx)
+      for (int rpg : {4, 8, 16, 32, 64}) cands.push_back(fr::GemmPlan{0, rpg, 0});
+    for (const fr::GemmPlan &p : cands) {
+      void *d = p.MBW ? pack_upload(c, op, p, s, false) : nullptr;
       GemmOp trial = op;
       trial.d_A = d; trial.MBW = p.MBW; trial.NC = p.NC; trial.WM = p.WM;
+      if (p.MBW == 0) trial.sp.rpg = p.NC;
       std::swap(*(step == 1 ? &b.m0 : step == 3 ? &b.s3 : step == 5 ? &b.m5 : &b.s8), trial);
       float ms = 0;
       try {
@@ -341,8 +399,9 @@ void tune_op(fr_ctx *c, GemmOp &op, int step, BlockRT &b, hipStream_t s) {
     g_tuned[key] = best;
   }
   if (best.MBW != op.MBW || best.NC != op.NC || best.WM != op.WM) {
-    op.d_A = pack_upload(c, op, best, s, true);
+    op.d_A = best.MBW ? pack_upload(c, op, best, s, true) : nullptr;
     op.MBW = best.MBW; op.NC = best.NC; op.WM = best.WM;
+    if (best.MBW == 0) op.sp.rpg = best.NC;
   }
 }
 
@@ -417,7 +476,7 @@ void adj_gemm(fr_ctx *c, const GemmOp &op, const double *B1, const double *B2, d
   fr::GemmArgs g = gemm_args(op);
   g.B1 = B1; g.ldb1 = N; g.B2 = B2; g.ldb2 = N;
   g.C = C; g.ldc = N; g.N = N; g.sB1 = sB1; g.sC = sC;
-  hip_check(fr::launch_gemm(fr::PREC_F64, epi, g, batch, s), "adjoint gemm");
+  hip_check(launch_op(op, fr::PREC_F64, epi, g, batch, s), "adjoint gemm");
 }
 
 // Autotune one transposed operator of the adjoint with its real operands.
@@ -433,10 +492,14 @@ void tune_adj(fr_ctx *c, GemmOp &op, const double *B1, const double *B2, double 
     hip_check(hipEventCreate(&e0), "event");
     hip_check(hipEventCreate(&e1), "event");
     float best_ms = 1e30f;
-    for (const fr::GemmPlan &p : fr::gemm_candidates(op.M, batch * N, c->prec)) {
+    std::vector<fr::GemmPlan> cands = fr::gemm_candidates(op.M, batch * N, c->prec);
+    if (op.sp.colidx)
+      for (int rpg : {4, 8, 16, 32, 64}) cands.push_back(fr::GemmPlan{0, rpg, 0});
+    for (const fr::GemmPlan &p : cands) {
       GemmOp trial = op;
-      trial.d_A = pack_upload(c, op, p, s, false);
+      trial.d_A = p.MBW ? pack_upload(c, op, p, s, false) : nullptr;
       trial.MBW = p.MBW; trial.NC = p.NC; trial.WM = p.WM;
+      if (p.MBW == 0) trial.sp.rpg = p.NC;
       float ms = 0;
       try {
         for (int w = 0; w < 2; ++w) adj_gemm(c, trial, B1, B2, C, N, epi, batch, sB1, sC, s);
@@ -457,8 +520,9 @@ void tune_adj(fr_ctx *c, GemmOp &op, const double *B1, const double *B2, double 
     g_tuned[key] = best;
   }
   if (best.MBW != op.MBW || best.NC != op.NC || best.WM != op.WM) {
-    op.d_A = pack_upload(c, op, best, s, true);
+    op.d_A = best.MBW ? pack_upload(c, op, best, s, true) : nullptr;
     op.MBW = best.MBW; op.NC = best.NC; op.WM = best.WM;
+    if (best.MBW == 0) op.sp.rpg = best.NC;
   }
 }
 
@@ -1111,15 +1175,17 @@ fr_status fr_debug_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, const d
     fr::GemmPlan p{mbw, nc, wm};
     if (mbw > 0 && (!fr::gemm_plan_valid(mbw, nc) || wm < 1 || mbw * wm * 16 < M))
       throw Fail{FR_EINVAL, "bad plan"};
-    make_op(&tmp, op, Av, M, K1, K2, N, s, mbw > 0 ? &p : nullptr);
+    if (mbw == 0 && nc < 0) throw Fail{FR_EINVAL, "bad plan"};
+    make_op(&tmp, op, Av, M, K1, K2, N, s, (mbw > 0 || nc > 0) ? &p : nullptr);
+    if (mbw == 0 && nc > 0 && op.MBW != 0) throw Fail{FR_EINVAL, "operator is not sparse"};
     fr::GemmArgs g = gemm_args(op);
     g.B1 = B1; g.ldb1 = ldb; g.b1_f32 = 0;
     g.B2 = B2; g.ldb2 = ldb; g.b2_f32 = 0;
     g.C = C; g.ldc = N; g.c_f32 = prec != FR_FP64;
     g.N = N;
-    hip_check(fr::launch_gemm(prec == FR_FP64 ? fr::PREC_F64
-                              : (prec == FR_FP32 ? fr::PREC_F32 : fr::PREC_BF16X3),
-                              fr::EPI_STORE, g, 1, s),
+    hip_check(launch_op(op, prec == FR_FP64 ? fr::PREC_F64
+                                : (prec == FR_FP32 ? fr::PREC_F32 : fr::PREC_BF16X3),
+                        fr::EPI_STORE, g, 1, s),
               "gemm");
     hip_check(hipStreamSynchronize(s), "sync");
   } catch (const Fail &f) {

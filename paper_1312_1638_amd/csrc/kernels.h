@@ -64,6 +64,22 @@ hipError_t launch_gemm_f64(int epi, const GemmArgs &g, int batch, hipStream_t s)
 hipError_t launch_gemm_f32(int epi, const GemmArgs &g, int batch, hipStream_t s);
 hipError_t launch_gemm_bf16x3(int epi, const GemmArgs &g, int batch, hipStream_t s);
 
+// Operator stored with a fixed number of entries per row (ELL) for the
+// sparse-row kernel (spop.hip): row r holds colidx[r * width + e] and
+// vals[r * width + e], e < width; padding entries have value 0.
+struct SparseOp {
+  const int32_t *colidx;   // [M][width], column in [0, K1 + K2)
+  const double *vals;      // [M][width]
+  int width;               // one of FR_SPOP_WIDTHS
+  int rpg;                 // operator rows per workgroup row
+};
+#define FR_SPOP_WIDTHS(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32)
+// smallest instantiated width >= nnz_max (0 if none)
+int spop_width(int nnz_max);
+hipError_t launch_spop(int prec, int epi, const GemmArgs &g, const SparseOp &sp, int batch,
+                       hipStream_t s);
+
+// MBW > 0: matrix-core plan; MBW == 0: sparse-row kernel with NC = rows per group.
 struct GemmPlan { int MBW, NC, WM; };
 // Default plan for an M-row operator and N columns (no tuning).
 GemmPlan gemm_plan(int M, int64_t N, int prec);

@@ -60,6 +60,45 @@ def test_gemm_every_tile_shape(prec):
         assert err < TOL[prec], (mbw, nc, wm, err)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_sparse_row_kernel(prec):
+    """The sparse-row operator kernel: a random operator with a few non-zeros
+    per row (ragged M, both panels, columns in a ragged last workgroup) and
+    the library's own line-structured hex operators, for several rows per
+    workgroup; it must equal the dense product."""
+    import torch
+    import paper_1312_1638_amd as P
+    rng = np.random.default_rng(13)
+    cases = []
+    M, K1, K2, N = 151, 40, 23, 16 * 21
+    A = rng.standard_normal((M, K1 + K2)) * (rng.random((M, K1 + K2)) < 0.1)
+    cases.append((A, K1, N))
+    m0 = P.binding.reference_operator("hex", 4, 0)
+    m3 = P.binding.reference_operator("hex", 4, 1)
+    m1p = P.binding.reference_operator("hex", 4, 4)
+    cases.append((m0, m0.shape[1], 16 * 40))
+    cases.append((np.concatenate([m1p, m3], 1), m1p.shape[1], 16 * 17))
+    for A, K1, N in cases:
+        M, K = A.shape
+        B = rng.standard_normal((K, N))
+        ref = A @ B
+        dB1 = torch.from_numpy(B[:K1].copy()).cuda()
+        dB2 = torch.from_numpy(B[K1:].copy()).cuda() if K > K1 else None
+        for rpg in (1, 4, 7, 16, 64):
+            got = P.binding.debug_gemm(A, dB1, dB2, prec, (0, rpg, 0)).double().cpu().numpy()
+            err = np.abs(got - ref).max() / np.abs(ref).max()
+            assert err < TOL[prec], (A.shape, rpg, err)
+
+
+def test_sparse_plan_rejected_for_dense_operator():
+    import torch
+    import paper_1312_1638_amd as P
+    A = np.ones((32, 16))
+    B = torch.ones((16, 32), dtype=torch.float64, device="cuda")
+    with pytest.raises(P.binding.FRError):
+        P.binding.debug_gemm(A, B, None, "fp64", (0, 8, 0))
+
+
 def _split(s, flat, rows_per_block, nvars):
     """Internal scratch array -> per-block [rows, alpha, n] (padding removed)."""
     out, off = [], 0

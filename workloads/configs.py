@@ -98,8 +98,9 @@ def batched_vortices(nproblems=512, seed=4, nmin=50, nmax=5000, nsteps=20,
         diag = rng.integers(0, 2, size=n * n).astype(np.int32)
         centre = rng.uniform(-2.0, 2.0, size=2)
         S = rng.uniform(2.0, 5.0)
-        probs.append(dict(p=p, n=n, centre=centre, S=S))
         qn, tn, pairs = meshes.mixed_quad_tri_mesh(n, n, split=split, diag=diag)
+        probs.append(dict(p=p, n=n, centre=centre, S=S, quad_nodes=qn, tri_nodes=tn,
+                          pairs=pairs))
         keys = {0: ("quad", p), 1: ("tri", p)}
         offs = {}
         for code, arr in ((0, qn), (1, tn)):
@@ -110,6 +111,7 @@ def batched_vortices(nproblems=512, seed=4, nmin=50, nmax=5000, nsteps=20,
                 g["prob"].append(np.full(len(arr), prob, np.int32))
                 g["count"] += len(arr)
         recs.append((pairs, keys, offs))
+        probs[-1]["offsets"] = dict(offs)
     order = sorted(groups.keys(), key=lambda k: (k[0] != "quad", k[1]))
     bidx = {k: i for i, k in enumerate(order)}
     blocks = []
@@ -137,9 +139,25 @@ def batched_vortices(nproblems=512, seed=4, nmin=50, nmax=5000, nsteps=20,
             out[sel] = fields.isentropic_vortex(x[sel], S=pr["S"], centre=pr["centre"])
         return out
 
+    for pr in probs:
+        pr["blocks"] = (bidx[("quad", pr["p"])], bidx[("tri", pr["p"])])
+    # step sizes differ per problem (smaller on finer grids)
+    dts = np.array([dt * min(1.0, 10.0 / pr["n"] * 2.0) for pr in probs])
     return Workload(f"batched{nproblems}_vortex", mesh, "euler", dt=dt,
-                    nsteps=nsteps, ic=ic,
-                    dt_per_problem=np.full(nproblems, dt))
+                    nsteps=nsteps, ic=ic, dt_per_problem=dts)
+
+
+def single_problem(batched, j):
+    """Problem j of a batched workload as a stand-alone workload, and the
+    (block, first element) of its quads and triangles in the batched mesh."""
+    pr = batched.mesh.info["problems"][j]
+    qn, tn, pairs = pr["quad_nodes"], pr["tri_nodes"], pr["pairs"]
+    m = meshes.Mesh(2, [meshes.Block("quad", pr["p"], 1, qn), meshes.Block("tri", pr["p"], 1, tn)],
+                    pairs, info=dict(h=10.0 / pr["n"]))
+    w = Workload(f"problem{j}", m, "euler", dt=float(batched.dt_per_problem[j]),
+                 ic=lambda b, x: fields.isentropic_vortex(x, S=pr["S"], centre=pr["centre"]))
+    where = [(pr["blocks"][0], pr["offsets"][0], len(qn)), (pr["blocks"][1], pr["offsets"][1], len(tn))]
+    return w, where
 
 
 def adjoint_tgv(n=24, order=3, nsteps=200, dt=2e-4, ckpt=20):
