@@ -41,35 +41,47 @@ STEP_NAMES = {1: "interp_M0", 2: "common_solution", 3: "grad_M6_M4p", 4: "grad_t
 
 PEAK_HBM = 8.0e12                                           # B/s
 PEAK_MFMA = {"fp64": 78.6e12, "fp32": 157.3e12}             # dense FLOP/s
-ROCPROF_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+ROCPROF_TRAFFIC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "hbm_traffic.md")
+
+
+def operator_nnz(P, etype, order, which):
+    """Structural non-zeros of a reference operator (entries above 1e-13 of
+    their row's largest magnitude; the rest is rounding residue)."""
+    import numpy as np
+    A = P.reference_operator(etype, order, which)
+    mx = np.abs(A).max(axis=1, keepdims=True)
+    return int((np.abs(A) > 1e-13 * mx).sum())
 
 
 def step_model(s, step, ts):
     """Algorithmic (bytes, flops) of one launch of RHS step `step` over all
-    blocks: each array read once and written once, operators cached."""
+    blocks: each array read once and written once, operators cached; an
+    operator product costs 2 flops per structural non-zero of the operator
+    and state column (multiplications by structural zeros are not work)."""
     D, NV = s.ndims, s.nvars
     byts = flops = 0.0
     for blk, b in zip(s.blocks, s.mesh.blocks):
         ne, nu = blk["nelem"], blk["nupts"]
         nf = s.nfpts[b.etype, b.order]
+        nnz = s.nnz[b.etype, b.order]
         cols = NV * ne
         if step == 1:
-            flops += 2.0 * nf * nu * cols
+            flops += 2.0 * nnz["M0"] * cols
             byts += cols * (nu * 8 + nf * ts)
         elif step == 3:
-            flops += 2.0 * D * nu * (nf + nu) * cols
+            flops += 2.0 * (nnz["M6"] + nnz["M4p"]) * cols
             byts += cols * (nf * ts + nu * 8 + D * nu * ts)
         elif step == 4:
             byts += 2.0 * D * nu * cols * ts + (D * D + 1) * nu * ne * 8
         elif step == 5:
-            flops += 2.0 * D * nf * nu * cols
+            flops += 2.0 * D * nnz["M0"] * cols
             byts += D * cols * (nu + nf) * ts
         elif step == 6:
             byts += nu * ne * (NV * 8 + D * D * 8 + D * NV * ts)
             if s.system == "ns":
                 byts += nu * ne * D * NV * ts
         elif step == 8:
-            flops += 2.0 * nu * (nf + D * nu) * cols
+            flops += 2.0 * (nnz["M3"] + nnz["M1p"]) * cols
             byts += cols * (nf + D * nu) * ts + nu * ne * 8 + nu * cols * 8
     npairs = s.npairs
     if step == 2:
@@ -87,9 +99,12 @@ def make_solver(workload, prec, P, configs):
     s = P.Solver(w.mesh, system=w.system, gamma=w.gamma, mu=w.mu, prandtl=w.prandtl,
                  ldg_beta=w.ldg_beta, ldg_tau=w.ldg_tau, prec=prec)
     s.system = w.system
-    s.nfpts = {}
+    s.nfpts, s.nnz = {}, {}
     for b in w.mesh.blocks:
         s.nfpts[b.etype, b.order] = P.reference_operator(b.etype, b.order, 6).shape[0]
+        s.nnz[b.etype, b.order] = {k: operator_nnz(P, b.etype, b.order, i)
+                                   for k, i in (("M0", 0), ("M3", 1), ("M4p", 2), ("M6", 3),
+                                                ("M1p", 4))}
     s.npairs = P.check_mesh(w.mesh, w.system)
     u0 = [np.ascontiguousarray(np.transpose(w.ic(b, s.solution_points(b)), (1, 2, 0)))
           for b in range(len(w.mesh.blocks))]
@@ -210,6 +225,8 @@ def main():
                     help="RK4 steps of the oracle for the CPU baseline (0: skip)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="diagnostic: run only the adjoint cost measurement and print it")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -220,6 +237,10 @@ def main():
     import paper_1312_1638_amd as P
     from workloads import configs
     assert torch.cuda.is_available(), "needs a HIP device"
+
+    if args.adjoint_only:
+        print(json.dumps(adjoint_ratio(P, configs, torch)))
+        return
 
     w, s, u0 = make_solver(args.workload, "fp64", P, configs)
     dof = sum(b["nupts"] * b["nelem"] for b in s.blocks) * s.nvars
@@ -246,13 +267,11 @@ def main():
     roof["avg_launch_us"] = kt[dom] * 1e6
     roof["algorithmic_bytes"] = byts
     roof["algorithmic_flops"] = flops
-    roof["traffic"] = None
-    if os.path.exists(ROCPROF_TRAFFIC):
-        with open(ROCPROF_TRAFFIC) as fh:
-            tr = json.load(fh)
-        key = f"{args.workload}:{STEP_NAMES[dom]}"
-        if key in tr:
-            roof["traffic"] = tr[key]
+    # HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    # table, null when it was taken on other library sources
+    from paper_1312_1638_amd.profile_report import read_traffic_table
+    roof["traffic"] = read_traffic_table(ROCPROF_TRAFFIC, args.workload, STEP_NAMES[dom])
+    roof["measured_hbm_triad_GBps"] = round(P.binding.measure_ceiling(0), 1)
     kernels = {}
     for st, t in sorted(kt.items()):
         b_, f_ = step_model(s, st, 8)

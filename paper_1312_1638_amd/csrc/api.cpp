@@ -70,8 +70,11 @@ struct fr_ctx {
   int64_t *d_blk_ufbase = nullptr, *d_blk_qfbase = nullptr, *d_blk_ld = nullptr,
           *d_blk_qstride = nullptr;
   // reductions
-  double *d_part = nullptr;
+  double *d_part = nullptr, *d_part2 = nullptr;
   int64_t *d_pstart = nullptr, *d_plist = nullptr;
+  // integral reductions: point ranges, slices per problem, list entries per slice
+  int nchunk = 1, nslice = 1;
+  int64_t slice_len = 64;
   int32_t *d_flag = nullptr;
   int nproblems = 1;
   // graph of one RK4 step
@@ -863,7 +866,13 @@ fr_status fr_setup_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *b
     c->d_stage = dev_alloc<double>(c.get(), c->total_len);
     c->cur = fr_ctx::Bufs{c->d_uf, c->d_qf, c->d_ft, c->d_uf, c->d_ft, c->d_stage};
     // reductions: element partials and per-problem element lists
-    c->d_part = dev_alloc<double>(c.get(), (size_t)c->nelem_total * (NV + 1));
+    {
+      // enough workgroups to fill the chip on small meshes
+      int64_t wgs = 0;
+      for (auto &b : c->blocks) wgs += (b.nelem + 63) / 64;
+      c->nchunk = (int)std::min<int64_t>(16, std::max<int64_t>(1, 2048 / std::max<int64_t>(1, wgs)));
+    }
+    c->d_part = dev_alloc<double>(c.get(), (size_t)c->nchunk * c->nelem_total * (NV + 1));
     {
       std::vector<std::vector<int64_t>> lists(c->nproblems);
       for (size_t bi = 0; bi < c->blocks.size(); ++bi)
@@ -872,7 +881,18 @@ fr_status fr_setup_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *b
           lists[pr].push_back(c->blocks[bi].part_off + n);
         }
       std::vector<int64_t> start(1, 0), flat;
-      for (auto &l : lists) { flat.insert(flat.end(), l.begin(), l.end()); start.push_back(flat.size()); }
+      size_t maxlen = 0;
+      for (auto &l : lists) {
+        flat.insert(flat.end(), l.begin(), l.end());
+        start.push_back(flat.size());
+        maxlen = std::max(maxlen, l.size());
+      }
+      // 64 list entries per slice, more once there would be over 32768 slices
+      const int64_t blocks64 = std::max<int64_t>(1, ((int64_t)maxlen + 63) / 64);
+      c->slice_len = 64 * ((blocks64 + 32767) / 32768);
+      c->nslice = (int)std::max<int64_t>(1, ((int64_t)maxlen + c->slice_len - 1) / c->slice_len);
+      if (c->nslice > 1)
+        c->d_part2 = dev_alloc<double>(c.get(), (size_t)c->nproblems * c->nslice * (NV + 1));
       c->d_pstart = dev_upload(c.get(), start.data(), start.size(), s);
       c->d_plist = dev_upload(c.get(), flat.data(), flat.size(), s);
     }
@@ -1032,11 +1052,14 @@ fr_status fr_integrate(fr_ctx *c, const double *u, int32_t kind, double *out, vo
   hipStream_t s = (hipStream_t)hip_stream;
   try {
     for (auto &b : c->blocks)
-      hip_check(fr::launch_elem_integrals(c->NV, c->D, b.Nu, b.ld, b.nelem, b.d_wdjac, u + b.uoff,
-                                          c->d_part + b.part_off * (c->NV + 1), s),
+      hip_check(fr::launch_elem_integrals(c->NV, c->D, b.Nu, b.ld, b.nelem, c->nchunk,
+                                          c->nelem_total, b.d_wdjac, u + b.uoff,
+                                          c->d_part + b.part_off, s),
                 "elem integrals");
-    hip_check(fr::launch_problem_sums(c->NV + 1, c->nproblems, c->d_pstart, c->d_plist,
-                                      c->d_part, out, s),
+    hip_check(fr::launch_problem_sums(c->NV + 1, c->nproblems, c->nchunk, c->nelem_total,
+                                      c->nslice, c->slice_len, c->d_pstart, c->d_plist, c->d_part,
+                                      c->d_part2,
+                                      out, s),
               "problem sums");
   } catch (const Fail &f) {
     return fail(c, f.st, f.msg);

@@ -134,15 +134,19 @@ hipError_t launch_comm_flux(const PairArgs &a, int navier_stokes, hipStream_t s)
 // ----------------------------------------------------------------------------
 // Reductions
 // ----------------------------------------------------------------------------
-// per-element integrals of (u[alpha] for alpha<NV, kinetic energy) into part
-// [nelem][NV+1]
+// per-element integrals of (u[alpha] for alpha<NV, kinetic energy) into
+// part[(chunk * (nvars + 1) + c) * pstride + n], chunk < nchunk (solution
+// point ranges)
 hipError_t launch_elem_integrals(int nvars, int ndims, int nupts, int64_t ld, int64_t nelem,
-                                 const double *wdjac, const double *u, double *part,
-                                 hipStream_t s);
-// sum part rows per problem in fixed order: CSR (pstart[nprob+1], plist)
-hipError_t launch_problem_sums(int ncomp, int nprob, const int64_t *pstart,
-                               const int64_t *plist, const double *part, double *out,
-                               hipStream_t s);
+                                 int nchunk, int64_t pstride, const double *wdjac,
+                                 const double *u, double *part, hipStream_t s);
+// sum the partials per problem in fixed order: element lists in CSR form
+// (pstart[nprob+1], plist), nslice workgroups of `per` list entries per
+// problem (per a multiple of 64, nslice * per >= longest list), part2 holds
+// nprob * nslice * ncomp slice sums when nslice > 1; ncomp is 5 or 6
+hipError_t launch_problem_sums(int ncomp, int nprob, int nchunk, int64_t pstride, int nslice,
+                               int64_t per, const int64_t *pstart, const int64_t *plist,
+                               const double *part, double *part2, double *out, hipStream_t s);
 // measured ceilings: kind 0 HBM triad GB/s, 1 FP64 MFMA TFLOP/s, 2 FP32 MFMA TFLOP/s
 hipError_t measure_ceiling(int kind, double *value, hipStream_t s);
 // flag[0] = 1 if any u is not finite

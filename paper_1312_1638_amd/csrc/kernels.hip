@@ -282,16 +282,23 @@ hipError_t launch_comm_flux(const PairArgs &a, int ns, hipStream_t s) {
 // the solution points (rho = wave, wave + 4, ...) and combine in LDS in a
 // fixed order.  part[n][c]: c < nvars the field integrals, c = nvars the
 // kinetic energy.
+// Per-element quadrature of every conserved field and of the kinetic energy
+// 0.5 |m|^2 / rho.  Workgroup: 64 elements x 4 waves; blockIdx.y splits the
+// solution points into `nchunk` ranges (enough workgroups for small meshes).
+// Partials go to part[(chunk * (nvars + 1) + c) * pstride + n].
 __global__ __launch_bounds__(256) void elem_integrals_kernel(int nvars, int ndims, int nupts,
                                                              int64_t ld, int64_t nelem,
+                                                             int64_t pstride,
                                                              const double *wdjac,
                                                              const double *u, double *part) {
   __shared__ double red[4][6][64];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int64_t n = (int64_t)blockIdx.x * 64 + tx;
+  const int rc = (nupts + (int)gridDim.y - 1) / (int)gridDim.y;
+  const int rbeg = (int)blockIdx.y * rc, rend = rbeg + rc < nupts ? rbeg + rc : nupts;
   double s[6] = {0, 0, 0, 0, 0, 0};
   if (n < nelem) {
-    for (int r = ty; r < nupts; r += 4) {
+    for (int r = rbeg + ty; r < rend; r += 4) {
       const double w = wdjac[(int64_t)r * ld + n];
       const double *ur = u + (int64_t)r * nvars * ld + n;
       double m2 = 0;
@@ -307,43 +314,103 @@ __global__ __launch_bounds__(256) void elem_integrals_kernel(int nvars, int ndim
   __syncthreads();
   if (ty == 0 && n < nelem)
     for (int c = 0; c <= nvars; ++c)
-      part[n * (nvars + 1) + c] = (red[0][c][tx] + red[1][c][tx]) + (red[2][c][tx] + red[3][c][tx]);
+      part[((int64_t)blockIdx.y * (nvars + 1) + c) * pstride + n] =
+          (red[0][c][tx] + red[1][c][tx]) + (red[2][c][tx] + red[3][c][tx]);
 }
 
 hipError_t launch_elem_integrals(int nvars, int ndims, int nupts, int64_t ld, int64_t nelem,
-                                 const double *wdjac, const double *u, double *part,
-                                 hipStream_t s) {
-  elem_integrals_kernel<<<(unsigned)((nelem + 63) / 64), 256, 0, s>>>(nvars, ndims, nupts, ld,
-                                                                      nelem, wdjac, u, part);
+                                 int nchunk, int64_t pstride, const double *wdjac,
+                                 const double *u, double *part, hipStream_t s) {
+  if (nelem <= 0) return hipSuccess;
+  dim3 grid((unsigned)((nelem + 63) / 64), (unsigned)nchunk);
+  elem_integrals_kernel<<<grid, 256, 0, s>>>(nvars, ndims, nupts, ld, nelem, pstride, wdjac, u,
+                                             part);
   return hipGetLastError();
 }
 
-// One workgroup per problem: strided partial sums of every component at
-// once, then a fixed-shape tree in LDS (bitwise reproducible).
-__global__ __launch_bounds__(256) void problem_sums_kernel(int ncomp, const int64_t *pstart,
+// Per-problem sums of the element partials.  Workgroup (problem, slice):
+// `per` (a multiple of 64) consecutive entries of the problem's element list,
+// 64 lanes across entries x 4 waves that split
+// the point ranges, then a fixed-shape LDS tree; a second kernel adds the
+// slice sums of each problem with another fixed-shape tree (bitwise
+// reproducible for a given mesh).
+template <int NC>
+__global__ __launch_bounds__(256) void problem_sums_kernel(int nchunk, int64_t pstride,
+                                                           int64_t per,
+                                                           const int64_t *pstart,
                                                            const int64_t *plist,
                                                            const double *part, double *out) {
-  __shared__ double red[6][256];
-  const int prob = blockIdx.x;
+  __shared__ double red[NC][256];
+  const int prob = blockIdx.x, nslice = gridDim.y, slice = blockIdx.y;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int64_t b = pstart[prob], e = pstart[prob + 1];
-  double s[6] = {0, 0, 0, 0, 0, 0};
-  for (int64_t i = b + threadIdx.x; i < e; i += 256) {
-    const double *p = part + plist[i] * ncomp;
-    for (int c = 0; c < ncomp; ++c) s[c] += p[c];
+  const int64_t lo = b + (int64_t)slice * per;
+  const int64_t hi = lo + per < e ? lo + per : e;
+  double s[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) s[c] = 0;
+  for (int64_t i = lo + tx; i < hi; i += 64) {
+    const int64_t el = plist[i];
+    for (int ch = ty; ch < nchunk; ch += 4)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) s[c] += part[((int64_t)ch * NC + c) * pstride + el];
   }
-  for (int c = 0; c < ncomp; ++c) red[c][threadIdx.x] = s[c];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) red[c][threadIdx.x] = s[c];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w)
-      for (int c = 0; c < ncomp; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
     __syncthreads();
   }
-  if ((int)threadIdx.x < ncomp) out[(int64_t)prob * ncomp + threadIdx.x] = red[threadIdx.x][0];
+  if ((int)threadIdx.x < NC)
+    out[((int64_t)prob * nslice + slice) * NC + threadIdx.x] = red[threadIdx.x][0];
 }
 
-hipError_t launch_problem_sums(int ncomp, int nprob, const int64_t *pstart, const int64_t *plist,
-                               const double *part, double *out, hipStream_t s) {
-  problem_sums_kernel<<<nprob, 256, 0, s>>>(ncomp, pstart, plist, part, out);
+template <int NC>
+__global__ __launch_bounds__(256) void slice_sums_kernel(int nslice, const double *part2,
+                                                         double *out) {
+  __shared__ double red[NC][256];
+  const int prob = blockIdx.x;
+  double s[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) s[c] = 0;
+  for (int sl = threadIdx.x; sl < nslice; sl += 256)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) s[c] += part2[((int64_t)prob * nslice + sl) * NC + c];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) red[c][threadIdx.x] = s[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if ((int)threadIdx.x < NC) out[(int64_t)prob * NC + threadIdx.x] = red[threadIdx.x][0];
+}
+
+template <int NC>
+static void problem_sums_t(int nprob, int nchunk, int64_t pstride, int nslice, int64_t per,
+                           const int64_t *pstart, const int64_t *plist, const double *part,
+                           double *part2, double *out, hipStream_t s) {
+  dim3 grid((unsigned)nprob, (unsigned)nslice);
+  problem_sums_kernel<NC><<<grid, 256, 0, s>>>(nchunk, pstride, per, pstart, plist, part,
+                                               nslice == 1 ? out : part2);
+  if (nslice > 1) slice_sums_kernel<NC><<<nprob, 256, 0, s>>>(nslice, part2, out);
+}
+
+hipError_t launch_problem_sums(int ncomp, int nprob, int nchunk, int64_t pstride, int nslice,
+                               int64_t per, const int64_t *pstart, const int64_t *plist,
+                               const double *part, double *part2, double *out, hipStream_t s) {
+  if (per < 64 || per % 64 || nslice < 1) return hipErrorInvalidValue;
+  if (ncomp == 5)
+    problem_sums_t<5>(nprob, nchunk, pstride, nslice, per, pstart, plist, part, part2, out, s);
+  else if (ncomp == 6)
+    problem_sums_t<6>(nprob, nchunk, pstride, nslice, per, pstart, plist, part, part2, out, s);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -12,9 +12,10 @@
 // fixed width W per row (ELL: padding entries have value 0 and repeat a real
 // column), W is a template parameter, so all W loads of a row are issued
 // back to back; column indices and values are wave-uniform (scalar loads).
-// The column grid is padded to a multiple of the 8 XCDs so that every
-// workgroup row of one column tile runs on the same XCD and re-reads of B
-// hit that XCD's L2; HBM sees each input and output about once.
+// The grid is one-dimensional and XCD-aware: workgroups are dealt round-robin
+// to the 8 XCDs, and the linear id is remapped so that each XCD runs all row
+// groups of one column tile back to back; re-reads of that tile's B rows then
+// hit the XCD's L2 while they are still there.
 #include "kernels.h"
 
 namespace fr {
@@ -22,12 +23,19 @@ namespace fr {
 template <typename T, int EPI, int W, typename TB1, typename TB2, typename TC>
 __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
                                                    const int32_t *__restrict__ colidx,
-                                                   const double *__restrict__ vals, int rpg) {
-  const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+                                                   const double *__restrict__ vals, int rpg,
+                                                   int ngroups) {
+  // linear id L -> XCD L % 8; the j-th workgroup of an XCD takes row group
+  // j % ngroups of column tile 8 (j / ngroups) + L % 8 (tiles padded to a
+  // multiple of 8 by the launch)
+  const int64_t L = blockIdx.x, j = L >> 3;
+  const int64_t tile = (j / ngroups) * 8 + (L & 7);
+  const int rgrp = (int)(j % ngroups);
+  const int64_t col = tile * 256 + threadIdx.x;
   if (col >= g.N) return;
-  const int r0 = blockIdx.y * rpg;
+  const int r0 = rgrp * rpg;
   const int r1 = r0 + rpg < g.M ? r0 + rpg : g.M;
-  const TB1 *__restrict__ B1b = (const TB1 *)g.B1 + (int64_t)blockIdx.z * g.sB1;
+  const TB1 *__restrict__ B1b = (const TB1 *)g.B1 + (int64_t)blockIdx.y * g.sB1;
   const TB1 *__restrict__ B1 = B1b + col;
   const TB2 *__restrict__ B2 = (const TB2 *)g.B2 + col;
   int64_t n = 0;
@@ -63,9 +71,9 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
     for (int e = 0; e < W; ++e) acc += (T)cv[e] * b[e];
     const int64_t idx = (int64_t)row * g.ldc + col;
     if (EPI == EPI_STORE) {
-      ((TC *)g.C)[(int64_t)blockIdx.z * g.sC + idx] = (TC)acc;
+      ((TC *)g.C)[(int64_t)blockIdx.y * g.sC + idx] = (TC)acc;
     } else if (EPI == EPI_ADD) {
-      TC *cp = (TC *)g.C + (int64_t)blockIdx.z * g.sC + idx;
+      TC *cp = (TC *)g.C + (int64_t)blockIdx.y * g.sC + idx;
       *cp = (TC)((double)*cp + (double)acc);
     } else {
       const double kk = live ? -g.rcpdjac[(int64_t)row * g.ld + n] * (double)acc : 0.0;
@@ -87,21 +95,20 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
 
 template <typename T, int EPI, int W>
 static void spop_launch_w(const GemmArgs &g, const SparseOp &sp, int batch, hipStream_t s) {
-  // column tiles padded to a multiple of 8: linear id % 8 (the XCD) then
-  // depends on blockIdx.x only
-  const unsigned gx = (unsigned)(((g.N + 255) / 256 + 7) / 8 * 8);
-  dim3 grid(gx, (unsigned)((g.M + sp.rpg - 1) / sp.rpg), batch);
+  const int64_t tiles = ((g.N + 255) / 256 + 7) / 8 * 8;
+  const int ngroups = (g.M + sp.rpg - 1) / sp.rpg;
+  dim3 grid((unsigned)(tiles * ngroups), batch);
   if constexpr (sizeof(T) == 8) {
-    spop_kernel<T, EPI, W, double, double, double><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg);
+    spop_kernel<T, EPI, W, double, double, double><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
   } else if constexpr (EPI == EPI_NEGDIV || EPI == EPI_RK) {
-    spop_kernel<T, EPI, W, float, float, double><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg);
+    spop_kernel<T, EPI, W, float, float, double><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
   } else {
     if (!g.b1_f32)
-      spop_kernel<T, EPI, W, double, double, float><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg);
+      spop_kernel<T, EPI, W, double, double, float><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
     else if (!g.b2_f32)
-      spop_kernel<T, EPI, W, float, double, float><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg);
+      spop_kernel<T, EPI, W, float, double, float><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
     else
-      spop_kernel<T, EPI, W, float, float, float><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg);
+      spop_kernel<T, EPI, W, float, float, float><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
   }
 }
 

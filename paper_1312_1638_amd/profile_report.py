@@ -1,0 +1,154 @@
+"""Summaries of rocprofv3 output for the kernels of this library.
+
+    python -m paper_1312_1638_amd.profile_report stats DIR
+        Markdown table of the kernel statistics (``*_kernel_stats.csv``) that
+        ``rocprofv3 --kernel-trace --stats --output-format csv -d DIR`` wrote.
+
+    python -m paper_1312_1638_amd.profile_report traffic FETCH_DIR WRITE_DIR \\
+            --workload NAME --step NAME --kernel SUBSTRING [--last N]
+        HBM traffic per dispatch of the kernels whose name contains SUBSTRING
+        (the last N such dispatches),
+        from one ``rocprofv3 --pmc FETCH_SIZE`` and one ``--pmc WRITE_SIZE``
+        run (KiB per dispatch), each scaled by what the same counter reads for
+        the library's triad kernel (fr_measure_ceiling kind 0: reads 4 GiB and
+        writes 2 GiB per dispatch).  Prints one table row in the format
+        bench.py reads, with the hash of the library sources it was taken on.
+"""
+import argparse
+import csv
+import glob
+import hashlib
+import os
+import sys
+
+TRIAD_FETCH_KIB = 4 * 1024 * 1024
+TRIAD_WRITE_KIB = 2 * 1024 * 1024
+TRIAD_NAME = "triad_kernel"
+
+
+def source_hash(root=None):
+    """Hash of every source of the native library (kernels and host code)."""
+    root = root or os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(root)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(root, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def _csv_rows(d, suffix):
+    files = glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)
+    if not files:
+        sys.exit(f"no *{suffix} under {d}")
+    rows = []
+    for f in files:
+        with open(f, newline="") as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def _col(row, *names):
+    low = {k.lower(): k for k in row}
+    for n in names:
+        if n.lower() in low:
+            return row[low[n.lower()]]
+    raise KeyError(names)
+
+
+def stats(d):
+    rows = _csv_rows(d, "_kernel_stats.csv")
+    rows.sort(key=lambda r: -float(_col(r, "TotalDurationNs")))
+    print("| kernel | calls | avg us | min us | max us | total ms | % |")
+    print("|---|---|---|---|---|---|---|")
+    for r in rows:
+        name = _col(r, "Name", "KernelName")
+        print(f"| `{name[:110]}` | {_col(r, 'Calls')} | {float(_col(r, 'AverageNs')) / 1e3:.2f} | "
+              f"{float(_col(r, 'MinNs')) / 1e3:.2f} | {float(_col(r, 'MaxNs')) / 1e3:.2f} | "
+              f"{float(_col(r, 'TotalDurationNs')) / 1e6:.3f} | {float(_col(r, 'Percentage')):.1f} |")
+
+
+def _per_dispatch(d, counter):
+    """{kernel name: [value per dispatch]} for one counter (summed over the
+    counter's instances within a dispatch)."""
+    rows = _csv_rows(d, "_counter_collection.csv")
+    acc = {}
+    for r in rows:
+        if _col(r, "Counter_Name") != counter:
+            continue
+        key = (_col(r, "Kernel_Name"), _col(r, "Dispatch_Id"))
+        acc[key] = acc.get(key, 0.0) + float(_col(r, "Counter_Value"))
+    out = {}
+    for (name, disp), v in acc.items():
+        out.setdefault(name, []).append((int(disp), v))
+    return out
+
+
+def _mean_for(per, sub, last=0):
+    """Mean over the dispatches of kernels whose name contains `sub` (the
+    last `last` of them if > 0, in dispatch order)."""
+    vals = [(i, v) for name, vs in per.items() if sub in name for i, v in vs]
+    vals.sort()
+    if last > 0:
+        vals = vals[-last:]
+    vals = [v for _, v in vals]
+    if not vals:
+        sys.exit(f"no dispatch of a kernel matching {sub!r}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def traffic(fetch_dir, write_dir, workload, step, kernel, last=0):
+    fe = _per_dispatch(fetch_dir, "FETCH_SIZE")
+    wr = _per_dispatch(write_dir, "WRITE_SIZE")
+    tf, _ = _mean_for(fe, TRIAD_NAME)
+    tw, _ = _mean_for(wr, TRIAD_NAME)
+    kf, nf = _mean_for(fe, kernel, last)
+    kw, nw = _mean_for(wr, kernel, last)
+    ff, fw = TRIAD_FETCH_KIB / tf, TRIAD_WRITE_KIB / tw
+    total = (kf * ff + kw * fw) * 1024.0
+    print("| workload | step | kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | "
+          "fetch scale | write scale | HBM bytes per launch | sources |")
+    print("|---|---|---|---|---|---|---|---|---|---|")
+    print(f"| {workload} | {step} | `{kernel}` | {nf}/{nw} | {kf:.1f} | {kw:.1f} | {ff:.4f} | "
+          f"{fw:.4f} | {total:.0f} | {source_hash()} |")
+
+
+def read_traffic_table(path, workload, step):
+    """HBM bytes per launch for (workload, step) from a table written by
+    `traffic`, or None if absent or taken on other library sources."""
+    if not os.path.exists(path):
+        return None
+    h = source_hash()
+    with open(path) as fh:
+        for line in fh:
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) == 10 and cells[0] == workload and cells[1] == step:
+                return float(cells[8]) if cells[9] == h else None
+    return None
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("dir")
+    b = sub.add_parser("traffic")
+    b.add_argument("fetch_dir")
+    b.add_argument("write_dir")
+    b.add_argument("--workload", required=True)
+    b.add_argument("--step", required=True)
+    b.add_argument("--kernel", required=True)
+    b.add_argument("--last", type=int, default=0,
+                   help="use only the last N matching dispatches")
+    sub.add_parser("hash")
+    args = ap.parse_args(argv)
+    if args.cmd == "stats":
+        stats(args.dir)
+    elif args.cmd == "traffic":
+        traffic(args.fetch_dir, args.write_dir, args.workload, args.step, args.kernel, args.last)
+    else:
+        print(source_hash())
+
+
+if __name__ == "__main__":
+    main()

@@ -159,6 +159,27 @@ def test_integrals_and_conservation():
     assert np.all(np.abs(r[:-1]) < 1e-13 * scale)
 
 
+def _ke(u, ndims):
+    rho, m = u[:, 0], u[:, 1:1 + ndims]
+    return 0.5 * np.sum(m * m, axis=1) / rho
+
+
+@pytest.mark.parametrize("n", [6, 16])
+def test_integrals_single_large_problem(n):
+    """Integrals of a single-problem hex mesh, large enough that the library
+    splits points into ranges and the element list into slices."""
+    w = configs.taylor_green_hexes(n, 3)
+    d, s, u = _both(w)
+    got = s.integrate(s.pack(u)).cpu().numpy()[0]
+    rf, g, ub = d.refs[0], d.geoms[0], u[0]
+    ref = np.einsum("r,rn,ran->a", rf.W, g.detJ.T, ub)
+    ke = np.einsum("r,rn,rn->", rf.W, g.detJ.T, _ke(ub, 3))
+    print(f"n={n}: integrals rel err {np.abs(got[:-1] - ref).max() / np.abs(ref).max():.2e}, "
+          f"kinetic energy rel err {abs(got[-1] - ke) / ke:.2e}")
+    assert np.allclose(got[:-1], ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+    assert abs(got[-1] - ke) <= 1e-13 * ke
+
+
 def test_check_finite():
     import paper_1312_1638_amd as P
     w = configs.vortex_quads(4, 2)
