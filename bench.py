@@ -128,9 +128,11 @@ def time_steps(s, u, dt, steps, warmup, torch):
     return time.perf_counter() - t0
 
 
-def plan_name(plan):
+def plan_name(plan, step=0):
     mbw, nc, wm = plan
-    return f"sparse-row rpg={nc}" if mbw == 0 else f"mfma {mbw}x{nc} wm={wm}"
+    if mbw == 0:
+        return f"sparse-row rpg={nc}" + (" + fused J^-T (step 4)" if step == 3 and wm == 1 else "")
+    return f"mfma {mbw}x{nc} wm={wm}"
 
 
 def time_kernels(s, u, torch, nrep=50):
@@ -278,7 +280,7 @@ def main():
         kernels[STEP_NAMES[st]] = dict(us=round(t * 1e6, 2), GBps=round(b_ / t / 1e9, 1),
                                        TFLOPs=round(f_ / t / 1e12, 2))
         if st in (1, 3, 5, 8):
-            kernels[STEP_NAMES[st]]["plan"] = plan_name(s.gemm_plan(0, st))
+            kernels[STEP_NAMES[st]]["plan"] = plan_name(s.gemm_plan(0, st), st)
 
     extra = {}
     if not args.no_fp32:
@@ -289,7 +291,7 @@ def main():
             ktr = time_kernels(sr, sr.pack(u0), torch)
             extra[prec] = dict(value=4.0 * dof * args.steps / elr, ms_per_step=elr / args.steps * 1e3,
                                kernels_us={STEP_NAMES[k]: round(v * 1e6, 2) for k, v in ktr.items()},
-                               plans={STEP_NAMES[k]: plan_name(sr.gemm_plan(0, k)) for k in ktr
+                               plans={STEP_NAMES[k]: plan_name(sr.gemm_plan(0, k), k) for k in ktr
                                       if k in (1, 3, 5, 8)})
             sr.close()
 

@@ -217,13 +217,23 @@ fr_status fr_debug_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, const d
  * plan (mbw, nc, wm) (mbw = 0: default plan); operands are internal.
  * fr_get_gemm_plan: the tile plan a context uses for right-hand-side step
  * 1, 3, 5 or 8 of `block` (mbw = 0: the sparse-row kernel, nc rows per
- * workgroup). */
+ * workgroup; for step 3, wm = 1 then means that the gradient transform of
+ * step 4 is fused into its epilogue and step 4 launches nothing). */
 fr_status fr_measure_ceiling(int32_t kind, double *value, void *hip_stream);
 fr_status fr_bench_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, int64_t N,
                         int32_t mbw, int32_t nc, int32_t wm, int32_t batch, int32_t nrep,
                         float *ms_per_launch, void *hip_stream);
 fr_status fr_get_gemm_plan(const fr_ctx *ctx, int32_t block, int32_t step, int32_t *mbw,
                            int32_t *nc, int32_t *wm);
+/* fr_debug_set_plan forces the plan of right-hand-side step 1, 3, 5 or 8 of
+ * `block` (test support: drives every kernel variant through the full
+ * chain): mbw > 0 a matrix-core plan (mbw, nc, wm) as for fr_debug_gemm;
+ * mbw = 0 the sparse-row kernel with nc rows per workgroup, wm = 1 (step 3
+ * only) with the gradient transform fused.  FR_EINVAL for an invalid plan
+ * or an operator without a sparse form.  Drops the captured RK4 graph.
+ * Synchronous on hip_stream. */
+fr_status fr_debug_set_plan(fr_ctx *ctx, int32_t block, int32_t step, int32_t mbw, int32_t nc,
+                            int32_t wm, void *hip_stream);
 
 /* Gradient of an integral of fr_integrate with respect to the state: kind 1
  * (kinetic energy, summed over problems) -> grad (DEVICE, state layout),

@@ -25,7 +25,7 @@ EXPORTS = ("fr_setup_mesh", "fr_get_layout", "fr_get_solution_points", "fr_get_q
            "fr_rhs", "fr_rk_step", "fr_rhs_adjoint", "fr_rk_step_adjoint", "fr_integrate",
            "fr_reference_operator", "fr_check_mesh", "fr_debug_stage", "fr_debug_scratch_len", "fr_bench_step",
            "fr_debug_gemm", "fr_measure_ceiling", "fr_bench_gemm", "fr_get_gemm_plan", "fr_integrate_grad", "fr_stash_len", "fr_rk_step_stash",
-           "fr_rk_step_adjoint_stash",
+           "fr_rk_step_adjoint_stash", "fr_debug_set_plan",
            "fr_last_error", "fr_destroy")
 
 
@@ -96,6 +96,7 @@ def load_library(path: str = LIB_PATH):
         "fr_get_gemm_plan": [vp, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                              ctypes.POINTER(i32)],
         "fr_debug_gemm": [i32, i32, i32, i32, dp, dp, dp, i64, dp, i64, i32, i32, i32, vp],
+        "fr_debug_set_plan": [vp, i32, i32, i32, i32, i32, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -372,6 +373,11 @@ class Solver:
         _check(self.L.fr_get_gemm_plan(self.ctx, block, step, ctypes.byref(m), ctypes.byref(n),
                                        ctypes.byref(w)), self.ctx)
         return (m.value, n.value, w.value)
+
+    def set_plan(self, block, step, plan):
+        """Force the (mbw, nc, wm) plan of RHS step 1, 3, 5 or 8 of a block."""
+        _check(self.L.fr_debug_set_plan(self.ctx, block, step, plan[0], plan[1], plan[2],
+                                        self._stream()), self.ctx)
 
     def integrate(self, u):
         """[nproblems, nvars + 1]: integral of every field, then kinetic energy."""

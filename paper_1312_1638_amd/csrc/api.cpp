@@ -55,6 +55,7 @@ struct fr_ctx {
   fr_config cfg{};
   int D = 0, NV = 0;
   bool ns = false;
+  bool no_fuse = false;  // run step 4 on its own even where step 3 would fuse it
   int prec = 0;
   size_t tsize = 8;  // element size of the scratch arrays
   std::string err = "no error";
@@ -210,6 +211,12 @@ void make_op(fr_ctx *c, GemmOp &op, const std::vector<double> &A, int M, int K1,
   }
 }
 
+// Step 3 with the gradient transform (step 4) fused into its epilogue: a
+// sparse-row plan of the [M6|M4'] operator with WM = 1.
+bool gradt_fused(const fr_ctx *c, const BlockRT &b) {
+  return c->ns && !c->no_fuse && b.s3.MBW == 0 && b.s3.WM == 1;
+}
+
 // Launch an operator product with whichever kernel its plan names.
 hipError_t launch_op(const GemmOp &op, int gprec, int epi, const fr::GemmArgs &g, int batch,
                      hipStream_t s) {
@@ -307,9 +314,16 @@ void run_step(fr_ctx *c, int st, const double *u, double *dudt, int epi, const f
       g.B2 = u + b.uoff; g.ldb2 = N; g.b2_f32 = 0;
       g.C = elem(c->cur.ft, b.ftoff, ts); g.ldc = N; g.c_f32 = f32;
       g.N = N;
-      hip_check(launch_op(b.s3, gprec, fr::EPI_STORE, g, 1, s), "gemm M6|M4'");
+      if (gradt_fused(c, b)) {
+        g.rcpdjac = b.d_rcpdjac; g.ld = b.ld; g.nelem = b.nelem;
+        g.smat = b.d_smat; g.D = D; g.Nu = b.Nu;
+        hip_check(launch_op(b.s3, gprec, fr::EPI_GRADT, g, 1, s), "gemm M6|M4' + J^-T");
+      } else {
+        hip_check(launch_op(b.s3, gprec, fr::EPI_STORE, g, 1, s), "gemm M6|M4'");
+      }
     } else if (st == 4) {
-      hip_check(fr::launch_gradcoru(point_args(c, b, u), s), "gradcoru");
+      if (!gradt_fused(c, b))
+        hip_check(fr::launch_gradcoru(point_args(c, b, u), s), "gradcoru");
     } else if (st == 5) {
       fr::GemmArgs g = gemm_args(b.m5);
       g.B1 = elem(c->cur.ft, b.ftoff, ts); g.ldb1 = N; g.b1_f32 = f32; g.b2_f32 = f32;
@@ -349,10 +363,11 @@ void rhs_chain(fr_ctx *c, const double *u, double *dudt, int epi, const fr::RkCo
 // real scratch arrays as operands, HIP events on the set-up stream) and keep
 // the fastest.  Results are memoised per shape for the process.
 struct TuneKey {
-  int prec, M, K1, K2, batch, epi;
+  int prec, M, K1, K2, batch, epi, step;
   int64_t N;
   bool operator<(const TuneKey &o) const {
-    return std::tie(prec, M, K1, K2, batch, epi, N) < std::tie(o.prec, o.M, o.K1, o.K2, o.batch, o.epi, o.N);
+    return std::tie(prec, M, K1, K2, batch, epi, step, N) <
+           std::tie(o.prec, o.M, o.K1, o.K2, o.batch, o.epi, o.step, o.N);
   }
 };
 std::map<TuneKey, fr::GemmPlan> g_tuned;
@@ -361,7 +376,7 @@ void tune_op(fr_ctx *c, GemmOp &op, int step, BlockRT &b, hipStream_t s) {
   const int batch = step == 5 ? c->D : 1;
   const int epi = step == 8 ? fr::EPI_NEGDIV : fr::EPI_STORE;
   const int64_t N = (int64_t)c->NV * b.ld;
-  TuneKey key{c->prec, op.M, op.K1, op.K2, batch, epi, N};
+  TuneKey key{c->prec, op.M, op.K1, op.K2, batch, epi, step, N};
   fr::GemmPlan best{op.MBW, op.NC, op.WM};
   auto it = g_tuned.find(key);
   if (it != g_tuned.end()) {
@@ -374,6 +389,10 @@ void tune_op(fr_ctx *c, GemmOp &op, int step, BlockRT &b, hipStream_t s) {
     std::vector<fr::GemmPlan> cands = fr::gemm_candidates(op.M, N, c->prec);
     if (op.sp.colidx)
       for (int rpg : {4, 8, 16, 32, 64}) cands.push_back(fr::GemmPlan{0, rpg, 0});
+    // step 3: also the plans with the gradient transform fused (WM = 1); every
+    // candidate is timed together with step 4 (a no-op when fused)
+    if (step == 3 && op.sp.colidx)
+      for (int rpg : {1, 2, 4, 8, 16}) cands.push_back(fr::GemmPlan{0, rpg, 1});
     for (const fr::GemmPlan &p : cands) {
       void *d = p.MBW ? pack_upload(c, op, p, s, false) : nullptr;
       GemmOp trial = op;
@@ -382,9 +401,15 @@ void tune_op(fr_ctx *c, GemmOp &op, int step, BlockRT &b, hipStream_t s) {
       std::swap(*(step == 1 ? &b.m0 : step == 3 ? &b.s3 : step == 5 ? &b.m5 : &b.s8), trial);
       float ms = 0;
       try {
-        for (int w = 0; w < 2; ++w) run_step(c, step, c->d_stage, c->d_acc, epi, nullptr, nullptr, s);
+        for (int w = 0; w < 2; ++w) {
+          run_step(c, step, c->d_stage, c->d_acc, epi, nullptr, nullptr, s);
+          if (step == 3) run_step(c, 4, c->d_stage, c->d_acc, epi, nullptr, nullptr, s);
+        }
         hip_check(hipEventRecord(e0, s), "record");
-        for (int w = 0; w < 5; ++w) run_step(c, step, c->d_stage, c->d_acc, epi, nullptr, nullptr, s);
+        for (int w = 0; w < 5; ++w) {
+          run_step(c, step, c->d_stage, c->d_acc, epi, nullptr, nullptr, s);
+          if (step == 3) run_step(c, 4, c->d_stage, c->d_acc, epi, nullptr, nullptr, s);
+        }
         hip_check(hipEventRecord(e1, s), "record");
         hip_check(hipEventSynchronize(e1), "sync");
         hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
@@ -485,7 +510,7 @@ void adj_gemm(fr_ctx *c, const GemmOp &op, const double *B1, const double *B2, d
 // Autotune one transposed operator of the adjoint with its real operands.
 void tune_adj(fr_ctx *c, GemmOp &op, const double *B1, const double *B2, double *C, int64_t N,
               int epi, int batch, int64_t sB1, int64_t sC, hipStream_t s) {
-  TuneKey key{c->prec, op.M, op.K1, op.K2, batch, 10 + epi, N};
+  TuneKey key{c->prec, op.M, op.K1, op.K2, batch, 10 + epi, 0, N};
   fr::GemmPlan best{op.MBW, op.NC, op.WM};
   auto it = g_tuned.find(key);
   if (it != g_tuned.end()) {
@@ -1145,7 +1170,10 @@ fr_status fr_debug_stage(fr_ctx *c, const double *u, int32_t stage, double *out,
   if (!c->ns && stage >= 2 && stage <= 5) return fail(c, FR_EINVAL, "no such stage for Euler");
   hipStream_t s = (hipStream_t)hip_stream;
   try {
+    // Q~ itself exists only when step 4 runs on its own
+    c->no_fuse = stage == 3;
     rhs_chain(c, u, nullptr, fr::EPI_NEGDIV, nullptr, nullptr, s, stage);
+    c->no_fuse = false;
     const void *src = nullptr;
     int64_t n = 0;
     if (stage == 1 || stage == 7) { src = c->d_uf; n = c->uf_len; }
@@ -1154,6 +1182,7 @@ fr_status fr_debug_stage(fr_ctx *c, const double *u, int32_t stage, double *out,
     else { src = c->d_ft; n = c->ft_len; }
     hip_check(hipMemcpyAsync(out, src, n * sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
   } catch (const Fail &f) {
+    c->no_fuse = false;
     return fail(c, f.st, f.msg);
   }
   return FR_OK;
@@ -1285,6 +1314,35 @@ fr_status fr_get_gemm_plan(const fr_ctx *c, int32_t block, int32_t step, int32_t
   const GemmOp *op = step == 1 ? &b.m0 : step == 3 ? &b.s3 : step == 5 ? &b.m5 : step == 8 ? &b.s8 : nullptr;
   if (!op || (!c->ns && (step == 3 || step == 5))) return FR_EINVAL;
   *mbw = op->MBW; *nc = op->NC; *wm = op->WM;
+  return FR_OK;
+}
+
+fr_status fr_debug_set_plan(fr_ctx *c, int32_t block, int32_t step, int32_t mbw, int32_t nc,
+                            int32_t wm, void *hip_stream) {
+  if (!c || block < 0 || block >= (int)c->blocks.size()) return FR_EINVAL;
+  BlockRT &b = c->blocks[block];
+  GemmOp *op = step == 1 ? &b.m0 : step == 3 ? &b.s3 : step == 5 ? &b.m5 : step == 8 ? &b.s8 : nullptr;
+  if (!op || (!c->ns && (step == 3 || step == 5))) return fail(c, FR_EINVAL, "no such step");
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    fr::GemmPlan p{mbw, nc, wm};
+    if (mbw > 0) {
+      if (!fr::gemm_plan_valid(mbw, nc) || wm < 1 || mbw * wm * 16 < op->M)
+        throw Fail{FR_EINVAL, "bad matrix-core plan"};
+      op->d_A = pack_upload(c, *op, p, s, true);
+    } else {
+      if (!op->sp.colidx) throw Fail{FR_EINVAL, "operator has no sparse-row form"};
+      if (nc < 1 || wm < 0 || wm > 1 || (wm == 1 && step != 3))
+        throw Fail{FR_EINVAL, "bad sparse-row plan"};
+      op->d_A = nullptr;
+      op->sp.rpg = nc;
+    }
+    op->MBW = mbw; op->NC = nc; op->WM = wm;
+    hip_check(hipStreamSynchronize(s), "sync");
+    release_graph(c);  // a captured step holds the previous plan's launches
+  } catch (const Fail &f) {
+    return fail(c, f.st, f.msg);
+  }
   return FR_OK;
 }
 

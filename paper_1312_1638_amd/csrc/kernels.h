@@ -16,7 +16,9 @@ enum GemmEpi {
   EPI_STORE = 0,   // C[row][col] = acc                         (C of type TC)
   EPI_NEGDIV = 1,  // out = -rcpdjac[row][n] * acc, 0 for padding  (FP64 out)
   EPI_RK = 2,      // RK4 stage update from k = -rcpdjac * acc      (FP64 regs)
-  EPI_ADD = 3      // C[row][col] += acc (FP64 only; adjoint accumulation)
+  EPI_ADD = 3,     // C[row][col] += acc (FP64 only; adjoint accumulation)
+  EPI_GRADT = 4    // sparse-row kernel only: the D rows d Nu + rho of one point
+                   // are transformed by J^-T = S^T / det J before the store
 };
 
 enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };
@@ -47,6 +49,7 @@ struct GemmArgs {
   double *acc; double *stage;
   const double *dt; const int32_t *prob;      // per-problem step size, element -> problem
   RkCoef rk;
+  const double *smat; int D; int Nu;          // EPI_GRADT: S = adj J [D][D][Nu][ld]
 };
 
 // Pack A (M x (K1 + K2), row-major, panel 2 columns follow panel 1) into the

@@ -67,6 +67,63 @@ def test_rhs_small_bf16x3(name):
     assert err < tol and eu < 1e-5
 
 
+def _force_plans(s, w, variant):
+    """Force one kernel family on every operator product of every block:
+    'mfma' (matrix cores), 'sparse' (sparse-row, 4 rows per workgroup) or
+    'fused' (sparse-row, the gradient transform fused into step 3).  Dense
+    triangle operators have no sparse-row form and keep their plan."""
+    import paper_1312_1638_amd as P
+    steps = [1, 3, 5, 8] if w.system == "ns" else [1, 8]
+    forced = 0
+    for bi, b in enumerate(w.mesh.blocks):
+        nu = s.blocks[bi]["nupts"]
+        nf = P.reference_operator(b.etype, b.order, 6).shape[0]
+        rows = {1: nf, 3: s.ndims * nu, 5: nf, 8: nu}
+        for st in steps:
+            if variant == "mfma":
+                plan = (1, 1, -(-rows[st] // 16))
+            elif variant == "sparse":
+                plan = (0, 4, 0)
+            else:
+                plan = (0, 3, 1) if st == 3 else (0, 7, 0)
+            try:
+                s.set_plan(bi, st, plan)
+            except P.FRError:
+                assert b.etype == "tri" and variant != "mfma"
+                continue
+            assert s.gemm_plan(bi, st) == plan
+            forced += 1
+    assert forced > 0
+
+
+@pytest.mark.parametrize("name", ["tgv3_p4", "mixed5_p2_ns", "curved3_p2_ns", "vortex7_p3",
+                                  "mixed6_p3_euler"])
+@pytest.mark.parametrize("variant", ["mfma", "sparse", "fused"])
+def test_every_kernel_variant(name, variant):
+    """du/dt and u after 3 RK4 steps (captured graph) with every operator
+    product forced onto one kernel family."""
+    w = C.SMALL[name]()
+    d, s, u = _both(w)
+    _force_plans(s, w, variant)
+    err = C.rel_l2(s.unpack(s.rhs(s.pack(u))), d.rhs(u))
+    t = s.pack(u)
+    dt = 1e-4
+    s.step(t, dt, 3)
+    eu = C.rel_l2(s.unpack(t), d.rk4(u, dt, 3))
+    print(f"{name} {variant}: rhs rel L2 {err:.3e}, u(3) {eu:.3e}")
+    assert err < 1e-12 and eu < 1e-12
+
+
+def test_fused_gradient_transform_fp32():
+    w = C.SMALL["tgv5_p3"]()
+    d, s, u = _both(w, "fp32")
+    _force_plans(s, w, "fused")
+    tol, ext, floor = C.floor_tolerance(d, u, 1e-5, C.FP32_OVER_FP64)
+    err = C.rel_l2(s.unpack(s.rhs(s.pack(u))), ext)
+    print(f"tgv5_p3 fp32 fused: rel L2 {err:.3e} (tol {tol:.2e})")
+    assert err < tol
+
+
 def test_rhs_alias_in_place():
     w = C.SMALL["mixed5_p2_ns"]()
     d, s, u = _both(w)
