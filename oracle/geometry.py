@@ -17,15 +17,15 @@ import numpy as np
 from .reference import lagrange_1d
 
 
-def shape_functions(etype, g, xi):
+def shape_functions(etype, g, xi, dtype=np.float64):
     """Values (m, nnodes) and reference gradients (m, nnodes, D) of the
     geometry shape functions at reference points xi (m, D)."""
-    xi = np.asarray(xi, dtype=np.float64)
+    xi = np.asarray(xi, dtype=dtype)
     if etype in ("quad", "hex"):
         D = xi.shape[1]
         nodes = np.linspace(-1.0, 1.0, g + 1)
         vd = [lagrange_1d(nodes, xi[:, d]) for d in range(D)]
-        vd = [(v.astype(np.float64), dv.astype(np.float64)) for v, dv in vd]
+        vd = [(v.astype(dtype), dv.astype(dtype)) for v, dv in vd]
         n1 = g + 1
 
         def comb(parts):
@@ -44,7 +44,7 @@ def shape_functions(etype, g, xi):
         l0 = -(xi[:, 0] + xi[:, 1]) / 2
         l1 = (1 + xi[:, 0]) / 2
         l2 = (1 + xi[:, 1]) / 2
-        dl = np.array([[-0.5, -0.5], [0.5, 0.0], [0.0, 0.5]])   # d lambda_k / d xi
+        dl = np.array([[-0.5, -0.5], [0.5, 0.0], [0.0, 0.5]], dtype=dtype)   # d lambda_k / d xi
         lam = [l0, l1, l2]
         if g == 1:
             val = np.stack(lam, 1)
@@ -80,36 +80,44 @@ def adjugate(J):
     return S
 
 
-class BlockGeometry:
-    """Physical coordinates and metric terms of one element block."""
+def _det(J, S):
+    """det J from the adjugate (J S = det(J) I): sum_j J[0, j] S[j, 0]."""
+    return np.einsum("...j,...j->...", J[..., 0, :], S[..., :, 0])
 
-    def __init__(self, ref, block):
-        nodes = np.asarray(block.nodes, dtype=np.float64)       # (ne, nn, D)
+
+class BlockGeometry:
+    """Physical coordinates and metric terms of one element block (dtype
+    long double: the same formulas with 64-bit significands, used only to
+    measure rounding floors)."""
+
+    def __init__(self, ref, block, dtype=np.float64):
+        nodes = np.asarray(block.nodes).astype(dtype)           # (ne, nn, D)
         etype, g = block.etype, block.geom_order
         self.nelem = nodes.shape[0]
         # solution points
-        N, dN = shape_functions(etype, g, ref.upts)
+        N, dN = shape_functions(etype, g, ref.upts, dtype)
         self.xu = np.einsum("pk,ekd->epd", N, nodes)             # (ne, Nu, D)
         J = np.einsum("ekd,pkj->epdj", nodes, dN)               # (ne, Nu, D, D)
-        self.detJ = np.linalg.det(J)                             # (ne, Nu)
         self.S = adjugate(J)                                     # (ne, Nu, D, D)
+        self.detJ = _det(J, self.S)                              # (ne, Nu)
         # flux points
-        Nf, dNf = shape_functions(etype, g, ref.fpts)
+        Nf, dNf = shape_functions(etype, g, ref.fpts, dtype)
         self.xf = np.einsum("pk,ekd->epd", Nf, nodes)            # (ne, Nf, D)
         Jf = np.einsum("ekd,pkj->epdj", nodes, dNf)
         Sf = adjugate(Jf)
-        nu = np.einsum("epij,pi->epj", Sf, ref.fnorm)            # S^T n~
-        self.fmag = np.linalg.norm(nu, axis=-1)                  # J^(f) n^(f)
+        nu = np.einsum("epij,pi->epj", Sf, np.asarray(ref.fnorm).astype(dtype))   # S^T n~
+        self.fmag = np.sqrt(np.sum(nu * nu, axis=-1))            # J^(f) n^(f)
         self.fnhat = nu / self.fmag[..., None]                   # unit physical normal
-        self.detJf = np.linalg.det(Jf)
+        self.detJf = _det(Jf, Sf)
 
 
-def pair_flux_points(mesh, refs, geoms, tol_rel=1e-9):
+def pair_flux_points(mesh, refs, geoms, tol_rel=1e-9, allow_unpaired=False):
     """Match the flux points of every face pair by physical coordinate.
 
     Returns a dict of int arrays (lb, le, ls, rb, re, rs), one entry per flux
     point pair, in face-pair order.  Raises ValueError if a pair does not
-    match point for point.
+    match point for point, or if a flux point is paired more than once or
+    (unless allow_unpaired: a patch cut out of a larger mesh) not at all.
     """
     pairs = mesh.pairs
     h = mesh.info.get("h", 1.0)
@@ -155,6 +163,6 @@ def pair_flux_points(mesh, refs, geoms, tol_rel=1e-9):
         for b in range(len(refs)):
             s = res[side + "b"] == b
             np.add.at(counts[b], (res[side + "e"][s], res[side + "s"][s]), 1)
-    if any(np.any(c != 1) for c in counts):
+    if any(np.any(c > 1) or (not allow_unpaired and np.any(c != 1)) for c in counts):
         raise ValueError("flux points not paired exactly once")
     return res

@@ -36,7 +36,11 @@ def _es(spec, *ops):
 class Discretisation:
     """Set-up of one mesh: reference elements, geometry, flux-point pairs."""
 
-    def __init__(self, workload):
+    def __init__(self, workload, allow_unpaired=False):
+        """allow_unpaired: the mesh is a patch cut out of a larger mesh; faces
+        on its outer boundary have no partner and receive no common flux, so
+        du/dt is right only on elements whose face neighbours (Euler), and
+        their face neighbours (Navier-Stokes), are in the patch."""
         w = workload
         self.mesh = w.mesh
         self.ndims = w.mesh.ndims
@@ -49,42 +53,45 @@ class Discretisation:
         for g in self.geoms:
             if np.any(g.detJ <= 0) or np.any(g.detJf <= 0):
                 raise ValueError("non-positive Jacobian")
-        pr = geometry.pair_flux_points(w.mesh, self.refs, self.geoms)
+        pr = geometry.pair_flux_points(w.mesh, self.refs, self.geoms,
+                                       allow_unpaired=allow_unpaired)
         self.pairs = pr
         # flat index of a flux point (block, sigma, n) into the concatenation
         # of every block's (Nf, ne) flux-point array
         self.fbase = np.cumsum([0] + [r.nfpts * g.nelem for r, g in zip(self.refs, self.geoms)])
         self.gl = self._flat(pr["lb"], pr["ls"], pr["le"])
         self.gr = self._flat(pr["rb"], pr["rs"], pr["re"])
+        self.nL, self.magL, self.magR = self._pair_metrics(self.geoms)
+        self.dt_per_elem = None
+
+    def _pair_metrics(self, geoms):
+        """Unit normal of the L side (D, npairpts) and J^(f) n^(f) of both
+        sides at every flux-point pair."""
+        pr = self.pairs
         D = self.ndims
-        nL = np.empty((len(self.gl), D))
-        magL = np.empty(len(self.gl))
-        magR = np.empty(len(self.gl))
-        for b, g in enumerate(self.geoms):
+        dt = geoms[0].fmag.dtype
+        nL = np.empty((len(self.gl), D), dtype=dt)
+        magL = np.empty(len(self.gl), dtype=dt)
+        magR = np.empty(len(self.gl), dtype=dt)
+        for b, g in enumerate(geoms):
             s = pr["lb"] == b
             nL[s] = g.fnhat[pr["le"][s], pr["ls"][s]]
             magL[s] = g.fmag[pr["le"][s], pr["ls"][s]]
             s = pr["rb"] == b
             magR[s] = g.fmag[pr["re"][s], pr["rs"][s]]
-        self.nL = nL.T.copy()                       # (D, npairpts)
-        self.magL, self.magR = magL, magR
-        self.dt_per_elem = None
+        return nL.T.copy(), magL, magR
 
     def extended(self):
-        """A copy whose metric terms and normals are held in long double, so
-        ``rhs`` on long-double states evaluates the same formula with 64-bit
-        significands.  Used only to measure the FP64 rounding floor of a
-        case (how far an FP64 evaluation of this formula can sit from the
-        exact value of the same formula)."""
+        """A copy whose metric terms and normals are recomputed from the nodes
+        in long double, so ``rhs`` on long-double states evaluates the same
+        formula, geometry included, with 64-bit significands.  Used only to
+        measure the FP64 rounding floor of a case (how far an FP64 evaluation
+        of this formula can sit from the exact value of the same formula)."""
         import copy
         e = copy.copy(self)
-        e.geoms = [copy.copy(g) for g in self.geoms]
-        for g in e.geoms:
-            g.S = g.S.astype(np.longdouble)
-            g.detJ = g.detJ.astype(np.longdouble)
-        e.nL = self.nL.astype(np.longdouble)
-        e.magL = self.magL.astype(np.longdouble)
-        e.magR = self.magR.astype(np.longdouble)
+        e.geoms = [geometry.BlockGeometry(r, b, np.longdouble)
+                   for r, b in zip(self.refs, self.mesh.blocks)]
+        e.nL, e.magL, e.magR = self._pair_metrics(e.geoms)
         return e
 
     def _flat(self, b, s, e):
@@ -140,7 +147,7 @@ class Discretisation:
         if ns:
             # 2. common solution, assigned to both members of each pair
             c = physics.common_solution(uL, uR, P["ldg_beta"])
-            CF = np.empty_like(UF)
+            CF = np.zeros_like(UF)        # zero at unpaired points of a patch
             CF[:, self.gl] = c
             CF[:, self.gr] = c
             qfs = []
@@ -179,7 +186,7 @@ class Discretisation:
         qL = qf_flat[:, :, self.gl] if ns else None
         qR = qf_flat[:, :, self.gr] if ns else None
         F = physics.common_flux(uL, uR, qL, qR, self.nL, P)
-        DF = np.empty_like(UF)
+        DF = np.zeros_like(UF)
         DF[:, self.gl] = self.magL * F
         DF[:, self.gr] = -self.magR * F
         if record is not None:

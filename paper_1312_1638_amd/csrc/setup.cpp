@@ -433,13 +433,19 @@ static void shape(int etype, int g, const double *xi, double *N, double *dN) {
 static double map_point(int etype, int g, int D, const double *X, int nn, const double *xi,
                         double *x, double *S, std::vector<double> &N, std::vector<double> &dN) {
   shape(etype, g, xi, N.data(), dN.data());
+  // Node coordinates are taken relative to node 0 (the shape functions sum
+  // to one and their gradients to zero): the Jacobian of a small element far
+  // from the origin then keeps full relative precision instead of losing
+  // |x| / h of it to cancellation.
   double J[3][3] = {{0}};
   for (int d = 0; d < D; ++d) x[d] = 0;
-  for (int k = 0; k < nn; ++k)
+  for (int k = 1; k < nn; ++k)
     for (int d = 0; d < D; ++d) {
-      x[d] += N[k] * X[k * D + d];
-      for (int j = 0; j < D; ++j) J[d][j] += X[k * D + d] * dN[k * D + j];
+      const double rel = X[k * D + d] - X[d];
+      x[d] += N[k] * rel;
+      for (int j = 0; j < D; ++j) J[d][j] += rel * dN[k * D + j];
     }
+  for (int d = 0; d < D; ++d) x[d] += X[d];
   if (D == 2) {
     S[0] = J[1][1]; S[1] = -J[0][1]; S[2] = -J[1][0]; S[3] = J[0][0];
     return J[0][0] * J[1][1] - J[0][1] * J[1][0];

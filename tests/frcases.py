@@ -34,6 +34,43 @@ def floor_tolerance(d, u, stated, unit_ratio=1.0, factor=4.0):
     return max(stated, factor * floor * unit_ratio), ext, floor
 
 
+def patch(w, sample, rings):
+    """The sampled elements of a single-block workload plus `rings` layers of
+    face neighbours, as a workload of its own whose pairs are every face pair
+    between two patch elements (the oracle's allow_unpaired mode).  Returns
+    (workload, index of each sampled element in the patch)."""
+    import dataclasses
+    pr = w.mesh.pairs
+    le, re = pr["lelem"].astype(np.int64), pr["relem"].astype(np.int64)
+    b = w.mesh.blocks[0]
+    inside = np.zeros(b.nelem, bool)
+    inside[np.asarray(sample)] = True
+    for _ in range(rings):
+        touch = inside[le] | inside[re]
+        inside[le[touch]] = True
+        inside[re[touch]] = True
+    elems = np.nonzero(inside)[0]
+    local = -np.ones(b.nelem, np.int64)
+    local[elems] = np.arange(len(elems))
+    sel = inside[le] & inside[re]
+    sub = pr[sel].copy()
+    sub["lelem"] = local[le[sel]]
+    sub["relem"] = local[re[sel]]
+    blk = meshes.Block(b.etype, b.order, b.geom_order, b.nodes[elems])
+    mesh = meshes.Mesh(w.mesh.ndims, [blk], sub, info=dict(w.mesh.info))
+    return dataclasses.replace(w, mesh=mesh), local[np.asarray(sample)]
+
+
+def sampled_floor_tolerance(d, u, loc, stated, unit_ratio=1.0, factor=4.0):
+    """floor_tolerance restricted to the elements `loc` of a patch (the only
+    ones whose du/dt is complete).  Returns (tolerance, exact reference on
+    loc, floor)."""
+    ref64 = d.rhs(u)[0][:, :, loc]
+    ext = d.extended().rhs([x.astype(np.longdouble) for x in u])[0][:, :, loc].astype(np.float64)
+    floor = rel_l2([ref64], [ext])
+    return max(stated, factor * floor * unit_ratio), ext, floor
+
+
 FP32_OVER_FP64 = 2.0 ** 29   # unit roundoff ratio 2^-24 / 2^-53
 # BF16x3 products keep ~16 significant bits (hi + lo parts of both operands,
 # the lo*lo term dropped): unit ratio 2^-16 / 2^-53
