@@ -60,7 +60,7 @@ def step_model(s, step, ts):
     and state column (multiplications by structural zeros are not work)."""
     D, NV = s.ndims, s.nvars
     byts = flops = 0.0
-    for blk, b in zip(s.blocks, s.mesh.blocks):
+    for bi, (blk, b) in enumerate(zip(s.blocks, s.mesh.blocks)):
         ne, nu = blk["nelem"], blk["nupts"]
         nf = s.nfpts[b.etype, b.order]
         nnz = s.nnz[b.etype, b.order]
@@ -71,8 +71,11 @@ def step_model(s, step, ts):
         elif step == 3:
             flops += 2.0 * (nnz["M6"] + nnz["M4p"]) * cols
             byts += cols * (nf * ts + nu * 8 + D * nu * ts)
+            if s.fused_gradt[bi]:        # step 4 in the epilogue: S = adj J and 1/J
+                byts += (D * D + 1) * nu * ne * 8
         elif step == 4:
-            byts += 2.0 * D * nu * cols * ts + (D * D + 1) * nu * ne * 8
+            if not s.fused_gradt[bi]:
+                byts += 2.0 * D * nu * cols * ts + (D * D + 1) * nu * ne * 8
         elif step == 5:
             flops += 2.0 * D * nnz["M0"] * cols
             byts += D * cols * (nu + nf) * ts
@@ -106,6 +109,9 @@ def make_solver(workload, prec, P, configs):
                                    for k, i in (("M0", 0), ("M3", 1), ("M4p", 2), ("M6", 3),
                                                 ("M1p", 4))}
     s.npairs = P.check_mesh(w.mesh, w.system)
+    # step 3 with the gradient transform (step 4) fused into its epilogue
+    s.fused_gradt = [w.system == "ns" and s.gemm_plan(b, 3)[0] == 0 and s.gemm_plan(b, 3)[2] == 1
+                     for b in range(len(w.mesh.blocks))]
     u0 = [np.ascontiguousarray(np.transpose(w.ic(b, s.solution_points(b)), (1, 2, 0)))
           for b in range(len(w.mesh.blocks))]
     s.bench_dt = w.dt

@@ -4,6 +4,11 @@
         Markdown table of the kernel statistics (``*_kernel_stats.csv``) that
         ``rocprofv3 --kernel-trace --stats --output-format csv -d DIR`` wrote.
 
+    python -m paper_1312_1638_amd.profile_report trace DIR --kernel SUBSTRING [--last N]
+        Average duration (and VGPR count) of the dispatches of the kernels
+        whose name contains SUBSTRING in ``*_kernel_trace.csv`` (the last N
+        of them: the launches a timing loop made after set-up and tuning).
+
     python -m paper_1312_1638_amd.profile_report traffic FETCH_DIR WRITE_DIR \\
             --workload NAME --step NAME --kernel SUBSTRING [--last N]
         HBM traffic per dispatch of the kernels whose name contains SUBSTRING
@@ -66,6 +71,20 @@ def stats(d):
         print(f"| `{name[:110]}` | {_col(r, 'Calls')} | {float(_col(r, 'AverageNs')) / 1e3:.2f} | "
               f"{float(_col(r, 'MinNs')) / 1e3:.2f} | {float(_col(r, 'MaxNs')) / 1e3:.2f} | "
               f"{float(_col(r, 'TotalDurationNs')) / 1e6:.3f} | {float(_col(r, 'Percentage')):.1f} |")
+
+
+def trace(d, kernel, last=0):
+    rows = [r for r in _csv_rows(d, "_kernel_trace.csv") if kernel in _col(r, "Kernel_Name")]
+    if not rows:
+        sys.exit(f"no dispatch of a kernel matching {kernel!r}")
+    rows.sort(key=lambda r: int(_col(r, "Dispatch_Id")))
+    if last > 0:
+        rows = rows[-last:]
+    dur = [(int(_col(r, "End_Timestamp")) - int(_col(r, "Start_Timestamp"))) / 1e3 for r in rows]
+    names = sorted({_col(r, "Kernel_Name") for r in rows})
+    print(f"kernel(s): {'; '.join(n[:120] for n in names)}")
+    print(f"dispatches: {len(dur)}  average {sum(dur) / len(dur):.2f} us  min {min(dur):.2f} us  "
+          f"max {max(dur):.2f} us  VGPR {_col(rows[-1], 'VGPR_Count')}")
 
 
 def _per_dispatch(d, counter):
@@ -140,10 +159,16 @@ def main(argv=None):
     b.add_argument("--kernel", required=True)
     b.add_argument("--last", type=int, default=0,
                    help="use only the last N matching dispatches")
+    t = sub.add_parser("trace")
+    t.add_argument("dir")
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--last", type=int, default=0)
     sub.add_parser("hash")
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         stats(args.dir)
+    elif args.cmd == "trace":
+        trace(args.dir, args.kernel, args.last)
     elif args.cmd == "traffic":
         traffic(args.fetch_dir, args.write_dir, args.workload, args.step, args.kernel, args.last)
     else:
