@@ -110,7 +110,7 @@ def make_solver(workload, prec, P, configs):
                                                 ("M1p", 4))}
     s.npairs = P.check_mesh(w.mesh, w.system)
     # step 3 with the gradient transform (step 4) fused into its epilogue
-    s.fused_gradt = [w.system == "ns" and s.gemm_plan(b, 3)[0] == 0 and s.gemm_plan(b, 3)[2] == 1
+    s.fused_gradt = [w.system == "ns" and s.gemm_plan(b, 3)[0] == 0 and s.gemm_plan(b, 3)[2] & 1
                      for b in range(len(w.mesh.blocks))]
     u0 = [np.ascontiguousarray(np.transpose(w.ic(b, s.solution_points(b)), (1, 2, 0)))
           for b in range(len(w.mesh.blocks))]
@@ -136,8 +136,11 @@ def time_steps(s, u, dt, steps, warmup, torch):
 
 def plan_name(plan, step=0):
     mbw, nc, wm = plan
+    if mbw == 0 and wm & 4:
+        return "sparse-row LDS-staged" + (" + fused J^-T (step 4)" if step == 3 and wm & 1 else "")
     if mbw == 0:
-        return f"sparse-row rpg={nc}" + (" + fused J^-T (step 4)" if step == 3 and wm == 1 else "")
+        return (f"sparse-row rpg={nc}" + (" all fields per thread" if wm & 2 else "")
+                + (" + fused J^-T (step 4)" if step == 3 and wm & 1 else ""))
     return f"mfma {mbw}x{nc} wm={wm}"
 
 

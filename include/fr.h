@@ -189,8 +189,9 @@ fr_status fr_check_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *b
  * core kernel: A HOST row-major M x (K1 + K2); B1 (K1 rows), B2 (K2 rows)
  * DEVICE float64 with row stride ldb; C DEVICE (float64 for FP64, float32
  * for FP32) M x N, row stride N; N a multiple of 16.  (mbw, nc, wm) forces a
- * matrix-core tile plan; mbw = 0 with nc > 0 forces the sparse-row kernel
- * with nc operator rows per workgroup (FR_EINVAL if A is not sparse: at
+ * matrix-core tile plan; mbw = 0 with nc > 0 and wm = 0 forces the
+ * sparse-row kernel, one column per thread, with nc operator rows per
+ * workgroup (FR_EINVAL if A is not sparse: at
  * least half of its entries must be zero, or below 1e-13 of their row's
  * largest magnitude); mbw = nc = 0: the default plan.  Synchronous. */
 fr_status fr_debug_stage(fr_ctx *ctx, const double *u, int32_t stage, double *out,
@@ -216,9 +217,12 @@ fr_status fr_debug_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, const d
  * an M x (K1 + K2) operator on N columns (batch copies of panel 1) with tile
  * plan (mbw, nc, wm) (mbw = 0: default plan); operands are internal.
  * fr_get_gemm_plan: the tile plan a context uses for right-hand-side step
- * 1, 3, 5 or 8 of `block` (mbw = 0: the sparse-row kernel, nc rows per
- * workgroup; for step 3, wm = 1 then means that the gradient transform of
- * step 4 is fused into its epilogue and step 4 launches nothing). */
+ * 1, 3, 5 or 8 of `block`.  mbw = 0: the sparse-row kernel with nc
+ * operator rows per workgroup and wm a set of flags: bit 0 (step 3 only)
+ * the gradient transform of step 4 fused into its epilogue, so that step 4
+ * launches nothing; bit 1 every field of an element computed by one thread;
+ * bit 2 the LDS-staged kernel (64 columns and all rows per workgroup, B
+ * streamed through LDS; nc is then unused and reported as 64). */
 fr_status fr_measure_ceiling(int32_t kind, double *value, void *hip_stream);
 fr_status fr_bench_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, int64_t N,
                         int32_t mbw, int32_t nc, int32_t wm, int32_t batch, int32_t nrep,
@@ -228,8 +232,10 @@ fr_status fr_get_gemm_plan(const fr_ctx *ctx, int32_t block, int32_t step, int32
 /* fr_debug_set_plan forces the plan of right-hand-side step 1, 3, 5 or 8 of
  * `block` (test support: drives every kernel variant through the full
  * chain): mbw > 0 a matrix-core plan (mbw, nc, wm) as for fr_debug_gemm;
- * mbw = 0 the sparse-row kernel with nc rows per workgroup, wm = 1 (step 3
- * only) with the gradient transform fused.  FR_EINVAL for an invalid plan
+ * mbw = 0 the sparse-row kernel with nc rows per workgroup and the flags
+ * wm of fr_get_gemm_plan (fusion with bit 1 needs an operator of at most 16
+ * non-zeros per row; bit 2 excludes bit 1 and needs at most 160 rows, or
+ * 64 points when fused).  FR_EINVAL for an invalid plan
  * or an operator without a sparse form.  Drops the captured RK4 graph.
  * Synchronous on hip_stream. */
 fr_status fr_debug_set_plan(fr_ctx *ctx, int32_t block, int32_t step, int32_t mbw, int32_t nc,

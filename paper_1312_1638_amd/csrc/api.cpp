@@ -25,7 +25,8 @@ struct GemmOp {
   int M = 0, K1 = 0, K2 = 0, KS1 = 0, KS2 = 0, MBW = 1, NC = 1, WM = 1;
   void *d_A = nullptr;
   std::vector<double> A;  // unpacked operator (kept for re-packing by the tuner)
-  fr::SparseOp sp{nullptr, nullptr, 0, 0};  // ELL copy when the operator is sparse
+  fr::SparseOp sp{nullptr, nullptr, 0, 0, 1};  // ELL copy when the operator is sparse
+  fr::StagedOp st{nullptr, nullptr, 0, 0, 0};  // chunked ELL copy for the LDS-staged kernel
   double density = 1.0;
 };
 
@@ -33,6 +34,44 @@ struct GemmOp {
 // rounding residue of structural zeros (the Vandermonde construction does
 // not produce exact zeros); the sparse-row kernel skips them.
 const double kSparseDrop = 1e-13;
+
+// Sparse-row plans: MBW = 0, NC = operator rows per workgroup, WM = flags
+// (bit 0: the gradient transform fused into step 3, bit 1: every field of
+// an element in one thread, bit 2: the LDS-staged kernel, which takes all
+// rows of 64 columns per workgroup and ignores NC).
+const int kPlanFusedGradT = 1, kPlanFields = 2, kPlanStaged = 4;
+
+void apply_sparse_plan(GemmOp &op, const fr::GemmPlan &p, int nvars) {
+  op.sp.rpg = p.NC;
+  op.sp.fields = (p.WM & kPlanFields) ? nvars : 1;
+}
+
+// Whether the LDS-staged kernel has an instantiation for this operator
+// (rows per wavefront, and points per wavefront when fused with the gradient
+// transform of a D-dimensional block).
+bool staged_ok(const GemmOp &op, bool fused, int D) {
+  if (!op.st.colidx) return false;
+  if (fused) return op.M % D == 0 && (op.M / D + 3) / 4 <= FR_LDS_GRADT_ROWS_MAX;
+  return (op.M + 3) / 4 <= FR_LDS_ROWS_MAX;
+}
+
+// Sparse-row candidates of one operator product (step 3 adds the fused
+// gradient-transform plans).
+void sparse_candidates(const GemmOp &op, int step, int D, std::vector<fr::GemmPlan> &cands) {
+  if (!op.sp.colidx) return;
+  if (staged_ok(op, false, D)) cands.push_back(fr::GemmPlan{0, 64, kPlanStaged});
+  if (step == 3 && staged_ok(op, true, D))
+    cands.push_back(fr::GemmPlan{0, 64, kPlanStaged | kPlanFusedGradT});
+  // few rows per workgroup keep many workgroups on one column tile at once
+  // (its B rows shared in L2); more rows amortise the operator loads
+  for (int f : {0, kPlanFields})
+    for (int rpg : {1, 2, 4, 8, 16, 32, 64}) cands.push_back(fr::GemmPlan{0, rpg, f});
+  if (step == 3)
+    for (int f : {0, kPlanFields}) {
+      if (f && op.sp.width > FR_SPOP_GRADT_FIELDS_WMAX) continue;
+      for (int rpg : {1, 2, 4, 8, 16}) cands.push_back(fr::GemmPlan{0, rpg, kPlanFusedGradT | f});
+    }
+}
 
 struct BlockRT {
   int ref = 0;
@@ -198,13 +237,44 @@ void make_op(fr_ctx *c, GemmOp &op, const std::vector<double> &A, int M, int K1,
       op.sp.vals = dev_upload(c, va.data(), va.size(), s);
       op.sp.width = W;
       op.sp.rpg = 16;
+      op.sp.fields = 1;
+      // chunked copy for the LDS-staged kernel: kc rows of B (32 KB of LDS)
+      // per chunk, columns within the chunk
+      const int kc = c->prec == FR_FP64 ? 64 : 128;
+      const int nchunk = (K + kc - 1) / kc;
+      int wc = 1;
+      for (int ch = 0; ch < nchunk; ++ch)
+        for (int r = 0; r < M; ++r) {
+          int cnt = 0;
+          for (int k : cols[r]) cnt += k / kc == ch;
+          wc = std::max(wc, cnt);
+        }
+      const int WC = fr::spop_lds_width(wc);
+      if (WC > 0) {
+        std::vector<int32_t> sci((size_t)nchunk * M * WC, 0);
+        std::vector<double> sva((size_t)nchunk * M * WC, 0.0);
+        for (int r = 0; r < M; ++r) {
+          std::vector<int> fill(nchunk, 0);
+          for (int k : cols[r]) {
+            const int ch = k / kc;
+            const size_t at = ((size_t)ch * M + r) * WC + fill[ch]++;
+            sci[at] = k - ch * kc;
+            sva[at] = A[(size_t)r * K + k];
+          }
+        }
+        op.st.colidx = dev_upload(c, sci.data(), sci.size(), s);
+        op.st.vals = dev_upload(c, sva.data(), sva.size(), s);
+        op.st.width = WC;
+        op.st.kc = kc;
+        op.st.nchunk = nchunk;
+      }
     }
   }
   fr::GemmPlan p = force ? *force : fr::gemm_plan(M, N, c->prec);
   if (p.MBW == 0 && !op.sp.colidx) p = fr::gemm_plan(M, N, c->prec);
   op.MBW = p.MBW; op.NC = p.NC; op.WM = p.WM;
   if (p.MBW == 0) {
-    op.sp.rpg = p.NC;
+    apply_sparse_plan(op, p, c->NV);
     op.d_A = nullptr;
   } else {
     op.d_A = pack_upload(c, op, p, s, true);
@@ -214,12 +284,13 @@ void make_op(fr_ctx *c, GemmOp &op, const std::vector<double> &A, int M, int K1,
 // Step 3 with the gradient transform (step 4) fused into its epilogue: a
 // sparse-row plan of the [M6|M4'] operator with WM = 1.
 bool gradt_fused(const fr_ctx *c, const BlockRT &b) {
-  return c->ns && !c->no_fuse && b.s3.MBW == 0 && b.s3.WM == 1;
+  return c->ns && !c->no_fuse && b.s3.MBW == 0 && (b.s3.WM & kPlanFusedGradT);
 }
 
 // Launch an operator product with whichever kernel its plan names.
 hipError_t launch_op(const GemmOp &op, int gprec, int epi, const fr::GemmArgs &g, int batch,
                      hipStream_t s) {
+  if (op.MBW == 0 && (op.WM & kPlanStaged)) return fr::launch_spop_lds(gprec, epi, g, op.st, batch, s);
   if (op.MBW == 0) return fr::launch_spop(gprec, epi, g, op.sp, batch, s);
   return fr::launch_gemm(gprec, epi, g, batch, s);
 }
@@ -304,12 +375,14 @@ void run_step(fr_ctx *c, int st, const double *u, double *dudt, int epi, const f
     const int64_t N = NV * b.ld;
     if (st == 1) {
       fr::GemmArgs g = gemm_args(b.m0);
+      g.ld = b.ld;
       g.B1 = u + b.uoff; g.ldb1 = N; g.b1_f32 = 0;
       g.C = elem(c->cur.uf, b.ufoff, ts); g.ldc = N; g.c_f32 = f32;
       g.N = N;
       hip_check(launch_op(b.m0, gprec, fr::EPI_STORE, g, 1, s), "gemm M0");
     } else if (st == 3) {
       fr::GemmArgs g = gemm_args(b.s3);
+      g.ld = b.ld;
       g.B1 = elem(c->cur.qf, b.qfoff, ts); g.ldb1 = N; g.b1_f32 = f32;
       g.B2 = u + b.uoff; g.ldb2 = N; g.b2_f32 = 0;
       g.C = elem(c->cur.ft, b.ftoff, ts); g.ldc = N; g.c_f32 = f32;
@@ -326,6 +399,7 @@ void run_step(fr_ctx *c, int st, const double *u, double *dudt, int epi, const f
         hip_check(fr::launch_gradcoru(point_args(c, b, u), s), "gradcoru");
     } else if (st == 5) {
       fr::GemmArgs g = gemm_args(b.m5);
+      g.ld = b.ld;
       g.B1 = elem(c->cur.ft, b.ftoff, ts); g.ldb1 = N; g.b1_f32 = f32; g.b2_f32 = f32;
       g.C = elem(c->cur.qf, b.qfoff, ts); g.ldc = N; g.c_f32 = f32;
       g.N = N;
@@ -387,17 +461,14 @@ void tune_op(fr_ctx *c, GemmOp &op, int step, BlockRT &b, hipStream_t s) {
     hip_check(hipEventCreate(&e1), "event");
     float best_ms = 1e30f;
     std::vector<fr::GemmPlan> cands = fr::gemm_candidates(op.M, N, c->prec);
-    if (op.sp.colidx)
-      for (int rpg : {4, 8, 16, 32, 64}) cands.push_back(fr::GemmPlan{0, rpg, 0});
-    // step 3: also the plans with the gradient transform fused (WM = 1); every
+    // step 3: also the plans with the gradient transform fused; every
     // candidate is timed together with step 4 (a no-op when fused)
-    if (step == 3 && op.sp.colidx)
-      for (int rpg : {1, 2, 4, 8, 16}) cands.push_back(fr::GemmPlan{0, rpg, 1});
+    sparse_candidates(op, step, c->D, cands);
     for (const fr::GemmPlan &p : cands) {
       void *d = p.MBW ? pack_upload(c, op, p, s, false) : nullptr;
       GemmOp trial = op;
       trial.d_A = d; trial.MBW = p.MBW; trial.NC = p.NC; trial.WM = p.WM;
-      if (p.MBW == 0) trial.sp.rpg = p.NC;
+      if (p.MBW == 0) apply_sparse_plan(trial, p, c->NV);
       std::swap(*(step == 1 ? &b.m0 : step == 3 ? &b.s3 : step == 5 ? &b.m5 : &b.s8), trial);
       float ms = 0;
       try {
@@ -429,7 +500,7 @@ void tune_op(fr_ctx *c, GemmOp &op, int step, BlockRT &b, hipStream_t s) {
   if (best.MBW != op.MBW || best.NC != op.NC || best.WM != op.WM) {
     op.d_A = best.MBW ? pack_upload(c, op, best, s, true) : nullptr;
     op.MBW = best.MBW; op.NC = best.NC; op.WM = best.WM;
-    if (best.MBW == 0) op.sp.rpg = best.NC;
+    if (best.MBW == 0) apply_sparse_plan(op, best, c->NV);
   }
 }
 
@@ -504,6 +575,7 @@ void adj_gemm(fr_ctx *c, const GemmOp &op, const double *B1, const double *B2, d
   fr::GemmArgs g = gemm_args(op);
   g.B1 = B1; g.ldb1 = N; g.B2 = B2; g.ldb2 = N;
   g.C = C; g.ldc = N; g.N = N; g.sB1 = sB1; g.sC = sC;
+  g.ld = N / c->NV;  // columns are (field, element) with N = N_V ld
   hip_check(launch_op(op, fr::PREC_F64, epi, g, batch, s), "adjoint gemm");
 }
 
@@ -521,13 +593,12 @@ void tune_adj(fr_ctx *c, GemmOp &op, const double *B1, const double *B2, double 
     hip_check(hipEventCreate(&e1), "event");
     float best_ms = 1e30f;
     std::vector<fr::GemmPlan> cands = fr::gemm_candidates(op.M, batch * N, c->prec);
-    if (op.sp.colidx)
-      for (int rpg : {4, 8, 16, 32, 64}) cands.push_back(fr::GemmPlan{0, rpg, 0});
+    sparse_candidates(op, 0, c->D, cands);
     for (const fr::GemmPlan &p : cands) {
       GemmOp trial = op;
       trial.d_A = p.MBW ? pack_upload(c, op, p, s, false) : nullptr;
       trial.MBW = p.MBW; trial.NC = p.NC; trial.WM = p.WM;
-      if (p.MBW == 0) trial.sp.rpg = p.NC;
+      if (p.MBW == 0) apply_sparse_plan(trial, p, c->NV);
       float ms = 0;
       try {
         for (int w = 0; w < 2; ++w) adj_gemm(c, trial, B1, B2, C, N, epi, batch, sB1, sC, s);
@@ -550,7 +621,7 @@ void tune_adj(fr_ctx *c, GemmOp &op, const double *B1, const double *B2, double 
   if (best.MBW != op.MBW || best.NC != op.NC || best.WM != op.WM) {
     op.d_A = best.MBW ? pack_upload(c, op, best, s, true) : nullptr;
     op.MBW = best.MBW; op.NC = best.NC; op.WM = best.WM;
-    if (best.MBW == 0) op.sp.rpg = best.NC;
+    if (best.MBW == 0) apply_sparse_plan(op, best, c->NV);
   }
 }
 
@@ -1227,7 +1298,7 @@ fr_status fr_debug_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, const d
     fr::GemmPlan p{mbw, nc, wm};
     if (mbw > 0 && (!fr::gemm_plan_valid(mbw, nc) || wm < 1 || mbw * wm * 16 < M))
       throw Fail{FR_EINVAL, "bad plan"};
-    if (mbw == 0 && nc < 0) throw Fail{FR_EINVAL, "bad plan"};
+    if (mbw == 0 && (nc < 0 || wm != 0)) throw Fail{FR_EINVAL, "bad plan"};
     make_op(&tmp, op, Av, M, K1, K2, N, s, (mbw > 0 || nc > 0) ? &p : nullptr);
     if (mbw == 0 && nc > 0 && op.MBW != 0) throw Fail{FR_EINVAL, "operator is not sparse"};
     fr::GemmArgs g = gemm_args(op);
@@ -1332,10 +1403,13 @@ fr_status fr_debug_set_plan(fr_ctx *c, int32_t block, int32_t step, int32_t mbw,
       op->d_A = pack_upload(c, *op, p, s, true);
     } else {
       if (!op->sp.colidx) throw Fail{FR_EINVAL, "operator has no sparse-row form"};
-      if (nc < 1 || wm < 0 || wm > 1 || (wm == 1 && step != 3))
+      const bool staged = wm & kPlanStaged, fused = wm & kPlanFusedGradT;
+      if (nc < 1 || wm < 0 || wm > 7 || (fused && step != 3) ||
+          (staged && ((wm & kPlanFields) || !staged_ok(*op, fused, c->D))) ||
+          (wm == (kPlanFusedGradT | kPlanFields) && op->sp.width > FR_SPOP_GRADT_FIELDS_WMAX))
         throw Fail{FR_EINVAL, "bad sparse-row plan"};
       op->d_A = nullptr;
-      op->sp.rpg = nc;
+      apply_sparse_plan(*op, p, c->NV);
     }
     op->MBW = mbw; op->NC = nc; op->WM = wm;
     hip_check(hipStreamSynchronize(s), "sync");

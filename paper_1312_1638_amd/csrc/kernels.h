@@ -75,10 +75,40 @@ struct SparseOp {
   const double *vals;      // [M][width]
   int width;               // one of FR_SPOP_WIDTHS
   int rpg;                 // operator rows per workgroup row
+  int fields;              // fields per thread: 1, or the field count (N = fields * ld)
 };
 #define FR_SPOP_WIDTHS(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32)
+// the fused gradient transform with every field in one thread holds D x N_V
+// accumulators besides the row's loads: instantiated up to this width only
+#define FR_SPOP_GRADT_FIELDS_WMAX 16
 // smallest instantiated width >= nnz_max (0 if none)
 int spop_width(int nnz_max);
+
+// LDS-staged form of a sparse operator (spop_lds.h).  The K = K1 + K2 rows
+// of B are taken in chunks of kc rows; chunk c holds, for every operator row
+// r, colidx[(c M + r) width + e] (a row of B within the chunk) and
+// vals[...], e < width; padding entries have value 0.
+struct StagedOp {
+  const int32_t *colidx;   // [nchunk][M][width]
+  const double *vals;      // [nchunk][M][width]
+  int width;               // one of FR_LDS_WIDTHS
+  int kc;                  // B rows per chunk (kc x 64 values of LDS)
+  int nchunk;
+};
+#define FR_LDS_WIDTHS(X) X(4) X(8) X(12)
+// output rows per wavefront (4 wavefronts split the M rows of a tile)
+#define FR_LDS_ROWS(X) X(4) X(8) X(16) X(24) X(32) X(40)
+#define FR_LDS_ROWS_MAX 40
+// the fused gradient transform keeps D accumulators per point
+#define FR_LDS_GRADT_ROWS_MAX 16
+hipError_t launch_spop_lds(int prec, int epi, const GemmArgs &g, const StagedOp &op, int batch,
+                           hipStream_t s);
+hipError_t launch_spop_lds_f64(int epi, const GemmArgs &g, const StagedOp &op, int batch,
+                               hipStream_t s);
+hipError_t launch_spop_lds_f32(int epi, const GemmArgs &g, const StagedOp &op, int batch,
+                               hipStream_t s);
+// smallest instantiated chunk width >= nnz_max (0 if none)
+int spop_lds_width(int nnz_max);
 hipError_t launch_spop(int prec, int epi, const GemmArgs &g, const SparseOp &sp, int batch,
                        hipStream_t s);
 

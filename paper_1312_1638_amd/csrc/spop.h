@@ -1,0 +1,265 @@
+// Sparse-row application of an operator matrix: C = A [B1; B2] where A has
+// few non-zeros per row (kernel template; instantiated in spop.hip for one
+// field per thread and in spop_fields.hip for all fields per thread).
+//
+// With Gauss-Legendre points on quads and hexes every Appendix A operator
+// couples only points on one coordinate line (interpolation to a face,
+// differentiation along a line, the DG lifting along the face normal), so a
+// row holds O(p) non-zeros out of up to a few hundred.  Applying such an
+// operator as a dense product would make an HBM-bound step compute-bound.
+//
+// Threads of a wavefront take consecutive elements (coalesced).  With F = 1
+// a thread owns one state column (field, element); with F = N_V it owns an
+// element and produces every field of it, so the operator entries (scalar
+// loads), the per-point metric terms of the epilogues and the step size are
+// fetched once for all fields, and each row issues F x W independent loads.
+// Each workgroup row takes `rpg` operator rows.  The operator is stored
+// padded to a fixed width W per row (ELL: padding entries have value 0 and
+// repeat a real column), W is a template parameter, so all loads of a row
+// are issued back to back; column indices and values are wave-uniform.
+// The grid is one-dimensional and XCD-aware: workgroups are dealt
+// round-robin to the 8 XCDs, and the linear id is remapped so that each XCD
+// runs all row groups of one column tile back to back; re-reads of that
+// tile's B rows then hit the XCD's L2 while they are still there.
+#pragma once
+
+#include "kernels.h"
+
+namespace fr {
+
+template <typename T, int EPI, int W, typename TB1, typename TB2, typename TC, int DG, int F>
+__global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
+                                                   const int32_t *__restrict__ colidx,
+                                                   const double *__restrict__ vals, int rpg,
+                                                   int ngroups) {
+  // linear id L -> XCD L % 8; the j-th workgroup of an XCD takes row group
+  // j % ngroups of column tile 8 (j / ngroups) + L % 8 (tiles padded to a
+  // multiple of 8 by the launch)
+  const int64_t L = blockIdx.x, j = L >> 3;
+  const int64_t tile = (j / ngroups) * 8 + (L & 7);
+  const int rgrp = (int)(j % ngroups);
+  // F == 1: t is the state column alpha * ld + n; F > 1: t is the element n
+  const int64_t t = tile * 256 + threadIdx.x;
+  if (t >= (F == 1 ? g.N : g.ld)) return;
+  const int r0 = rgrp * rpg;
+  const int rmax = EPI == EPI_GRADT ? g.Nu : g.M;
+  const int r1 = r0 + rpg < rmax ? r0 + rpg : rmax;
+  const TB1 *__restrict__ B1b = (const TB1 *)g.B1 + (int64_t)blockIdx.y * g.sB1;
+  const TB1 *__restrict__ B1 = B1b + t;
+  const TB2 *__restrict__ B2 = (const TB2 *)g.B2 + t;
+  int64_t n = 0;
+  if (EPI == EPI_NEGDIV || EPI == EPI_RK || EPI == EPI_GRADT) n = F == 1 ? t % g.ld : t;
+  const bool live = n < g.nelem;
+  double dtv = 0;
+  if (EPI == EPI_RK && live) dtv = g.dt[g.prob ? g.prob[n] : 0];
+  const int K1 = g.K1;
+  const int64_t ldb1 = g.ldb1, ldb2 = g.ldb2, fs = F == 1 ? 0 : g.ld;
+  // B2 addressed from B1 by an element offset (same element type), so that
+  // picking the panel of an entry is a uniform select, not a branch
+  const int64_t d2 = ((intptr_t)g.B2 - (intptr_t)B1b) / (int64_t)sizeof(TB1);
+
+  // acc[a] = row `row` of A times field a's column
+  auto row_product = [&](int row, T(&acc)[F]) {
+    const int32_t *__restrict__ ci = colidx + (int64_t)row * W;
+    const double *__restrict__ cv = vals + (int64_t)row * W;
+    int32_t kc[W];
+#pragma unroll
+    for (int e = 0; e < W; ++e) kc[e] = ci[e];
+    T b[F][W];
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+      const int k = kc[e];
+      if constexpr (sizeof(TB1) == sizeof(TB2)) {
+        const int64_t off = k < K1 ? (int64_t)k * ldb1 : d2 + (int64_t)(k - K1) * ldb2;
+#pragma unroll
+        for (int a = 0; a < F; ++a) b[a][e] = (T)B1[off + a * fs];
+      } else {
+#pragma unroll
+        for (int a = 0; a < F; ++a)
+          b[a][e] = k < K1 ? (T)B1[(int64_t)k * ldb1 + a * fs]
+                           : (T)B2[(int64_t)(k - K1) * ldb2 + a * fs];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < F; ++a) {
+      T s = 0;
+#pragma unroll
+      for (int e = 0; e < W; ++e) s += (T)cv[e] * b[a][e];
+      acc[a] = s;
+    }
+  };
+
+  if constexpr (EPI == EPI_GRADT) {
+    // rows d Nu + rho, d < DG, of the points rho in [r0, r1) (r1 <= Nu)
+    const int64_t plane = (int64_t)g.Nu * g.ld;
+    TC *C = (TC *)g.C;
+    for (int rho = r0; rho < r1; ++rho) {
+      T qt[DG][F];
+#pragma unroll
+      for (int d = 0; d < DG; ++d) row_product(d * g.Nu + rho, qt[d]);
+      const int64_t pt = (int64_t)rho * g.ld + n;
+      if (live) {
+        const double rj = g.rcpdjac[pt];
+        double S[DG][DG];
+#pragma unroll
+        for (int i = 0; i < DG; ++i)
+#pragma unroll
+          for (int jj = 0; jj < DG; ++jj) S[i][jj] = g.smat[(i * DG + jj) * plane + pt];
+#pragma unroll
+        for (int a = 0; a < F; ++a)
+#pragma unroll
+          for (int jj = 0; jj < DG; ++jj) {
+            double sj = 0;
+#pragma unroll
+            for (int i = 0; i < DG; ++i) sj += S[i][jj] * (double)qt[i][a];
+            C[(int64_t)(jj * g.Nu + rho) * g.ldc + t + a * fs] = (TC)(rj * sj);
+          }
+      } else {
+#pragma unroll
+        for (int a = 0; a < F; ++a)
+#pragma unroll
+          for (int jj = 0; jj < DG; ++jj)
+            C[(int64_t)(jj * g.Nu + rho) * g.ldc + t + a * fs] = (TC)qt[jj][a];
+      }
+    }
+    return;
+  }
+#pragma unroll 2
+  for (int row = r0; row < r1; ++row) {
+    T acc[F];
+    row_product(row, acc);
+    double rj = 0;
+    if (EPI == EPI_NEGDIV || EPI == EPI_RK) rj = live ? g.rcpdjac[(int64_t)row * g.ld + n] : 0.0;
+#pragma unroll
+    for (int a = 0; a < F; ++a) {
+      const int64_t idx = (int64_t)row * g.ldc + t + a * fs;
+      if (EPI == EPI_STORE) {
+        ((TC *)g.C)[(int64_t)blockIdx.y * g.sC + idx] = (TC)acc[a];
+      } else if (EPI == EPI_ADD) {
+        TC *cp = (TC *)g.C + (int64_t)blockIdx.y * g.sC + idx;
+        *cp = (TC)((double)*cp + (double)acc[a]);
+      } else {
+        // padding columns: exactly 0 whatever they hold (even NaN)
+        const double kk = live ? -rj * (double)acc[a] : 0.0;
+        if (EPI == EPI_NEGDIV) {
+          g.out[idx] = kk;
+        } else {
+          const double bdt = g.rk.b * dtv * kk;
+          if (g.rk.last) {
+            g.out[idx] = g.acc[idx] + bdt;
+          } else {
+            const double u0 = g.out[idx];
+            g.acc[idx] = (g.rk.first ? u0 : g.acc[idx]) + bdt;
+            g.stage[idx] = u0 + g.rk.a_next * dtv * kk;
+          }
+        }
+      }
+    }
+  }
+}
+
+// Column tiles of 256 threads, padded to a multiple of the 8 XCDs.
+template <int F>
+inline int64_t spop_tiles(const GemmArgs &g) {
+  const int64_t threads = F == 1 ? g.N : g.ld;
+  return ((threads + 255) / 256 + 7) / 8 * 8;
+}
+
+template <typename T, int EPI, int W, int F>
+void spop_launch_w(const GemmArgs &g, const SparseOp &sp, int batch, hipStream_t s) {
+  const int ngroups = (g.M + sp.rpg - 1) / sp.rpg;
+  dim3 grid((unsigned)(spop_tiles<F>(g) * ngroups), batch);
+  if constexpr (sizeof(T) == 8) {
+    spop_kernel<T, EPI, W, double, double, double, 0, F><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
+  } else if constexpr (EPI == EPI_NEGDIV || EPI == EPI_RK) {
+    spop_kernel<T, EPI, W, float, float, double, 0, F><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
+  } else {
+    if (!g.b1_f32)
+      spop_kernel<T, EPI, W, double, double, float, 0, F><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
+    else if (!g.b2_f32)
+      spop_kernel<T, EPI, W, float, double, float, 0, F><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
+    else
+      spop_kernel<T, EPI, W, float, float, float, 0, F><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
+  }
+}
+
+template <typename T, int W, int DG, int F>
+void spop_launch_gradt(const GemmArgs &g, const SparseOp &sp, hipStream_t s) {
+  const int ngroups = (g.Nu + sp.rpg - 1) / sp.rpg;
+  dim3 grid((unsigned)(spop_tiles<F>(g) * ngroups), 1);
+  if constexpr (sizeof(T) == 8)
+    spop_kernel<T, EPI_GRADT, W, double, double, double, DG, F><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
+  else  // FP32 contexts: C^f in FP32 scratch (panel 1), the FP64 state (panel 2)
+    spop_kernel<T, EPI_GRADT, W, float, double, float, DG, F><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
+}
+
+template <typename T, int F>
+hipError_t spop_gradt_t(const GemmArgs &g, const SparseOp &sp, hipStream_t s) {
+  if ((g.D != 2 && g.D != 3) || g.Nu * g.D != g.M || !g.smat) return hipErrorInvalidValue;
+  if (sizeof(T) == 4 && (!g.b1_f32 || g.b2_f32 || !g.c_f32)) return hipErrorInvalidValue;
+  // all fields per thread: F is the field count D + 2
+  constexpr int DG = F == 4 ? 2 : 3;
+  if (F > 1 && g.D != DG) return hipErrorInvalidValue;
+  switch (sp.width) {
+#define FR_W(W_)                                                          \
+  case W_:                                                                \
+    if constexpr (F > 1 && W_ > FR_SPOP_GRADT_FIELDS_WMAX)                \
+      return hipErrorInvalidValue;                                        \
+    else if constexpr (F > 1) spop_launch_gradt<T, W_, DG, F>(g, sp, s);  \
+    else if (g.D == 3) spop_launch_gradt<T, W_, 3, F>(g, sp, s);          \
+    else spop_launch_gradt<T, W_, 2, F>(g, sp, s);                        \
+    break;
+    FR_SPOP_WIDTHS(FR_W)
+#undef FR_W
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int EPI, int F>
+hipError_t spop_launch_t(const GemmArgs &g, const SparseOp &sp, int batch, hipStream_t s) {
+  switch (sp.width) {
+#define FR_W(W_) \
+  case W_: spop_launch_w<T, EPI, W_, F>(g, sp, batch, s); break;
+    FR_SPOP_WIDTHS(FR_W)
+#undef FR_W
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Launch with F fields per thread (F = 1, or the field count with
+// g.N == F * g.ld).
+template <int F>
+hipError_t launch_spop_f(int prec, int epi, const GemmArgs &g, const SparseOp &sp, int batch,
+                         hipStream_t s) {
+  if (F > 1 && g.N != (int64_t)F * g.ld) return hipErrorInvalidValue;
+  if (epi == EPI_GRADT) {
+    if (batch != 1) return hipErrorInvalidValue;
+    if (prec == PREC_F64) return spop_gradt_t<double, F>(g, sp, s);
+    if (prec == PREC_F32) return spop_gradt_t<float, F>(g, sp, s);
+    return hipErrorInvalidValue;
+  }
+  if (prec == PREC_F64) {
+    switch (epi) {
+      case EPI_STORE: return spop_launch_t<double, EPI_STORE, F>(g, sp, batch, s);
+      case EPI_NEGDIV: return spop_launch_t<double, EPI_NEGDIV, F>(g, sp, batch, s);
+      case EPI_RK: return spop_launch_t<double, EPI_RK, F>(g, sp, batch, s);
+      case EPI_ADD: return spop_launch_t<double, EPI_ADD, F>(g, sp, batch, s);
+    }
+  } else if (prec == PREC_F32) {
+    switch (epi) {
+      case EPI_STORE: return spop_launch_t<float, EPI_STORE, F>(g, sp, batch, s);
+      case EPI_NEGDIV: return spop_launch_t<float, EPI_NEGDIV, F>(g, sp, batch, s);
+      case EPI_RK: return spop_launch_t<float, EPI_RK, F>(g, sp, batch, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_spop_fields4(int prec, int epi, const GemmArgs &g, const SparseOp &sp,
+                               int batch, hipStream_t s);
+hipError_t launch_spop_fields5(int prec, int epi, const GemmArgs &g, const SparseOp &sp,
+                               int batch, hipStream_t s);
+
+}  // namespace fr

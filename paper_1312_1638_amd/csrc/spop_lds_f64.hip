@@ -1,0 +1,11 @@
+// LDS-staged sparse operator kernel, FP64 contexts (kernel in spop_lds.h).
+#include "spop_lds.h"
+
+namespace fr {
+
+hipError_t launch_spop_lds_f64(int epi, const GemmArgs &g, const StagedOp &op, int batch,
+                               hipStream_t s) {
+  return spop_lds_prec<double>(epi, g, op, batch, s);
+}
+
+}  // namespace fr

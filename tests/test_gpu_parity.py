@@ -69,9 +69,11 @@ def test_rhs_small_bf16x3(name):
 
 def _force_plans(s, w, variant):
     """Force one kernel family on every operator product of every block:
-    'mfma' (matrix cores), 'sparse' (sparse-row, 4 rows per workgroup) or
-    'fused' (sparse-row, the gradient transform fused into step 3).  Dense
-    triangle operators have no sparse-row form and keep their plan."""
+    'mfma' (matrix cores), 'sparse' (sparse-row, 4 rows per workgroup),
+    'fused' (sparse-row, the gradient transform fused into step 3), the
+    same two with every field of an element in one thread ('fields',
+    'fused_fields'), and the LDS-staged kernel ('staged', 'staged_fused').
+    Dense triangle operators have no sparse-row form and keep their plan."""
     import paper_1312_1638_amd as P
     steps = [1, 3, 5, 8] if w.system == "ns" else [1, 8]
     forced = 0
@@ -84,12 +86,22 @@ def _force_plans(s, w, variant):
                 plan = (1, 1, -(-rows[st] // 16))
             elif variant == "sparse":
                 plan = (0, 4, 0)
-            else:
+            elif variant == "fields":
+                plan = (0, 5, 2)
+            elif variant == "fused":
                 plan = (0, 3, 1) if st == 3 else (0, 7, 0)
+            elif variant == "staged":
+                plan = (0, 64, 4)
+            elif variant == "staged_fused":
+                plan = (0, 64, 5) if st == 3 else (0, 64, 4)
+            else:
+                plan = (0, 2, 3) if st == 3 else (0, 3, 2)
             try:
                 s.set_plan(bi, st, plan)
             except P.FRError:
-                assert b.etype == "tri" and variant != "mfma"
+                # dense triangle operators have no sparse form; the staged
+                # kernel holds at most 160 rows (64 points when fused)
+                assert variant != "mfma" and (b.etype == "tri" or variant.startswith("staged"))
                 continue
             assert s.gemm_plan(bi, st) == plan
             forced += 1
@@ -98,7 +110,8 @@ def _force_plans(s, w, variant):
 
 @pytest.mark.parametrize("name", ["tgv3_p4", "mixed5_p2_ns", "curved3_p2_ns", "vortex7_p3",
                                   "mixed6_p3_euler"])
-@pytest.mark.parametrize("variant", ["mfma", "sparse", "fused"])
+@pytest.mark.parametrize("variant", ["mfma", "sparse", "fused", "fields", "fused_fields",
+                                     "staged", "staged_fused"])
 def test_every_kernel_variant(name, variant):
     """du/dt and u after 3 RK4 steps (captured graph) with every operator
     product forced onto one kernel family."""
@@ -114,13 +127,14 @@ def test_every_kernel_variant(name, variant):
     assert err < 1e-12 and eu < 1e-12
 
 
-def test_fused_gradient_transform_fp32():
+@pytest.mark.parametrize("variant", ["fused", "fused_fields", "staged_fused"])
+def test_fused_gradient_transform_fp32(variant):
     w = C.SMALL["tgv5_p3"]()
     d, s, u = _both(w, "fp32")
-    _force_plans(s, w, "fused")
+    _force_plans(s, w, variant)
     tol, ext, floor = C.floor_tolerance(d, u, 1e-5, C.FP32_OVER_FP64)
     err = C.rel_l2(s.unpack(s.rhs(s.pack(u))), ext)
-    print(f"tgv5_p3 fp32 fused: rel L2 {err:.3e} (tol {tol:.2e})")
+    print(f"tgv5_p3 fp32 {variant}: rel L2 {err:.3e} (tol {tol:.2e})")
     assert err < tol
 
 
