@@ -230,8 +230,10 @@ fr_status fr_bench_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, int64_t
 fr_status fr_get_gemm_plan(const fr_ctx *ctx, int32_t block, int32_t step, int32_t *mbw,
                            int32_t *nc, int32_t *wm);
 /* fr_debug_set_plan forces the plan of right-hand-side step 1, 3, 5 or 8 of
- * `block` (test support: drives every kernel variant through the full
- * chain): mbw > 0 a matrix-core plan (mbw, nc, wm) as for fr_debug_gemm;
+ * `block`, or (step 13, FP64 contexts) of the adjoint's M0^T product, which
+ * with a sparse-row plan also applies the reverse gradient transform (test
+ * support: drives every kernel variant through the full chain): mbw > 0 a
+ * matrix-core plan (mbw, nc, wm) as for fr_debug_gemm;
  * mbw = 0 the sparse-row kernel with nc rows per workgroup and the flags
  * wm of fr_get_gemm_plan (fusion with bit 1 needs an operator of at most 16
  * non-zeros per row; bit 2 excludes bit 1 and needs at most 160 rows, or

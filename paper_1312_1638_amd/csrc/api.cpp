@@ -686,10 +686,20 @@ void rhs_adjoint_chain(fr_ctx *c, const double *u, const double *lam, double *ul
     hip_check(fr::launch_tflux_vjp(a, c->ns, s), "tflux_vjp");
     const int64_t N = (int64_t)NV * b.ld;
     if (c->ns) {
-      // Q b += blockdiag(M0)^T Q^f b
-      adj_gemm(c, b.t_m0, c->d_qfb + b.qfoff, nullptr, c->d_ftb + b.ftoff, N, fr::EPI_ADD, D,
-               (int64_t)b.Nf * N, (int64_t)b.Nu * N, s);
-      hip_check(fr::launch_gradcoru_t(a, s), "gradcoru_t");
+      // Q b += blockdiag(M0)^T Q^f b, then Q~ b = J^-1 Q b (the reverse of
+      // the gradient transform), in one sparse-row launch where possible
+      if (b.t_m0.MBW == 0 && !(b.t_m0.WM & kPlanStaged)) {
+        fr::GemmArgs g = gemm_args(b.t_m0);
+        g.B1 = c->d_qfb + b.qfoff; g.ldb1 = N; g.C = c->d_ftb + b.ftoff; g.ldc = N; g.N = N;
+        g.sB1 = (int64_t)b.Nf * N; g.sC = (int64_t)b.Nu * N;
+        g.ld = b.ld; g.nelem = b.nelem; g.rcpdjac = b.d_rcpdjac;
+        g.smat = b.d_smat; g.D = D; g.Nu = b.Nu;
+        hip_check(launch_op(b.t_m0, fr::PREC_F64, fr::EPI_ADDT, g, 1, s), "M0^T + J^-1");
+      } else {
+        adj_gemm(c, b.t_m0, c->d_qfb + b.qfoff, nullptr, c->d_ftb + b.ftoff, N, fr::EPI_ADD, D,
+                 (int64_t)b.Nf * N, (int64_t)b.Nu * N, s);
+        hip_check(fr::launch_gradcoru_t(a, s), "gradcoru_t");
+      }
       // C^f b = M6^T Q~b (into the first rows of the Q^f b region)
       adj_gemm(c, b.t_m6, c->d_ftb + b.ftoff, nullptr, c->d_qfb + b.qfoff, N, fr::EPI_STORE, 1,
                0, 0, s);
@@ -1392,9 +1402,23 @@ fr_status fr_debug_set_plan(fr_ctx *c, int32_t block, int32_t step, int32_t mbw,
                             int32_t wm, void *hip_stream) {
   if (!c || block < 0 || block >= (int)c->blocks.size()) return FR_EINVAL;
   BlockRT &b = c->blocks[block];
-  GemmOp *op = step == 1 ? &b.m0 : step == 3 ? &b.s3 : step == 5 ? &b.m5 : step == 8 ? &b.s8 : nullptr;
-  if (!op || (!c->ns && (step == 3 || step == 5))) return fail(c, FR_EINVAL, "no such step");
   hipStream_t s = (hipStream_t)hip_stream;
+  if (step == 13) {
+    // M0^T of the adjoint (set up and tuned first, so the plan sticks)
+    if (c->prec != FR_FP64) return fail(c, FR_EUNSUPPORTED, "the adjoint is FP64 only");
+    try {
+      ensure_adjoint(c, s);
+      if (!c->adj_tuned) {
+        c->adj_tuned = true;
+        tune_adjoint_ops(c, s);
+      }
+    } catch (const Fail &f) {
+      return fail(c, f.st, f.msg);
+    }
+  }
+  GemmOp *op = step == 1 ? &b.m0 : step == 3 ? &b.s3 : step == 5 ? &b.m5 : step == 8 ? &b.s8
+               : step == 13 ? &b.t_m0 : nullptr;
+  if (!op || (!c->ns && (step == 3 || step == 5))) return fail(c, FR_EINVAL, "no such step");
   try {
     fr::GemmPlan p{mbw, nc, wm};
     if (mbw > 0) {

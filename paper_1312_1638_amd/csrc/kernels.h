@@ -17,8 +17,12 @@ enum GemmEpi {
   EPI_NEGDIV = 1,  // out = -rcpdjac[row][n] * acc, 0 for padding  (FP64 out)
   EPI_RK = 2,      // RK4 stage update from k = -rcpdjac * acc      (FP64 regs)
   EPI_ADD = 3,     // C[row][col] += acc (FP64 only; adjoint accumulation)
-  EPI_GRADT = 4    // sparse-row kernel only: the D rows d Nu + rho of one point
+  EPI_GRADT = 4,   // sparse-row kernel only: the D rows d Nu + rho of one point
                    // are transformed by J^-T = S^T / det J before the store
+  EPI_ADDT = 5     // sparse-row kernel only (adjoint, FP64): row rho of the D
+                   // batch slices is added to C, then the D sums of one point
+                   // are transformed by J^-1 = S / det J (the reverse of the
+                   // gradient transform); padding columns are only added
 };
 
 enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };

@@ -42,13 +42,14 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
   const int64_t t = tile * 256 + threadIdx.x;
   if (t >= (F == 1 ? g.N : g.ld)) return;
   const int r0 = rgrp * rpg;
-  const int rmax = EPI == EPI_GRADT ? g.Nu : g.M;
+  const int rmax = EPI == EPI_GRADT ? g.Nu : g.M;  // EPI_ADDT: M = Nu
   const int r1 = r0 + rpg < rmax ? r0 + rpg : rmax;
   const TB1 *__restrict__ B1b = (const TB1 *)g.B1 + (int64_t)blockIdx.y * g.sB1;
   const TB1 *__restrict__ B1 = B1b + t;
   const TB2 *__restrict__ B2 = (const TB2 *)g.B2 + t;
   int64_t n = 0;
-  if (EPI == EPI_NEGDIV || EPI == EPI_RK || EPI == EPI_GRADT) n = F == 1 ? t % g.ld : t;
+  if (EPI == EPI_NEGDIV || EPI == EPI_RK || EPI == EPI_GRADT || EPI == EPI_ADDT)
+    n = F == 1 ? t % g.ld : t;
   const bool live = n < g.nelem;
   double dtv = 0;
   if (EPI == EPI_RK && live) dtv = g.dt[g.prob ? g.prob[n] : 0];
@@ -58,8 +59,9 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
   // picking the panel of an entry is a uniform select, not a branch
   const int64_t d2 = ((intptr_t)g.B2 - (intptr_t)B1b) / (int64_t)sizeof(TB1);
 
-  // acc[a] = row `row` of A times field a's column
-  auto row_product = [&](int row, T(&acc)[F]) {
+  // acc[a] = row `row` of A times field a's column (of panel 1 shifted by
+  // boff elements: a batch slice)
+  auto row_product = [&](int row, T(&acc)[F], int64_t boff = 0) {
     const int32_t *__restrict__ ci = colidx + (int64_t)row * W;
     const double *__restrict__ cv = vals + (int64_t)row * W;
     int32_t kc[W];
@@ -70,7 +72,7 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
     for (int e = 0; e < W; ++e) {
       const int k = kc[e];
       if constexpr (sizeof(TB1) == sizeof(TB2)) {
-        const int64_t off = k < K1 ? (int64_t)k * ldb1 : d2 + (int64_t)(k - K1) * ldb2;
+        const int64_t off = k < K1 ? (int64_t)k * ldb1 + boff : d2 + (int64_t)(k - K1) * ldb2;
 #pragma unroll
         for (int a = 0; a < F; ++a) b[a][e] = (T)B1[off + a * fs];
       } else {
@@ -89,6 +91,47 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
     }
   };
 
+  if constexpr (EPI == EPI_ADDT) {
+    // row rho of batch slices d < DG (panel 1 only), added to C, then
+    // qtb_i = (1/J) sum_j S_ij qb_j at the point
+    const int64_t plane = (int64_t)g.Nu * g.ld;
+    double *C = (double *)g.C;
+    for (int rho = r0; rho < r1; ++rho) {
+      T pr[DG][F];
+#pragma unroll
+      for (int d = 0; d < DG; ++d) row_product(rho, pr[d], d * g.sB1);
+      double qb[DG][F];
+#pragma unroll
+      for (int d = 0; d < DG; ++d)
+#pragma unroll
+        for (int a = 0; a < F; ++a)
+          qb[d][a] = C[d * g.sC + (int64_t)rho * g.ldc + t + a * fs] + (double)pr[d][a];
+      const int64_t pt = (int64_t)rho * g.ld + n;
+      if (live) {
+        const double rj = g.rcpdjac[pt];
+        double S[DG][DG];
+#pragma unroll
+        for (int i = 0; i < DG; ++i)
+#pragma unroll
+          for (int jj = 0; jj < DG; ++jj) S[i][jj] = g.smat[(i * DG + jj) * plane + pt];
+#pragma unroll
+        for (int a = 0; a < F; ++a)
+#pragma unroll
+          for (int i = 0; i < DG; ++i) {
+            double si = 0;
+#pragma unroll
+            for (int jj = 0; jj < DG; ++jj) si += S[i][jj] * qb[jj][a];
+            C[i * g.sC + (int64_t)rho * g.ldc + t + a * fs] = rj * si;
+          }
+      } else {
+#pragma unroll
+        for (int d = 0; d < DG; ++d)
+#pragma unroll
+          for (int a = 0; a < F; ++a) C[d * g.sC + (int64_t)rho * g.ldc + t + a * fs] = qb[d][a];
+      }
+    }
+    return;
+  }
   if constexpr (EPI == EPI_GRADT) {
     // rows d Nu + rho, d < DG, of the points rho in [r0, r1) (r1 <= Nu)
     const int64_t plane = (int64_t)g.Nu * g.ld;
@@ -193,6 +236,35 @@ void spop_launch_gradt(const GemmArgs &g, const SparseOp &sp, hipStream_t s) {
     spop_kernel<T, EPI_GRADT, W, float, double, float, DG, F><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
 }
 
+template <int W, int DG, int F>
+void spop_launch_addt(const GemmArgs &g, const SparseOp &sp, hipStream_t s) {
+  const int ngroups = (g.M + sp.rpg - 1) / sp.rpg;
+  dim3 grid((unsigned)(spop_tiles<F>(g) * ngroups), 1);
+  spop_kernel<double, EPI_ADDT, W, double, double, double, DG, F><<<grid, 256, 0, s>>>(
+      g, sp.colidx, sp.vals, sp.rpg, ngroups);
+}
+
+template <int F>
+hipError_t spop_addt_t(const GemmArgs &g, const SparseOp &sp, hipStream_t s) {
+  if ((g.D != 2 && g.D != 3) || g.Nu != g.M || g.K2 != 0 || !g.smat) return hipErrorInvalidValue;
+  constexpr int DG = F == 4 ? 2 : 3;
+  if (F > 1 && g.D != DG) return hipErrorInvalidValue;
+  switch (sp.width) {
+#define FR_W(W_)                                                          \
+  case W_:                                                                \
+    if constexpr (F > 1 && W_ > FR_SPOP_GRADT_FIELDS_WMAX)                \
+      return hipErrorInvalidValue;                                        \
+    else if constexpr (F > 1) spop_launch_addt<W_, DG, F>(g, sp, s);      \
+    else if (g.D == 3) spop_launch_addt<W_, 3, F>(g, sp, s);              \
+    else spop_launch_addt<W_, 2, F>(g, sp, s);                            \
+    break;
+    FR_SPOP_WIDTHS(FR_W)
+#undef FR_W
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <typename T, int F>
 hipError_t spop_gradt_t(const GemmArgs &g, const SparseOp &sp, hipStream_t s) {
   if ((g.D != 2 && g.D != 3) || g.Nu * g.D != g.M || !g.smat) return hipErrorInvalidValue;
@@ -234,6 +306,11 @@ template <int F>
 hipError_t launch_spop_f(int prec, int epi, const GemmArgs &g, const SparseOp &sp, int batch,
                          hipStream_t s) {
   if (F > 1 && g.N != (int64_t)F * g.ld) return hipErrorInvalidValue;
+  if (epi == EPI_ADDT) {
+    // the D batch slices are looped inside the kernel
+    if (batch != 1 || prec != PREC_F64) return hipErrorInvalidValue;
+    return spop_addt_t<F>(g, sp, s);
+  }
   if (epi == EPI_GRADT) {
     if (batch != 1) return hipErrorInvalidValue;
     if (prec == PREC_F64) return spop_gradt_t<double, F>(g, sp, s);

@@ -182,3 +182,32 @@ def test_stash_path_matches_recompute_path(name):
     err = float(torch.linalg.norm(l1 - l2) / torch.linalg.norm(l1))
     print(f"{name}: stash vs recompute step adjoint rel {err:.2e}")
     assert err < 1e-14
+
+
+@pytest.mark.parametrize("name", ["mixed5_p2_ns", "tgv3_p4", "curved3_p2_ns"])
+def test_adjoint_m0t_plans_agree(name):
+    """The adjoint's M0^T product with the reverse gradient transform fused
+    into its epilogue (sparse-row, one or all fields per thread) against the
+    unfused paths (matrix cores, LDS-staged) followed by the separate
+    transform kernel."""
+    import paper_1312_1638_amd as P
+    w = C.SMALL[name]()
+    d = Discretisation(w)
+    u = _off_kink(d, d.initial_state(w))
+    lam = _rand_like(u, 2)
+    s = C.solver_for(w)
+    got = {}
+    for tag in ("mfma", "sparse", "fields", "staged"):
+        for bi in range(len(w.mesh.blocks)):
+            nu = s.blocks[bi]["nupts"]
+            plan = {"mfma": (1, 1, -(-nu // 16)), "sparse": (0, 4, 0), "fields": (0, 2, 2),
+                    "staged": (0, 64, 4)}[tag]
+            try:
+                s.set_plan(bi, 13, plan)
+            except P.FRError:
+                assert tag == "staged"
+        got[tag] = s.unpack(s.rhs_adjoint(s.pack(u), s.pack(lam)))
+    for tag in ("sparse", "fields", "staged"):
+        err = C.rel_l2(got[tag], got["mfma"])
+        print(f"{name}: adjoint with M0^T plan {tag} vs matrix cores: rel L2 {err:.2e}")
+        assert err < 1e-13
