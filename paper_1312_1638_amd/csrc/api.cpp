@@ -630,6 +630,79 @@ struct Primal {
   const double *uf, *qf, *q;  // U^f, Q^f, Q of the state (null: recompute)
 };
 
+// Q b += blockdiag(M0)^T Q^f b, then Q~ b = J^-1 Q b (the reverse of the
+// gradient transform): one sparse-row launch with both fused where the plan
+// allows it, else the product and the transform kernel.
+void adj_m0t_transform(fr_ctx *c, BlockRT &b, const GemmOp &op, hipStream_t s) {
+  const int D = c->D;
+  const int64_t N = (int64_t)c->NV * b.ld;
+  if (op.MBW == 0 && !(op.WM & kPlanStaged)) {
+    fr::GemmArgs g = gemm_args(op);
+    g.B1 = c->d_qfb + b.qfoff; g.ldb1 = N; g.C = c->d_ftb + b.ftoff; g.ldc = N; g.N = N;
+    g.sB1 = (int64_t)b.Nf * N; g.sC = (int64_t)b.Nu * N;
+    g.ld = b.ld; g.nelem = b.nelem; g.rcpdjac = b.d_rcpdjac;
+    g.smat = b.d_smat; g.D = D; g.Nu = b.Nu;
+    hip_check(launch_op(op, fr::PREC_F64, fr::EPI_ADDT, g, 1, s), "M0^T + J^-1");
+  } else {
+    adj_gemm(c, op, c->d_qfb + b.qfoff, nullptr, c->d_ftb + b.ftoff, N, fr::EPI_ADD, D,
+             (int64_t)b.Nf * N, (int64_t)b.Nu * N, s);
+    fr::AdjPointArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.ndims = D; a.nvars = c->NV; a.nupts = b.Nu; a.ld = b.ld; a.nelem = b.nelem;
+    a.smat = b.d_smat; a.rcpdjac = b.d_rcpdjac; a.fb = c->d_ftb + b.ftoff;
+    hip_check(fr::launch_gradcoru_t(a, s), "gradcoru_t");
+  }
+}
+
+// Tune the adjoint's M0^T product of a Navier-Stokes block together with the
+// reverse gradient transform that follows it (fused or not, per plan).
+void tune_adj_m0t(fr_ctx *c, BlockRT &b, hipStream_t s) {
+  GemmOp &op = b.t_m0;
+  const int64_t N = (int64_t)c->NV * b.ld;
+  TuneKey key{c->prec, op.M, op.K1, op.K2, c->D, 20, 0, N};
+  fr::GemmPlan best{op.MBW, op.NC, op.WM};
+  auto it = g_tuned.find(key);
+  if (it != g_tuned.end()) {
+    best = it->second;
+  } else {
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "event");
+    hip_check(hipEventCreate(&e1), "event");
+    float best_ms = 1e30f;
+    std::vector<fr::GemmPlan> cands = fr::gemm_candidates(op.M, c->D * N, c->prec);
+    sparse_candidates(op, 0, c->D, cands);
+    for (const fr::GemmPlan &p : cands) {
+      if (p.MBW == 0 && (p.WM & kPlanFields) && op.sp.width > FR_SPOP_GRADT_FIELDS_WMAX) continue;
+      GemmOp trial = op;
+      trial.d_A = p.MBW ? pack_upload(c, op, p, s, false) : nullptr;
+      trial.MBW = p.MBW; trial.NC = p.NC; trial.WM = p.WM;
+      if (p.MBW == 0) apply_sparse_plan(trial, p, c->NV);
+      float ms = 0;
+      try {
+        for (int w = 0; w < 2; ++w) adj_m0t_transform(c, b, trial, s);
+        hip_check(hipEventRecord(e0, s), "record");
+        for (int w = 0; w < 5; ++w) adj_m0t_transform(c, b, trial, s);
+        hip_check(hipEventRecord(e1, s), "record");
+        hip_check(hipEventSynchronize(e1), "sync");
+        hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+      } catch (...) {
+        hipFree(trial.d_A);
+        throw;
+      }
+      hipFree(trial.d_A);
+      if (ms < best_ms) { best_ms = ms; best = p; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    g_tuned[key] = best;
+  }
+  if (best.MBW != op.MBW || best.NC != op.NC || best.WM != op.WM) {
+    op.d_A = best.MBW ? pack_upload(c, op, best, s, true) : nullptr;
+    op.MBW = best.MBW; op.NC = best.NC; op.WM = best.WM;
+    if (best.MBW == 0) apply_sparse_plan(op, best, c->NV);
+  }
+}
+
 void tune_adjoint_ops(fr_ctx *c, hipStream_t s) {
   const int D = c->D, NV = c->NV;
   for (auto &b : c->blocks) {
@@ -637,8 +710,7 @@ void tune_adjoint_ops(fr_ctx *c, hipStream_t s) {
     tune_adj(c, b.t_m3, c->d_lt + b.uoff, nullptr, c->d_ufb + b.ufoff, N, fr::EPI_STORE, 1, 0, 0, s);
     tune_adj(c, b.t_m1, c->d_lt + b.uoff, nullptr, c->d_ftb + b.ftoff, N, fr::EPI_STORE, 1, 0, 0, s);
     if (c->ns) {
-      tune_adj(c, b.t_m0, c->d_qfb + b.qfoff, nullptr, c->d_ftb + b.ftoff, N, fr::EPI_ADD, D,
-               (int64_t)b.Nf * N, (int64_t)b.Nu * N, s);
+      tune_adj_m0t(c, b, s);
       tune_adj(c, b.t_m6, c->d_ftb + b.ftoff, nullptr, c->d_qfb + b.qfoff, N, fr::EPI_STORE, 1, 0,
                0, s);
       tune_adj(c, b.t_fin, c->d_ftb + b.ftoff, c->d_ufb + b.ufoff, c->d_w + b.uoff, N,
@@ -686,20 +758,7 @@ void rhs_adjoint_chain(fr_ctx *c, const double *u, const double *lam, double *ul
     hip_check(fr::launch_tflux_vjp(a, c->ns, s), "tflux_vjp");
     const int64_t N = (int64_t)NV * b.ld;
     if (c->ns) {
-      // Q b += blockdiag(M0)^T Q^f b, then Q~ b = J^-1 Q b (the reverse of
-      // the gradient transform), in one sparse-row launch where possible
-      if (b.t_m0.MBW == 0 && !(b.t_m0.WM & kPlanStaged)) {
-        fr::GemmArgs g = gemm_args(b.t_m0);
-        g.B1 = c->d_qfb + b.qfoff; g.ldb1 = N; g.C = c->d_ftb + b.ftoff; g.ldc = N; g.N = N;
-        g.sB1 = (int64_t)b.Nf * N; g.sC = (int64_t)b.Nu * N;
-        g.ld = b.ld; g.nelem = b.nelem; g.rcpdjac = b.d_rcpdjac;
-        g.smat = b.d_smat; g.D = D; g.Nu = b.Nu;
-        hip_check(launch_op(b.t_m0, fr::PREC_F64, fr::EPI_ADDT, g, 1, s), "M0^T + J^-1");
-      } else {
-        adj_gemm(c, b.t_m0, c->d_qfb + b.qfoff, nullptr, c->d_ftb + b.ftoff, N, fr::EPI_ADD, D,
-                 (int64_t)b.Nf * N, (int64_t)b.Nu * N, s);
-        hip_check(fr::launch_gradcoru_t(a, s), "gradcoru_t");
-      }
+      adj_m0t_transform(c, b, b.t_m0, s);
       // C^f b = M6^T Q~b (into the first rows of the Q^f b region)
       adj_gemm(c, b.t_m6, c->d_ftb + b.ftoff, nullptr, c->d_qfb + b.qfoff, N, fr::EPI_STORE, 1,
                0, 0, s);
@@ -1430,7 +1489,8 @@ fr_status fr_debug_set_plan(fr_ctx *c, int32_t block, int32_t step, int32_t mbw,
       const bool staged = wm & kPlanStaged, fused = wm & kPlanFusedGradT;
       if (nc < 1 || wm < 0 || wm > 7 || (fused && step != 3) ||
           (staged && ((wm & kPlanFields) || !staged_ok(*op, fused, c->D))) ||
-          (wm == (kPlanFusedGradT | kPlanFields) && op->sp.width > FR_SPOP_GRADT_FIELDS_WMAX))
+          (wm == (kPlanFusedGradT | kPlanFields) && op->sp.width > FR_SPOP_GRADT_FIELDS_WMAX) ||
+          (step == 13 && c->ns && (wm & kPlanFields) && op->sp.width > FR_SPOP_GRADT_FIELDS_WMAX))
         throw Fail{FR_EINVAL, "bad sparse-row plan"};
       op->d_A = nullptr;
       apply_sparse_plan(*op, p, c->NV);
