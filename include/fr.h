@@ -97,15 +97,57 @@ typedef struct {          /* one conforming face pair: x_R + shift == x_L       
   double shift[3];        /* periodic translation, zero otherwise             */
 } fr_facepair;
 
+/* Boundary conditions (Appendix C), given through ghost states of the
+ * boundary element's solution u_L at each boundary flux point. */
+typedef enum {
+  FR_BC_SUPERSONIC_INFLOW = 0,    /* ghost: the free stream (rho, v, p)        */
+  FR_BC_SUBSONIC_OUTFLOW = 1,     /* ghost: rho_L, v_L with the pressure p      */
+  FR_BC_NOSLIP_ISOTHERMAL_WALL = 2 /* inviscid ghost: rho_L, 2 v_w - v_L and
+                                     energy rho_L (C_p T_w / gamma + |.|^2/2);
+                                     LDG ghost: rho_L, v_w, rho_L (C_p T_w /
+                                     gamma + |v_w|^2/2); ghost gradient q_L    */
+} fr_bctype;
+
+typedef struct {          /* one boundary condition                           */
+  int32_t type;           /* fr_bctype                                         */
+  int32_t reserved;
+  double rho;             /* free-stream density (inflow)                      */
+  double v[3];            /* free-stream velocity (inflow)                     */
+  double p;               /* free-stream pressure (inflow, outflow)            */
+  double cp_tw;           /* C_p T_w (wall)                                    */
+  double vw[3];           /* wall velocity (wall)                              */
+} fr_bc;
+
+typedef struct {          /* one element face on the domain boundary           */
+  int32_t block;
+  int32_t face;           /* numbering as in fr_facepair                       */
+  int64_t elem;
+  int32_t bc;             /* index into the fr_bc array                        */
+  int32_t reserved;
+} fr_bcface;
+
 /* Build a context: reference operators (Appendix A: M0, M3, M4-M6 M0,
  * M1-M3 M2, M6, block-diagonal M5), per-point metric terms (section 2), the
  * flux-point pair table (each pair visited once, eq. commsoln) and scratch.
  * `blocks`, `pairs` and node arrays are host memory, only read during the
- * call.  Periodic meshes only: every flux point must be paired exactly once,
- * else FR_EMESH.  On success *out owns all device memory it allocated. */
+ * call.  fr_setup_mesh: periodic meshes; every flux point must be paired
+ * exactly once, else FR_EMESH.  On success *out owns all device memory it
+ * allocated. */
 fr_status fr_setup_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *blocks,
                         int64_t npairs, const fr_facepair *pairs, void *hip_stream,
                         fr_ctx **out);
+/* fr_setup_mesh with boundary faces (Appendix C): every flux point must be
+ * paired, or lie on one of the `nbcfaces` boundary faces, exactly once (else
+ * FR_EMESH).  At a boundary flux point the common solution is
+ * (1/2 - beta) u_L + (1/2 + beta) g_ldg and the common normal flux is the
+ * Rusanov flux of (u_L, g_inv) minus n.[(1/2 + beta) f_v(u_L, q_L) +
+ * (1/2 - beta) f_v(g_ldg, g_q)] plus tau (u_L - g_ldg), the boundary element
+ * being the L side.  `bcs` and `bcfaces` are host memory.  The adjoint calls
+ * return FR_EUNSUPPORTED on a context with boundary faces. */
+fr_status fr_setup_mesh_bc(const fr_config *cfg, int32_t nblocks, const fr_block *blocks,
+                           int64_t npairs, const fr_facepair *pairs, int32_t nbcs,
+                           const fr_bc *bcs, int64_t nbcfaces, const fr_bcface *bcfaces,
+                           void *hip_stream, fr_ctx **out);
 
 /* Layout of block `block`: its offset into the state array, leading
  * dimension, points per element, fields, and the total state length. */

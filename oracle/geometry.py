@@ -111,13 +111,15 @@ class BlockGeometry:
         self.detJf = _det(Jf, Sf)
 
 
-def pair_flux_points(mesh, refs, geoms, tol_rel=1e-9, allow_unpaired=False):
+def pair_flux_points(mesh, refs, geoms, tol_rel=1e-9, allow_unpaired=False, boundary=None):
     """Match the flux points of every face pair by physical coordinate.
 
     Returns a dict of int arrays (lb, le, ls, rb, re, rs), one entry per flux
     point pair, in face-pair order.  Raises ValueError if a pair does not
     match point for point, or if a flux point is paired more than once or
     (unless allow_unpaired: a patch cut out of a larger mesh) not at all.
+    ``boundary`` (b, e, s) arrays: flux points of boundary faces, which count
+    as their own interface.
     """
     pairs = mesh.pairs
     h = mesh.info.get("h", 1.0)
@@ -159,6 +161,11 @@ def pair_flux_points(mesh, refs, geoms, tol_rel=1e-9, allow_unpaired=False):
     res = {k: np.concatenate(v).astype(np.int64) for k, v in out.items()}
     # check every flux point of every block is used exactly once
     counts = [np.zeros((g.nelem, r.nfpts), np.int64) for g, r in zip(geoms, refs)]
+    if boundary is not None:
+        bb, be, bs = boundary
+        for b in range(len(refs)):
+            s = bb == b
+            np.add.at(counts[b], (be[s], bs[s]), 1)
     for side in ("l", "r"):
         for b in range(len(refs)):
             s = res[side + "b"] == b

@@ -113,3 +113,61 @@ def common_flux(uL, uR, qL, qR, n, params):
 def common_solution(uL, uR, beta):
     """LDG common solution C(uL, uR) = (1/2 - beta) uL + (1/2 + beta) uR."""
     return (0.5 - beta) * uL + (0.5 + beta) * uR
+
+
+# ---------------------------------------------------------------------------
+# Boundary conditions (Appendix C): ghost states of the boundary element's
+# solution at its flux points.  A boundary flux point is an interface of its
+# own with the boundary element as the L side.
+# ---------------------------------------------------------------------------
+def boundary_ghosts(uL, qL, bc, gamma):
+    """(B_inv u_L, B_ldg u_L, B_ldg q_L) for one boundary condition; uL is
+    (NV, m), qL (D, NV, m) or None (Euler)."""
+    D = uL.shape[0] - 2
+    rho = uL[0]
+    kind = bc["type"]
+    if kind == "supersonic-inflow":
+        rf, pf = bc["rho"], bc["p"]
+        vf = np.asarray(bc["v"][:D], dtype=float)
+        g = np.empty_like(uL)
+        g[0] = rf
+        g[1:1 + D] = rf * vf[:, None]
+        g[D + 1] = pf / (gamma - 1) + 0.5 * rf * np.dot(vf, vf)
+        return g, g, None if qL is None else np.zeros_like(qL)
+    if kind == "subsonic-outflow":
+        g = uL.copy()
+        v = uL[1:1 + D] / rho
+        g[D + 1] = bc["p"] / (gamma - 1) + 0.5 * rho * np.sum(v * v, axis=0)
+        return g, g, None if qL is None else np.zeros_like(qL)
+    if kind == "no-slip-isothermal-wall":
+        vw = np.asarray(bc["vw"][:D], dtype=float)[:, None]
+        w = 2 * vw - uL[1:1 + D] / rho
+        e = bc["cp_tw"] / gamma
+        ginv = np.concatenate([rho[None], rho * w, rho * (e + 0.5 * np.sum(w * w, axis=0))[None]])
+        gldg = np.concatenate([rho[None], rho * vw * np.ones_like(rho),
+                               rho[None] * (e + 0.5 * float(np.sum(vw * vw)))])
+        return ginv, gldg, qL
+    raise ValueError(kind)
+
+
+def boundary_common_solution(uL, bc, params):
+    """Common solution at boundary flux points: C(u_L, B_ldg u_L)."""
+    _, gldg, _ = boundary_ghosts(uL, None, bc, params["gamma"])
+    return common_solution(uL, gldg, params["ldg_beta"])
+
+
+def boundary_common_flux(uL, qL, n, bc, params):
+    """Common normal flux at boundary flux points: the Rusanov flux with the
+    inviscid ghost and, for Navier-Stokes, the LDG viscous flux and penalty
+    with the LDG ghost state and gradient."""
+    ginv, gldg, gq = boundary_ghosts(uL, qL, bc, params["gamma"])
+    F = rusanov(uL, ginv, n, params["gamma"])
+    if params["system"] == "ns":
+        g, mu, pr = params["gamma"], params["mu"], params["prandtl"]
+        beta, tau = params["ldg_beta"], params["ldg_tau"]
+        fvL = viscous_flux(uL, qL, g, mu, pr)
+        fvR = viscous_flux(gldg, gq, g, mu, pr)
+        D = n.shape[0]
+        fv = sum(n[j] * ((0.5 + beta) * fvL[j] + (0.5 - beta) * fvR[j]) for j in range(D))
+        F = F - fv + tau * (uL - gldg)
+    return F

@@ -53,8 +53,20 @@ class Discretisation:
         for g in self.geoms:
             if np.any(g.detJ <= 0) or np.any(g.detJf <= 0):
                 raise ValueError("non-positive Jacobian")
+        # flux points on boundary faces (Appendix C): (block, elem, sigma, bc)
+        self.bcs = tuple(getattr(w.mesh, "bcs", ()))
+        bcf = getattr(w.mesh, "bcfaces", None)
+        bb, be, bs, bk = [], [], [], []
+        if bcf is not None:
+            for rec in bcf:
+                b, e, f, k = int(rec["block"]), int(rec["elem"]), int(rec["face"]), int(rec["bc"])
+                sig = np.nonzero(self.refs[b].fface == f)[0]
+                bb += [b] * len(sig); be += [e] * len(sig); bs += list(sig); bk += [k] * len(sig)
+        self.bnd = dict(b=np.array(bb, np.int64), e=np.array(be, np.int64),
+                        s=np.array(bs, np.int64), bc=np.array(bk, np.int64))
         pr = geometry.pair_flux_points(w.mesh, self.refs, self.geoms,
-                                       allow_unpaired=allow_unpaired)
+                                       allow_unpaired=allow_unpaired,
+                                       boundary=(self.bnd["b"], self.bnd["e"], self.bnd["s"]))
         self.pairs = pr
         # flat index of a flux point (block, sigma, n) into the concatenation
         # of every block's (Nf, ne) flux-point array
@@ -62,6 +74,8 @@ class Discretisation:
         self.gl = self._flat(pr["lb"], pr["ls"], pr["le"])
         self.gr = self._flat(pr["rb"], pr["rs"], pr["re"])
         self.nL, self.magL, self.magR = self._pair_metrics(self.geoms)
+        self.gb = self._flat(self.bnd["b"], self.bnd["s"], self.bnd["e"])
+        self.nB, self.magB = self._boundary_metrics(self.geoms)
         self.dt_per_elem = None
 
     def _pair_metrics(self, geoms):
@@ -81,6 +95,18 @@ class Discretisation:
             magR[s] = g.fmag[pr["re"][s], pr["rs"][s]]
         return nL.T.copy(), magL, magR
 
+    def _boundary_metrics(self, geoms):
+        """Outward unit normal (D, nbpts) and J^(f) n^(f) at boundary flux points."""
+        bd = self.bnd
+        dt = geoms[0].fmag.dtype
+        nB = np.empty((len(bd["b"]), self.ndims), dtype=dt)
+        magB = np.empty(len(bd["b"]), dtype=dt)
+        for b, g in enumerate(geoms):
+            s = bd["b"] == b
+            nB[s] = g.fnhat[bd["e"][s], bd["s"][s]]
+            magB[s] = g.fmag[bd["e"][s], bd["s"][s]]
+        return nB.T.copy(), magB
+
     def extended(self):
         """A copy whose metric terms and normals are recomputed from the nodes
         in long double, so ``rhs`` on long-double states evaluates the same
@@ -92,6 +118,7 @@ class Discretisation:
         e.geoms = [geometry.BlockGeometry(r, b, np.longdouble)
                    for r, b in zip(self.refs, self.mesh.blocks)]
         e.nL, e.magL, e.magR = self._pair_metrics(e.geoms)
+        e.nB, e.magB = self._boundary_metrics(e.geoms)
         return e
 
     def _flat(self, b, s, e):
@@ -150,6 +177,10 @@ class Discretisation:
             CF = np.zeros_like(UF)        # zero at unpaired points of a patch
             CF[:, self.gl] = c
             CF[:, self.gr] = c
+            # boundary flux points: common solution with the boundary's ghost
+            for k, bc in enumerate(self.bcs):
+                sel = self.gb[self.bnd["bc"] == k]
+                CF[:, sel] = physics.boundary_common_solution(UF[:, sel], bc, P)
             qfs = []
             for b in range(nb):
                 r, g = refs[b], geoms[b]
@@ -189,6 +220,14 @@ class Discretisation:
         DF = np.zeros_like(UF)
         DF[:, self.gl] = self.magL * F
         DF[:, self.gr] = -self.magR * F
+        # boundary flux points: common normal flux with the boundary's ghosts,
+        # scaled like an L side
+        for k, bc in enumerate(self.bcs):
+            m = self.bnd["bc"] == k
+            sel = self.gb[m]
+            qB = qf_flat[:, :, sel] if ns else None
+            FB = physics.boundary_common_flux(UF[:, sel], qB, self.nB[:, m], bc, P)
+            DF[:, sel] = self.magB[m] * FB
         if record is not None:
             record["uf"] = uf
             record["ft"] = Ft

@@ -21,7 +21,7 @@ ETYPE = {"quad": 0, "tri": 1, "hex": 2}
 SYSTEM = {"euler": 0, "ns": 1}
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
-EXPORTS = ("fr_setup_mesh", "fr_get_layout", "fr_get_solution_points", "fr_get_quadrature",
+EXPORTS = ("fr_setup_mesh", "fr_setup_mesh_bc", "fr_get_layout", "fr_get_solution_points", "fr_get_quadrature",
            "fr_rhs", "fr_rk_step", "fr_rhs_adjoint", "fr_rk_step_adjoint", "fr_integrate",
            "fr_reference_operator", "fr_check_mesh", "fr_debug_stage", "fr_debug_scratch_len", "fr_bench_step",
            "fr_debug_gemm", "fr_measure_ceiling", "fr_bench_gemm", "fr_get_gemm_plan", "fr_integrate_grad", "fr_stash_len", "fr_rk_step_stash",
@@ -51,6 +51,13 @@ class FrBlock(ctypes.Structure):
 
 
 # numpy view of fr_facepair (natural C alignment, 56 bytes)
+# fr_bc and fr_bcface (include/fr.h)
+BC_C = np.dtype([("type", "<i4"), ("reserved", "<i4"), ("rho", "<f8"), ("v", "<f8", (3,)),
+                 ("p", "<f8"), ("cp_tw", "<f8"), ("vw", "<f8", (3,))], align=True)
+BCFACE_C = np.dtype([("block", "<i4"), ("face", "<i4"), ("elem", "<i8"), ("bc", "<i4"),
+                     ("reserved", "<i4")], align=True)
+BCTYPE = {"supersonic-inflow": 0, "subsonic-outflow": 1, "no-slip-isothermal-wall": 2}
+
 FACEPAIR_C = np.dtype([("lblock", "<i4"), ("lface", "<i4"), ("lelem", "<i8"),
                        ("rblock", "<i4"), ("rface", "<i4"), ("relem", "<i8"),
                        ("shift", "<f8", (3,))], align=True)
@@ -68,6 +75,8 @@ def load_library(path: str = LIB_PATH):
     L = ctypes.CDLL(path)
     vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
     sig = {
+        "fr_setup_mesh_bc": [ctypes.POINTER(FrConfig), i32, ctypes.POINTER(FrBlock), i64, vp, i32,
+                             vp, i64, vp, vp, ctypes.POINTER(vp)],
         "fr_setup_mesh": [ctypes.POINTER(FrConfig), i32, ctypes.POINTER(FrBlock), i64, vp, vp,
                           ctypes.POINTER(vp)],
         "fr_get_layout": [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64),
@@ -191,6 +200,25 @@ def _marshal_mesh(mesh):
     return arr, pairs, keep
 
 
+def _marshal_bcs(mesh):
+    """mesh.bcs (dicts: type and parameters) and mesh.bcfaces (block, elem,
+    face, bc records) -> fr_bc and fr_bcface arrays."""
+    bcs = np.zeros(len(mesh.bcs), dtype=BC_C)
+    for k, b in enumerate(mesh.bcs):
+        bcs[k]["type"] = BCTYPE[b["type"]]
+        bcs[k]["rho"] = b.get("rho", 0.0)
+        bcs[k]["v"] = list(b.get("v", (0.0, 0.0, 0.0))) + [0.0] * (3 - len(b.get("v", (0.0, 0.0, 0.0))))
+        bcs[k]["p"] = b.get("p", 0.0)
+        bcs[k]["cp_tw"] = b.get("cp_tw", 0.0)
+        vw = list(b.get("vw", (0.0, 0.0, 0.0)))
+        bcs[k]["vw"] = vw + [0.0] * (3 - len(vw))
+    f = mesh.bcfaces
+    faces = np.zeros(len(f), dtype=BCFACE_C)
+    for name in ("block", "face", "elem", "bc"):
+        faces[name] = f[name]
+    return bcs, faces
+
+
 def check_mesh(mesh, system="euler") -> int:
     """Run the library's host set-up (metrics + pairing); returns the number of
     flux-point pairs or raises FRError."""
@@ -229,8 +257,15 @@ class Solver:
         arr, pairs, keep = _marshal_mesh(mesh)
         ctx = ctypes.c_void_p()
         stream = torch.cuda.current_stream().cuda_stream
-        _check(L.fr_setup_mesh(ctypes.byref(cfg), len(mesh.blocks), arr, len(pairs),
-                               pairs.ctypes.data, stream, ctypes.byref(ctx)))
+        bcfaces = getattr(mesh, "bcfaces", None)
+        if bcfaces is not None and len(bcfaces):
+            bcs, faces = _marshal_bcs(mesh)
+            _check(L.fr_setup_mesh_bc(ctypes.byref(cfg), len(mesh.blocks), arr, len(pairs),
+                                      pairs.ctypes.data, len(bcs), bcs.ctypes.data, len(faces),
+                                      faces.ctypes.data, stream, ctypes.byref(ctx)))
+        else:
+            _check(L.fr_setup_mesh(ctypes.byref(cfg), len(mesh.blocks), arr, len(pairs),
+                                   pairs.ctypes.data, stream, ctypes.byref(ctx)))
         self.ctx = ctx
         self.blocks = []
         for b in range(len(mesh.blocks)):

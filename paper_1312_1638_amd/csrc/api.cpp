@@ -107,6 +107,10 @@ struct fr_ctx {
   int64_t npairs = 0;
   int32_t *d_lidx = nullptr, *d_ridx = nullptr, *d_lblk = nullptr, *d_rblk = nullptr;
   double *d_nrm = nullptr, *d_magL = nullptr, *d_magR = nullptr;
+  // boundary flux points (Appendix C)
+  int64_t nbpts = 0;
+  int32_t *d_bidx = nullptr, *d_bblk = nullptr, *d_bcid = nullptr;
+  double *d_bnrm = nullptr, *d_bmag = nullptr, *d_bcpar = nullptr;
   int64_t *d_blk_ufbase = nullptr, *d_blk_qfbase = nullptr, *d_blk_ld = nullptr,
           *d_blk_qstride = nullptr;
   // reductions
@@ -341,6 +345,18 @@ fr::PairArgs pair_args(fr_ctx *c) {
   return pa;
 }
 
+// Arguments of the boundary kernels: the boundary flux points as L sides.
+fr::PairArgs bc_args(fr_ctx *c) {
+  fr::PairArgs pa = pair_args(c);
+  pa.npairs = c->nbpts;
+  pa.lidx = c->d_bidx; pa.ridx = nullptr;
+  pa.lblk = c->blocks.size() > 1 ? c->d_bblk : nullptr;
+  pa.rblk = nullptr;
+  pa.nrm = c->d_bnrm; pa.magL = c->d_bmag; pa.magR = nullptr;
+  pa.bcid = c->d_bcid; pa.bcpar = c->d_bcpar;
+  return pa;
+}
+
 fr::PointArgs point_args(fr_ctx *c, const BlockRT &b, const double *u) {
   fr::PointArgs p;
   std::memset(&p, 0, sizeof(p));
@@ -369,8 +385,16 @@ void run_step(fr_ctx *c, int st, const double *u, double *dudt, int epi, const f
   const int gprec = c->prec == FR_FP64 ? fr::PREC_F64
                     : (c->prec == FR_FP32 ? fr::PREC_F32 : fr::PREC_BF16X3);
   if (!c->ns && st >= 2 && st <= 5) return;
-  if (st == 2) { hip_check(fr::launch_con_u(pair_args(c), s), "con_u"); return; }
-  if (st == 7) { hip_check(fr::launch_comm_flux(pair_args(c), c->ns, s), "comm_flux"); return; }
+  if (st == 2) {
+    hip_check(fr::launch_con_u(pair_args(c), s), "con_u");
+    if (c->nbpts) hip_check(fr::launch_bc_con_u(bc_args(c), s), "boundary con_u");
+    return;
+  }
+  if (st == 7) {
+    hip_check(fr::launch_comm_flux(pair_args(c), c->ns, s), "comm_flux");
+    if (c->nbpts) hip_check(fr::launch_bc_comm_flux(bc_args(c), c->ns, s), "boundary comm_flux");
+    return;
+  }
   for (auto &b : c->blocks) {
     const int64_t N = NV * b.ld;
     if (st == 1) {
@@ -524,6 +548,7 @@ std::vector<double> transpose(const std::vector<double> &A, int rows, int cols) 
 }
 
 void ensure_adjoint(fr_ctx *c, hipStream_t s) {
+  if (c->nbpts) throw Fail{FR_EUNSUPPORTED, "the adjoint does not cover boundary conditions"};
   if (c->adj_ready) return;
   if (c->prec != FR_FP64) throw Fail{FR_EUNSUPPORTED, "the adjoint is available for FP64 contexts"};
   const int D = c->D, NV = c->NV;
@@ -904,10 +929,23 @@ extern "C" {
 fr_status fr_setup_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *blocks,
                         int64_t npairs, const fr_facepair *pairs, void *hip_stream,
                         fr_ctx **out) {
+  return fr_setup_mesh_bc(cfg, nblocks, blocks, npairs, pairs, 0, nullptr, 0, nullptr, hip_stream,
+                          out);
+}
+
+fr_status fr_setup_mesh_bc(const fr_config *cfg, int32_t nblocks, const fr_block *blocks,
+                           int64_t npairs, const fr_facepair *pairs, int32_t nbcs,
+                           const fr_bc *bcs, int64_t nbcfaces, const fr_bcface *bcfaces,
+                           void *hip_stream, fr_ctx **out) {
   if (!out) return fail(nullptr, FR_EINVAL, "out is NULL");
   *out = nullptr;
   if (!cfg || !blocks || nblocks < 1 || npairs < 0 || (npairs > 0 && !pairs))
     return fail(nullptr, FR_EINVAL, "bad arguments");
+  if (nbcs < 0 || nbcfaces < 0 || (nbcs > 0 && !bcs) || (nbcfaces > 0 && !bcfaces))
+    return fail(nullptr, FR_EINVAL, "bad boundary arguments");
+  for (int32_t k = 0; k < nbcs; ++k)
+    if (bcs[k].type < FR_BC_SUPERSONIC_INFLOW || bcs[k].type > FR_BC_NOSLIP_ISOTHERMAL_WALL)
+      return fail(nullptr, FR_EINVAL, "bad boundary condition type");
   if (cfg->ndims != 2 && cfg->ndims != 3) return fail(nullptr, FR_EINVAL, "ndims must be 2 or 3");
   if (cfg->system != FR_EULER && cfg->system != FR_NAVIER_STOKES)
     return fail(nullptr, FR_EINVAL, "bad system");
@@ -966,8 +1004,31 @@ fr_status fr_setup_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *b
       pin[k] = fr::FacePairIn{P.lblock, P.lface, P.lelem, P.rblock, P.rface, P.relem,
                               {P.shift[0], P.shift[1], P.shift[2]}};
     }
-    fr::PairTable T = fr::build_pairs(c->refs, geoms, block_ref, D, NV, pin.data(), npairs);
+    std::vector<fr::BcFaceIn> bin(nbcfaces);
+    for (int64_t k = 0; k < nbcfaces; ++k)
+      bin[k] = fr::BcFaceIn{bcfaces[k].block, bcfaces[k].face, bcfaces[k].elem, bcfaces[k].bc};
+    fr::BcTable BT;
+    fr::PairTable T = fr::build_pairs(c->refs, geoms, block_ref, D, NV, pin.data(), npairs,
+                                      bin.data(), nbcfaces, nbcs, &BT);
     c->npairs = T.n;
+    c->nbpts = BT.n;
+    if (BT.n) {
+      std::vector<int32_t> bi(BT.n);
+      for (int64_t i = 0; i < BT.n; ++i) bi[i] = (int32_t)BT.idx[i];
+      c->d_bidx = dev_upload(c.get(), bi.data(), BT.n, s);
+      c->d_bblk = dev_upload(c.get(), BT.blk.data(), BT.n, s);
+      c->d_bcid = dev_upload(c.get(), BT.bc.data(), BT.n, s);
+      c->d_bnrm = dev_upload(c.get(), BT.nrm.data(), BT.nrm.size(), s);
+      c->d_bmag = dev_upload(c.get(), BT.mag.data(), BT.n, s);
+      std::vector<double> par((size_t)nbcs * FR_BC_NPAR, 0.0);
+      for (int32_t k = 0; k < nbcs; ++k) {
+        double *q = &par[(size_t)k * FR_BC_NPAR];
+        q[0] = bcs[k].type; q[1] = bcs[k].rho;
+        for (int d = 0; d < 3; ++d) { q[2 + d] = bcs[k].v[d]; q[7 + d] = bcs[k].vw[d]; }
+        q[5] = bcs[k].p; q[6] = bcs[k].cp_tw;
+      }
+      c->d_bcpar = dev_upload(c.get(), par.data(), par.size(), s);
+    }
     // device data: geometry and operators
     for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
       BlockRT &b = c->blocks[bi];
@@ -1293,7 +1354,8 @@ fr_status fr_check_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *b
       pin[k] = fr::FacePairIn{P.lblock, P.lface, P.lelem, P.rblock, P.rface, P.relem,
                               {P.shift[0], P.shift[1], P.shift[2]}};
     }
-    fr::PairTable T = fr::build_pairs(refs, geoms, block_ref, D, D + 2, pin.data(), npairs);
+    fr::PairTable T = fr::build_pairs(refs, geoms, block_ref, D, D + 2, pin.data(), npairs,
+                                      nullptr, 0, 0, nullptr);
     if (npoint_pairs) *npoint_pairs = T.n;
   } catch (const fr::SetupError &e) {
     return fail(nullptr, (fr_status)e.status, e.what());

@@ -161,12 +161,21 @@ struct PairArgs {
   const int64_t *blk_qstride;      // per block: Nf * NV * ld
   int64_t ld0, qstride0;           // single-block values
   double gamma, mu, prandtl, beta, tau;
+  // boundary flux points (launch_bc_*): npairs of them, lidx/lblk/nrm/magL
+  // describe the point, bcid its boundary, bcpar[bc * FR_BC_NPAR + ...] the
+  // boundary's parameters (layout of bc_ghosts in physics.h)
+  const int32_t *bcid;
+  const double *bcpar;
 };
+#define FR_BC_NPAR 12
 
 // S2: common solution to both sides
 hipError_t launch_con_u(const PairArgs &a, hipStream_t s);
 // S7: common normal flux, scaled per side, in place over U^f
 hipError_t launch_comm_flux(const PairArgs &a, int navier_stokes, hipStream_t s);
+// S2 and S7 at boundary flux points (Appendix C ghost states)
+hipError_t launch_bc_con_u(const PairArgs &a, hipStream_t s);
+hipError_t launch_bc_comm_flux(const PairArgs &a, int navier_stokes, hipStream_t s);
 
 // ----------------------------------------------------------------------------
 // Reductions

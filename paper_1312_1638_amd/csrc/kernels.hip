@@ -230,6 +230,112 @@ __global__ __launch_bounds__(256) void comm_flux_kernel(PairArgs a, unsigned nre
   }
 }
 
+// Boundary flux points: the common solution (from the ghost of the LDG
+// terms) and the common normal flux (inviscid ghost in the Rusanov flux, LDG
+// ghost and ghost gradient in the viscous flux and penalty), with the
+// boundary element as the L side.
+template <int D, bool MULTI, typename T>
+__global__ __launch_bounds__(256) void bc_con_u_kernel(PairArgs a) {
+  constexpr int NV = D + 2;
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= a.npairs) return;
+  const Side L = side_of<MULTI>(a, a.lblk, k, true);
+  const int64_t i = a.lidx[k];
+  const T *uf = (const T *)a.uf;
+  T *cf = (T *)a.cf;
+  double u[NV], ginv[NV], gldg[NV];
+#pragma unroll
+  for (int al = 0; al < NV; ++al) u[al] = (double)uf[L.base + i + al * L.ld];
+  bool qzero;
+  bc_ghosts<D>(u, a.bcpar + (int64_t)a.bcid[k] * FR_BC_NPAR, a.gamma, ginv, gldg, qzero);
+  const double wl = 0.5 - a.beta, wr = 0.5 + a.beta;
+#pragma unroll
+  for (int al = 0; al < NV; ++al) cf[L.qbase + i + al * L.ld] = (T)(wl * u[al] + wr * gldg[al]);
+}
+
+template <int D, int NS, bool MULTI, typename T>
+__global__ __launch_bounds__(256) void bc_comm_flux_kernel(PairArgs a) {
+  constexpr int NV = D + 2;
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= a.npairs) return;
+  const Side L = side_of<MULTI>(a, a.lblk, k, NS);
+  const int64_t i = a.lidx[k];
+  T *uf = (T *)a.uf;
+  double u[NV], ginv[NV], gldg[NV], n[D], F[NV];
+#pragma unroll
+  for (int al = 0; al < NV; ++al) u[al] = (double)uf[L.base + i + al * L.ld];
+#pragma unroll
+  for (int d = 0; d < D; ++d) n[d] = a.nrm[d * a.npairs + k];
+  bool qzero;
+  bc_ghosts<D>(u, a.bcpar + (int64_t)a.bcid[k] * FR_BC_NPAR, a.gamma, ginv, gldg, qzero);
+  rusanov<D>(u, ginv, n, a.gamma, F);
+  if (NS) {
+    const T *qf = (const T *)a.qf;
+    double qL[D][NV], qR[D][NV], fvL[D][NV], fvR[D][NV];
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+      for (int al = 0; al < NV; ++al) {
+        qL[j][al] = (double)qf[L.qbase + j * L.qstride + i + al * L.ld];
+        qR[j][al] = qzero ? 0.0 : qL[j][al];
+      }
+    viscous_flux<D>(u, qL, a.gamma, a.mu, a.prandtl, fvL);
+    viscous_flux<D>(gldg, qR, a.gamma, a.mu, a.prandtl, fvR);
+    const double wl = 0.5 + a.beta, wr = 0.5 - a.beta;
+#pragma unroll
+    for (int al = 0; al < NV; ++al) {
+      double fv = 0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) fv += n[j] * (wl * fvL[j][al] + wr * fvR[j][al]);
+      F[al] = F[al] - fv + a.tau * (u[al] - gldg[al]);
+    }
+  }
+  const double m = a.magL[k];
+  T *df = a.dfout ? (T *)a.dfout : uf;
+#pragma unroll
+  for (int al = 0; al < NV; ++al) df[L.base + i + al * L.ld] = (T)(m * F[al]);
+}
+
+template <typename T>
+static hipError_t bc_con_u_t(const PairArgs &a, hipStream_t s) {
+  const unsigned grid = (unsigned)((a.npairs + 255) / 256);
+  const bool multi = a.lblk != nullptr;
+  if (a.ndims == 2) {
+    if (multi) bc_con_u_kernel<2, true, T><<<grid, 256, 0, s>>>(a);
+    else bc_con_u_kernel<2, false, T><<<grid, 256, 0, s>>>(a);
+  } else {
+    if (multi) bc_con_u_kernel<3, true, T><<<grid, 256, 0, s>>>(a);
+    else bc_con_u_kernel<3, false, T><<<grid, 256, 0, s>>>(a);
+  }
+  return hipGetLastError();
+}
+hipError_t launch_bc_con_u(const PairArgs &a, hipStream_t s) {
+  if (a.npairs <= 0) return hipSuccess;
+  return a.uf_f32 ? bc_con_u_t<float>(a, s) : bc_con_u_t<double>(a, s);
+}
+
+template <typename T, int NS>
+static void bc_comm_flux_go(const PairArgs &a, hipStream_t s) {
+  const unsigned grid = (unsigned)((a.npairs + 255) / 256);
+  const bool multi = a.lblk != nullptr;
+  if (a.ndims == 2) {
+    if (multi) bc_comm_flux_kernel<2, NS, true, T><<<grid, 256, 0, s>>>(a);
+    else bc_comm_flux_kernel<2, NS, false, T><<<grid, 256, 0, s>>>(a);
+  } else {
+    if (multi) bc_comm_flux_kernel<3, NS, true, T><<<grid, 256, 0, s>>>(a);
+    else bc_comm_flux_kernel<3, NS, false, T><<<grid, 256, 0, s>>>(a);
+  }
+}
+hipError_t launch_bc_comm_flux(const PairArgs &a, int ns, hipStream_t s) {
+  if (a.npairs <= 0) return hipSuccess;
+  if (a.uf_f32) {
+    if (ns) bc_comm_flux_go<float, 1>(a, s); else bc_comm_flux_go<float, 0>(a, s);
+  } else {
+    if (ns) bc_comm_flux_go<double, 1>(a, s); else bc_comm_flux_go<double, 0>(a, s);
+  }
+  return hipGetLastError();
+}
+
 static void pair_grid(int64_t npairs, unsigned &grid, unsigned &nreal) {
   nreal = (unsigned)((npairs + 255) / 256);
   grid = (nreal + 7) / 8 * 8;

@@ -266,4 +266,55 @@ __device__ __forceinline__ void rusanov_vjp(const double *uL, const double *uR, 
   inviscid_flux_vjp<D>(uR, gamma, fb, Pb, vbR, uRb);
 }
 
+// Boundary ghost states (Appendix C).  par: the boundary's parameters
+// [type, rho_f, v_f (3), p_f, C_p T_w, v_w (3)]; type 0 supersonic inflow,
+// 1 subsonic outflow, 2 no-slip isothermal wall.  ginv is the ghost of the
+// inviscid flux, gldg that of the common solution and of the LDG viscous
+// terms; the ghost gradient is zero (inflow, outflow) or q_L (wall).
+template <int D>
+__device__ __forceinline__ void bc_ghosts(const double *u, const double *par, double gamma,
+                                          double *ginv, double *gldg, bool &qzero) {
+  const int type = (int)par[0];
+  const double rho = u[0];
+  if (type == 0) {
+    double v2 = 0;
+    ginv[0] = par[1];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      ginv[1 + d] = par[1] * par[2 + d];
+      v2 += par[2 + d] * par[2 + d];
+    }
+    ginv[D + 1] = par[5] / (gamma - 1) + 0.5 * par[1] * v2;
+    qzero = true;
+  } else if (type == 1) {
+    double v2 = 0;
+    ginv[0] = rho;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      ginv[1 + d] = u[1 + d];
+      v2 += (u[1 + d] / rho) * (u[1 + d] / rho);
+    }
+    ginv[D + 1] = par[5] / (gamma - 1) + 0.5 * rho * v2;
+    qzero = true;
+  } else {
+    double w2 = 0, vw2 = 0;
+    ginv[0] = rho;
+    gldg[0] = rho;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const double w = 2 * par[7 + d] - u[1 + d] / rho;
+      ginv[1 + d] = rho * w;
+      gldg[1 + d] = rho * par[7 + d];
+      w2 += w * w;
+      vw2 += par[7 + d] * par[7 + d];
+    }
+    ginv[D + 1] = rho * (par[6] / gamma + 0.5 * w2);
+    gldg[D + 1] = rho * (par[6] / gamma + 0.5 * vw2);
+    qzero = false;
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < D + 2; ++a) gldg[a] = ginv[a];
+}
+
 }  // namespace fr

@@ -523,7 +523,8 @@ BlockGeom build_geom(const RefOps &ref, int g, int64_t nelem, const double *node
 // ---------------------------------------------------------------------------
 PairTable build_pairs(const std::vector<RefOps> &refs, const std::vector<BlockGeom> &geoms,
                       const std::vector<int> &block_ref, int D, int nvars,
-                      const FacePairIn *pairs, int64_t npairs) {
+                      const FacePairIn *pairs, int64_t npairs, const BcFaceIn *bcfaces,
+                      int64_t nbcfaces, int nbcs, BcTable *bct) {
   const int nb = (int)geoms.size();
   double hmin = 1e300;
   for (auto &g : geoms) hmin = std::min(hmin, g.hmin);
@@ -570,9 +571,47 @@ PairTable build_pairs(const std::vector<RefOps> &refs, const std::vector<BlockGe
       recs.push_back(r);
     }
   }
+  // boundary faces: each of their flux points is its own interface
+  struct BRec { int b, bc; int64_t i; double n[3]; double m; };
+  std::vector<BRec> brecs;
+  for (int64_t k = 0; k < nbcfaces; ++k) {
+    const BcFaceIn &F = bcfaces[k];
+    if (F.block < 0 || F.block >= nb) throw SetupError(1, "boundary face block out of range");
+    const RefOps &R = refs[block_ref[F.block]];
+    const BlockGeom &G = geoms[F.block];
+    if (F.elem < 0 || F.elem >= G.nelem || F.face < 0 || F.face >= R.nfaces)
+      throw SetupError(1, "boundary face element or face out of range");
+    if (F.bc < 0 || F.bc >= nbcs) throw SetupError(1, "boundary condition index out of range");
+    const int m = R.nfp_face;
+    for (int a = 0; a < m; ++a) {
+      const int s = F.face * m + a;
+      uint8_t &u = used[F.block][(size_t)F.elem * R.nfpts + s];
+      if (u) throw SetupError(2, "boundary flux point also paired or listed twice");
+      u = 1;
+      BRec r;
+      r.b = F.block; r.bc = F.bc;
+      r.i = (int64_t)s * nvars * G.ld + F.elem;
+      for (int d = 0; d < 3; ++d) r.n[d] = d < D ? G.fnhat[((size_t)F.elem * R.nfpts + s) * D + d] : 0;
+      r.m = G.fmag[(size_t)F.elem * R.nfpts + s];
+      brecs.push_back(r);
+    }
+  }
   for (int b = 0; b < nb; ++b)
     for (uint8_t u : used[b])
-      if (!u) throw SetupError(2, "unpaired flux point (only periodic meshes are supported)");
+      if (!u) throw SetupError(2, "flux point neither paired nor on a boundary face");
+  std::sort(brecs.begin(), brecs.end(), [](const BRec &a, const BRec &b) {
+    return a.b != b.b ? a.b < b.b : a.i < b.i;
+  });
+  if (bct) {
+    bct->n = (int64_t)brecs.size();
+    bct->blk.resize(bct->n); bct->bc.resize(bct->n); bct->idx.resize(bct->n);
+    bct->nrm.resize((size_t)D * bct->n); bct->mag.resize(bct->n);
+    for (int64_t i = 0; i < bct->n; ++i) {
+      const BRec &r = brecs[i];
+      bct->blk[i] = r.b; bct->bc[i] = r.bc; bct->idx[i] = r.i; bct->mag[i] = r.m;
+      for (int d = 0; d < D; ++d) bct->nrm[(size_t)d * bct->n + i] = r.n[d];
+    }
+  }
   // order pairs by (L block, L flux point, L element): consecutive pairs then
   // read consecutive elements of one U^f row, which coalesces the L side
   std::sort(recs.begin(), recs.end(), [](const Rec &a, const Rec &b) {

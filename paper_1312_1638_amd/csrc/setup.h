@@ -69,9 +69,28 @@ struct PairTable {
   std::vector<double> magL, magR;    // J^(f) n^(f) on each side
 };
 
+// A face on the domain boundary (Appendix C: one flux point per boundary
+// interface point, with a boundary type).
+struct BcFaceIn {
+  int block, face; int64_t elem; int bc;
+};
+
+// Boundary flux-point table, sorted like the pair table's L side.
+struct BcTable {
+  int64_t n = 0;
+  std::vector<int32_t> blk, bc;      // block and boundary condition of each point
+  std::vector<int64_t> idx;          // sigma * nvars * ld + n within the block's U^f
+  std::vector<double> nrm;           // [D][n] outward unit normal
+  std::vector<double> mag;           // J^(f) n^(f)
+};
+
+// Pairs every flux point of the face pairs; flux points of boundary faces go
+// to `bct` (bcfaces may be null with nbcfaces = 0).  Every flux point must be
+// paired or on a boundary face exactly once.
 PairTable build_pairs(const std::vector<RefOps> &refs, const std::vector<BlockGeom> &geoms,
                       const std::vector<int> &block_ref, int ndims, int nvars,
-                      const FacePairIn *pairs, int64_t npairs);
+                      const FacePairIn *pairs, int64_t npairs, const BcFaceIn *bcfaces,
+                      int64_t nbcfaces, int nbcs, BcTable *bct);
 
 int nnodes_of(int etype, int geom_order);
 

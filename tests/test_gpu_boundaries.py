@@ -1,0 +1,133 @@
+"""Boundary conditions (Appendix C) through the C ABI against the oracle:
+no-slip isothermal walls (Couette channels on quads, mixed quads/triangles and
+hexes), supersonic inflow and subsonic outflow (a channel in x), Euler and
+Navier-Stokes; du/dt from states that violate the boundary conditions, RK4
+steps in the captured graph, FP32 operator products, every kernel family; and
+the Couette steady state reached by time marching, against the analytic
+solution and the oracle's Newton steady state."""
+import math
+
+import numpy as np
+import pytest
+
+import frcases as C
+from oracle import Discretisation
+from workloads import configs, fields, meshes
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "couette_quad4_p3": lambda: configs.couette(4, 3, "quad", start="constant"),
+    "couette_mixed5_p2": lambda: configs.couette(5, 2, "mixed", seed=1, start="constant"),
+    "couette_hex3_p2": lambda: configs.couette(3, 2, "hex", start="constant"),
+    "couette_exact_mixed4_p3": lambda: configs.couette(4, 3, "mixed", seed=2),
+    "channel5_p3_euler": lambda: configs.channel(5, 3, "euler", eps=0.05),
+    "channel4_p2_ns": lambda: configs.channel(4, 2, "ns", eps=0.05),
+}
+
+
+def _both(name, prec="fp64"):
+    w = CASES[name]()
+    d = Discretisation(w)
+    u = C.perturbed(d, d.initial_state(w))
+    return w, d, u, C.solver_for(w, prec)
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_boundary_rhs_and_steps(name):
+    w, d, u, s = _both(name)
+    tol, ext, floor = C.floor_tolerance(d, u, 1e-12)
+    t = s.pack(u)
+    err = C.rel_l2(s.unpack(s.rhs(t)), ext)
+    dt = 0.2 * w.dt
+    s.step(t, dt, 10)
+    eu = C.rel_l2(s.unpack(t), d.rk4(u, dt, 10))
+    print(f"{name}: rhs rel L2 {err:.2e} (floor {floor:.2e}, tol {tol:.2e}), u(10) {eu:.2e}")
+    assert err < tol and eu < 1e-12
+
+
+@pytest.mark.parametrize("name", ["couette_mixed5_p2", "channel5_p3_euler"])
+def test_boundary_rhs_fp32(name):
+    w, d, u, s = _both(name, "fp32")
+    tol, ext, floor = C.floor_tolerance(d, u, 1e-5, C.FP32_OVER_FP64)
+    err = C.rel_l2(s.unpack(s.rhs(s.pack(u))), ext)
+    print(f"{name} fp32: rel L2 {err:.2e} (tol {tol:.2e})")
+    assert err < tol
+
+
+@pytest.mark.parametrize("variant", ["mfma", "sparse", "fused_fields", "staged_fused"])
+@pytest.mark.parametrize("name", ["couette_mixed5_p2", "couette_hex3_p2"])
+def test_boundary_every_kernel_variant(name, variant):
+    from test_gpu_parity import _force_plans
+    w, d, u, s = _both(name)
+    _force_plans(s, w, variant)
+    tol, ext, floor = C.floor_tolerance(d, u, 1e-12)
+    err = C.rel_l2(s.unpack(s.rhs(s.pack(u))), ext)
+    print(f"{name} {variant}: rel L2 {err:.2e} (tol {tol:.2e})")
+    assert err < tol
+
+
+def test_adjoint_refuses_boundaries():
+    import paper_1312_1638_amd as P
+    w, d, u, s = _both("couette_quad4_p3")
+    with pytest.raises(P.FRError) as e:
+        s.rhs_adjoint(s.pack(u), s.pack(u))
+    assert e.value.status == P.binding.FR_EUNSUPPORTED
+
+
+def _thin_couette(ny, p):
+    c = fields.COUETTE
+    m = meshes.quad_mesh(1, ny, lo=(0.0, 0.0), hi=(1.0 / ny, c["H"]), order=p, walls_y=True)
+    m.bcs = configs.couette_walls(c)
+    w = configs.couette(ny, p, start="constant")
+    w.mesh = m
+    return w
+
+
+def _sigma(s, t, w):
+    """L2 energy error against the analytic solution (quadrature W J)."""
+    total = 0.0
+    for b, ub in enumerate(s.unpack(t)):
+        x = s.solution_points(b)                       # (ne, Nu, D)
+        E = fields.couette(x)[..., -1].T               # (Nu, ne)
+        total += float(np.sum(s.quadrature(b) * (ub[:, -1] - E) ** 2))
+    return math.sqrt(total)
+
+
+def test_couette_marched_to_steady_state():
+    """The paper's protocol: from the constant start, march RK4 and evaluate
+    the L2 energy error every 0.1 time units until sigma(t)/sigma(t + 0.1)
+    <= 1.01; the converged error decreases at order >= p + 1/2 over channels 4
+    and 8 elements across (p = 2), and the marched state agrees with the
+    oracle's Newton steady state far below that error."""
+    from test_oracle_pins import _steady_state
+    p = 2
+    errs = []
+    for ny in (4, 8):
+        w = _thin_couette(ny, p)
+        s = C.solver_for(w)
+        t = s.pack([np.ascontiguousarray(np.transpose(w.ic(0, s.solution_points(0)), (1, 2, 0)))])
+        nper = int(round(0.1 / w.dt))
+        dt = 0.1 / nper
+        prev = _sigma(s, t, w)
+        tt = 0.0
+        while True:
+            s.step(t, dt, nper)
+            tt += 0.1
+            sig = _sigma(s, t, w)
+            if prev / sig <= 1.01 and sig / prev <= 1.01:
+                break
+            prev = sig
+            assert tt < 60.0, "no convergence"
+        d = Discretisation(w)
+        start = [np.ascontiguousarray(np.transpose(fields.couette(x), (1, 2, 0)))
+                 for x in d.solution_coords()]
+        un = _steady_state(d, start)
+        diff = C.rel_l2(s.unpack(t), un)
+        errs.append(sig)
+        print(f"ny={ny}: converged at t={tt:.1f}, sigma {sig:.3e}, marched vs Newton steady state "
+              f"rel L2 {diff:.2e}")
+        assert diff < 1e-6
+    rate = math.log2(errs[0] / errs[1])
+    print(f"order {rate:.2f}")
+    assert rate >= p + 0.5

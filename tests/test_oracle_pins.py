@@ -609,3 +609,125 @@ def _patch_elems(w, sample, rings):
         inside[pr["lelem"][t]] = True
         inside[pr["relem"][t]] = True
     return np.nonzero(inside)[0]
+
+
+# ---------------------------------------------------------------------------
+# Boundary conditions (Appendix C)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("etype,p", [("quad", 2), ("quad", 3), ("mixed", 2), ("mixed", 3),
+                                     ("hex", 2)])
+def test_couette_exact_state_residual_converges(etype, p):
+    """The exact Couette solution (paper section 5) is steady under the
+    Navier-Stokes equations with no-slip isothermal walls, so du/dt of its
+    interpolant must vanish as h -> 0 (rate about p on the finest pair).  A
+    wrong wall ghost leaves an O(1/h) residual at the walls."""
+    ns_ = (2, 4, 8) if etype != "hex" else (2, 4)
+    res = []
+    for n in ns_:
+        w = configs.couette(n, p, etype)
+        d = Discretisation(w)
+        r = d.rhs(d.initial_state(w))
+        res.append(max(float(np.abs(x).max()) for x in r))
+    rate = math.log2(res[-2] / res[-1])
+    print(etype, p, res, rate)
+    assert rate >= p - 0.5
+
+
+def test_walls_conserve_mass():
+    """Mass crosses no no-slip wall (the ghost mirrors the normal velocity and
+    keeps the density), so sum W J drho/dt vanishes for any state."""
+    w = configs.couette(4, 3, "mixed")
+    d = Discretisation(w)
+    u = d.initial_state(w)
+    rng = np.random.default_rng(2)
+    u = [x * (1 + 1e-2 * rng.standard_normal(x.shape)) for x in u]
+    r = d.rhs(u)
+    tot = sum(float(np.einsum("r,rn,rn->", rf.W, g.detJ.T, rb[:, 0])) for rf, g, rb in
+              zip(d.refs, d.geoms, r))
+    scale = sum(float(np.einsum("r,rn,rn->", rf.W, g.detJ.T, np.abs(rb[:, 0]))) for rf, g, rb in
+                zip(d.refs, d.geoms, r))
+    assert abs(tot) <= 1e-13 * scale
+
+
+@pytest.mark.parametrize("system", ["euler", "ns"])
+def test_inflow_outflow_free_stream(system):
+    """A uniform stream entering through the supersonic inflow (ghost = the
+    stream) and leaving through the subsonic outflow (ghost pressure = the
+    stream's) stays uniform: du/dt vanishes to round-off.  With a different
+    outflow pressure it does not."""
+    w = configs.channel(4, 3, system)
+    d = Discretisation(w)
+    u = d.initial_state(w)
+    r = d.rhs(u)
+    assert max(float(np.abs(x).max()) for x in r) < 1e-11
+    w.mesh.bcs = (w.mesh.bcs[0], dict(w.mesh.bcs[1], p=1.1 * w.mesh.bcs[1]["p"]))
+    r = Discretisation(w).rhs(u)
+    assert max(float(np.abs(x).max()) for x in r) > 1e-3
+
+
+def test_boundary_face_also_paired_is_rejected():
+    w = configs.couette(3, 2, "quad")
+    w.mesh.bcfaces = np.concatenate([w.mesh.bcfaces, w.mesh.bcfaces[:1]])   # listed twice
+    with pytest.raises(ValueError):
+        Discretisation(w)
+
+
+def _thin_couette(ny, p):
+    """Couette channel one element wide (periodic in x), ny elements across."""
+    c = fields.COUETTE
+    m = meshes.quad_mesh(1, ny, lo=(0.0, 0.0), hi=(1.0 / ny, c["H"]), order=p, walls_y=True)
+    m.bcs = configs.couette_walls(c)
+    w = configs.couette(2, p)
+    w.mesh = m
+    return w
+
+
+def _steady_state(d, u0, iters=8):
+    """Newton on R(u) = 0 with the Jacobian assembled column by column from
+    the oracle's exact complex-step JVPs (least squares: total mass is
+    conserved between no-slip walls, so J has a null direction)."""
+    from oracle import jvp
+    shapes = [x.shape for x in u0]
+    flat = lambda a: np.concatenate([x.ravel() for x in a])
+
+    def unflat(v):
+        out, o = [], 0
+        for sh in shapes:
+            k = int(np.prod(sh))
+            out.append(v[o:o + k].reshape(sh))
+            o += k
+        return out
+    u = flat(u0)
+    n = len(u)
+    for _ in range(iters):
+        R = flat(d.rhs(unflat(u)))
+        J = np.empty((n, n))
+        for k in range(n):
+            e = np.zeros(n)
+            e[k] = 1.0
+            J[:, k] = flat(jvp(d, unflat(u), unflat(e)))
+        du = np.linalg.lstsq(J, -R, rcond=1e-13)[0]
+        u = u + du
+        if np.abs(du).max() < 1e-13 * np.abs(u).max():
+            break
+    return unflat(u)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_couette_steady_state_converges_at_order_p_plus_1(p):
+    """The discrete steady state of the Couette problem (paper section 5:
+    no-slip isothermal walls, Rusanov and LDG with beta = 1/2, tau = 0.1)
+    converges to the analytic solution: the L2 energy error decreases at
+    rate >= p + 1/2 over channels 2, 4, 8 elements across (the paper reports
+    about p + 1)."""
+    errs = []
+    for ny in (2, 4, 8):
+        w = _thin_couette(ny, p)
+        d = Discretisation(w)
+        u = _steady_state(d, d.initial_state(w))
+        E = [fields.couette(x)[..., -1] for x in d.solution_coords()]
+        errs.append(math.sqrt(sum(float(np.einsum("r,rn,rn->", rf.W, g.detJ.T, (ub[:, -1] - Eb.T) ** 2))
+                                  for rf, g, ub, Eb in zip(d.refs, d.geoms, u, E))))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    print(p, errs, rates)
+    assert rates[-1] >= p + 0.5

@@ -160,6 +160,60 @@ def single_problem(batched, j):
     return w, where
 
 
+def couette_walls(c=fields.COUETTE):
+    """The two no-slip isothermal plates: boundary 0 at rest (y = 0), boundary
+    1 moving with v_w in x (y = H)."""
+    cptw = c["cp"] * c["Tw"]
+    return ({"type": "no-slip-isothermal-wall", "cp_tw": cptw, "vw": (0.0, 0.0, 0.0)},
+            {"type": "no-slip-isothermal-wall", "cp_tw": cptw, "vw": (c["vw"], 0.0, 0.0)})
+
+
+def couette(n=8, order=2, etype="quad", seed=0, nsteps=1000, dt=None, start="exact"):
+    """Couette flow (paper section 5) on [0, 1] x [0, H] (x [0, 1] in 3-D),
+    periodic in x (and z), walls at y = 0 and y = H.  etype: "quad", "mixed"
+    (random cells split into triangles, seed) or "hex".  start: "exact" (the
+    analytic solution) or "constant" (the paper's constant start)."""
+    c = fields.COUETTE
+    if etype == "quad":
+        m = meshes.quad_mesh(n, n, lo=(0.0, 0.0), hi=(1.0, c["H"]), order=order, walls_y=True)
+    elif etype == "mixed":
+        rng = np.random.default_rng(seed)
+        m = meshes.mixed_mesh(n, n, lo=(0.0, 0.0), hi=(1.0, c["H"]), order=order,
+                              split=rng.random(n * n) < 0.5, diag=rng.integers(0, 2, n * n),
+                              walls_y=True)
+    else:
+        m = meshes.hex_mesh(n, n, n, lo=(0.0, 0.0, 0.0), hi=(1.0, c["H"], 1.0), order=order,
+                            walls_y=True)
+    m.bcs = couette_walls(c)
+    h = c["H"] / n
+    if dt is None:
+        # acoustic bound of RK4 with margin: (|v| + c) (p + 1)^2 / h
+        dt = 0.5 * h / (420.0 * (order + 1) ** 2)
+    ic = fields.couette if start == "exact" else fields.couette_initial
+    return Workload(f"couette_{etype}{n}_p{order}", m, "ns", gamma=c["gamma"], mu=c["mu"],
+                    prandtl=c["prandtl"], dt=dt, nsteps=nsteps,
+                    ic=lambda b, x: ic(x), info=dict(exact=fields.couette, couette=c))
+
+
+def channel(n=6, order=3, system="euler", Ma=2.0, eps=0.0, seed=0, mu=0.01):
+    """A stream along x through [0, 2] x [0, 1]: supersonic inflow of the
+    stream at x = 0 (boundary 0), subsonic outflow at its pressure at x = 2
+    (boundary 1), periodic in y.  eps > 0 adds smooth random modes to the
+    initial state (the boundary data stay the unperturbed stream)."""
+    rho, p = 1.0, 1.0 / (1.4 * Ma * Ma)
+    m = meshes.quad_mesh(2 * n, n, lo=(0.0, 0.0), hi=(2.0, 1.0), order=order, open_x=(0, 1))
+    m.bcs = ({"type": "supersonic-inflow", "rho": rho, "v": (1.0, 0.0, 0.0), "p": p},
+             {"type": "subsonic-outflow", "p": p})
+    modes = fields.freestream_modes(2, seed, eps=eps) if eps > 0 else None
+
+    def ic(b, x):
+        if modes is None:
+            return fields.uniform(x, rho=rho, vel=(1.0, 0.0), p=p)
+        return fields.perturbed_freestream(x, modes, vel=(1.0, 0.0), Ma=Ma)
+    return Workload(f"channel{n}_p{order}_{system}", m, system, mu=mu if system == "ns" else 0.0,
+                    dt=1e-3, ic=ic)
+
+
 def adjoint_tgv(n=24, order=3, nsteps=200, dt=2e-4, ckpt=20):
     w = taylor_green_hexes(n=n, order=order, nsteps=nsteps, dt=dt)
     w.name = f"adjoint_tgv_hex{n}^3_p{order}"

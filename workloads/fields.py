@@ -98,3 +98,33 @@ def perturbed_freestream(x, modes, vel=(1.0, 0.5, 0.25), Ma=0.5, gamma=GAMMA,
     vel_ = np.stack(prim[1:1 + D], -1)
     p = prim[1 + D]
     return primitive_to_conserved(rho, vel_, p, gamma)
+
+
+# Couette flow between isothermal plates (paper section 5): the bottom plate
+# (y = 0) at rest, the top plate (y = H) moving with speed v_w in x.
+COUETTE = dict(gamma=1.4, prandtl=0.72, mu=0.417, cp=1005.0, H=1.0, Tw=300.0, pc=1.0e5,
+               vw=69.445)
+
+
+def couette_density(phi, c=COUETTE):
+    g = c["gamma"]
+    return g / (g - 1) * 2 * c["pc"] / (2 * c["cp"] * c["Tw"] + c["prandtl"] * c["vw"] ** 2
+                                        * phi * (1 - phi))
+
+
+def couette(x, c=COUETTE):
+    """The exact steady solution at points x (..., D), conserved variables."""
+    phi = x[..., 1] / c["H"]
+    rho = couette_density(phi, c)
+    vel = np.stack([c["vw"] * phi] + [np.zeros_like(phi)] * (x.shape[-1] - 1), -1)
+    return primitive_to_conserved(rho, vel, np.full_like(phi, c["pc"]), c["gamma"])
+
+
+def couette_initial(x, c=COUETTE):
+    """The paper's constant start: the mean density, v = v_w x, p = p_c."""
+    t, w = np.polynomial.legendre.leggauss(64)
+    rho_mean = 0.5 * np.sum(w * couette_density(0.5 * (t + 1), c))
+    shape = x.shape[:-1]
+    vel = np.stack([np.full(shape, c["vw"])] + [np.zeros(shape)] * (x.shape[-1] - 1), -1)
+    return primitive_to_conserved(np.full(shape, rho_mean), vel, np.full(shape, c["pc"]),
+                                  c["gamma"])

@@ -31,6 +31,11 @@ FACEPAIR_DTYPE = np.dtype([
     ("shift", np.float64, (3,)),
 ])
 
+# a face on the domain boundary and the boundary condition it carries
+# (index into Mesh.bcs)
+BCFACE_DTYPE = np.dtype([("block", np.int32), ("elem", np.int64), ("face", np.int32),
+                         ("bc", np.int32)])
+
 ETYPES = ("quad", "tri", "hex")
 ETYPE_CODE = {"quad": 0, "tri": 1, "hex": 2}
 ETYPE_NDIMS = {"quad": 2, "tri": 2, "hex": 3}
@@ -67,6 +72,8 @@ class Mesh:
     pairs: np.ndarray                  # FACEPAIR_DTYPE records
     nproblems: int = 1
     info: dict = field(default_factory=dict)
+    bcfaces: np.ndarray | None = None  # BCFACE_DTYPE records (boundary faces)
+    bcs: tuple = ()                    # boundary conditions: dicts with "type" and parameters
 
 
 def _pairs(records):
@@ -96,11 +103,15 @@ def _lattice(ng):
 # Structured periodic quadrilateral meshes
 # ---------------------------------------------------------------------------
 def quad_mesh(nx, ny, lo=(-5.0, -5.0), hi=(5.0, 5.0), order=3, geom_order=1,
-              mapping=None):
+              mapping=None, walls_y=False, open_x=None):
     """nx*ny periodic quads; element n = i + nx*j.
 
     ``mapping`` (optional) maps lattice points (..., 2) to physical points; it
     must leave the domain boundary fixed so periodic faces still match.
+    ``walls_y``: not periodic in y; the faces at y = lo carry boundary 0 and
+    those at y = hi boundary 1 (Mesh.bcfaces; the caller sets Mesh.bcs).
+    ``open_x`` = (left, right): not periodic in x; the faces at x = lo and
+    x = hi carry those boundary indices.
     """
     g = geom_order
     xs = np.linspace(lo[0], hi[0], nx + 1)
@@ -123,20 +134,39 @@ def quad_mesh(nx, ny, lo=(-5.0, -5.0), hi=(5.0, 5.0), order=3, geom_order=1,
     rx = (i + 1) % nx + nx * j
     shx = np.where(i == nx - 1, Lx, 0.0)
     px = _pairs_vec(0, n, 1, 0, rx, 3, np.stack([shx, 0 * shx], 1))
+    if open_x is not None:
+        px = px[i != nx - 1]
     ry = i + nx * ((j + 1) % ny)
     shy = np.where(j == ny - 1, Ly, 0.0)
     py = _pairs_vec(0, n, 2, 0, ry, 0, np.stack([0 * shy, shy], 1))
+    bcf = None
+    if walls_y:
+        py = py[j != ny - 1]
+        bot, top = n[j == 0], n[j == ny - 1]
+        bcf = np.zeros(len(bot) + len(top), dtype=BCFACE_DTYPE)
+        bcf["elem"] = np.concatenate([bot, top])
+        bcf["face"] = np.concatenate([np.zeros(len(bot)), np.full(len(top), 2)])
+        bcf["bc"] = np.concatenate([np.zeros(len(bot)), np.ones(len(top))])
+    if open_x is not None:
+        lft, rgt = n[i == 0], n[i == nx - 1]
+        bx = np.zeros(len(lft) + len(rgt), dtype=BCFACE_DTYPE)
+        bx["elem"] = np.concatenate([lft, rgt])
+        bx["face"] = np.concatenate([np.full(len(lft), 3), np.ones(len(rgt))])
+        bx["bc"] = np.concatenate([np.full(len(lft), open_x[0]), np.full(len(rgt), open_x[1])])
+        bcf = bx if bcf is None else np.concatenate([bcf, bx])
     blk = Block("quad", order, g, nodes)
     return Mesh(2, [blk], np.concatenate([px, py]),
-                info=dict(nx=nx, ny=ny, lo=lo, hi=hi, h=min(hx, hy)))
+                info=dict(nx=nx, ny=ny, lo=lo, hi=hi, h=min(hx, hy)), bcfaces=bcf)
 
 
 # ---------------------------------------------------------------------------
 # Structured periodic hexahedral meshes
 # ---------------------------------------------------------------------------
 def hex_mesh(nx, ny, nz, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), order=3,
-             geom_order=1, mapping=None):
-    """nx*ny*nz periodic hexes; element n = i + nx*(j + ny*k)."""
+             geom_order=1, mapping=None, walls_y=False):
+    """nx*ny*nz periodic hexes; element n = i + nx*(j + ny*k).  ``walls_y``:
+    not periodic in y, faces at y = lo carry boundary 0 and at y = hi
+    boundary 1."""
     g = geom_order
     xs = [np.linspace(lo[d], hi[d], m + 1) for d, m in enumerate((nx, ny, nz))]
     hs = [x[1] - x[0] for x in xs]
@@ -165,13 +195,22 @@ def hex_mesh(nx, ny, nz, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), order=3,
     pieces.append(_pairs_vec(0, n, 2, 0, idx((i3 + 1) % nx, j3, k3), 4, sh))
     # eta faces: 3 (eta=+1) <-> 1 (eta=-1)
     sh = np.stack([z, np.where(j3 == ny - 1, L[1], 0.0), z], 1)
-    pieces.append(_pairs_vec(0, n, 3, 0, idx(i3, (j3 + 1) % ny, k3), 1, sh))
+    py = _pairs_vec(0, n, 3, 0, idx(i3, (j3 + 1) % ny, k3), 1, sh)
+    bcf = None
+    if walls_y:
+        py = py[j3 != ny - 1]
+        bot, top = n[j3 == 0], n[j3 == ny - 1]
+        bcf = np.zeros(len(bot) + len(top), dtype=BCFACE_DTYPE)
+        bcf["elem"] = np.concatenate([bot, top])
+        bcf["face"] = np.concatenate([np.ones(len(bot)), np.full(len(top), 3)])
+        bcf["bc"] = np.concatenate([np.zeros(len(bot)), np.ones(len(top))])
+    pieces.append(py)
     # zeta faces: 5 (zeta=+1) <-> 0 (zeta=-1)
     sh = np.stack([z, z, np.where(k3 == nz - 1, L[2], 0.0)], 1)
     pieces.append(_pairs_vec(0, n, 5, 0, idx(i3, j3, (k3 + 1) % nz), 0, sh))
     blk = Block("hex", order, g, nodes)
     return Mesh(3, [blk], np.concatenate(pieces),
-                info=dict(n=(nx, ny, nz), lo=lo, hi=hi, h=min(hs)))
+                info=dict(n=(nx, ny, nz), lo=lo, hi=hi, h=min(hs)), bcfaces=bcf)
 
 
 def sine_perturbation(amp=0.1, period=1.0):
@@ -192,13 +231,14 @@ def sine_perturbation(amp=0.1, period=1.0):
 # Mixed quad/triangle meshes (quads split along a diagonal)
 # ---------------------------------------------------------------------------
 def mixed_quad_tri_mesh(nx, ny, lo=(-5.0, -5.0), hi=(5.0, 5.0), split=None,
-                        diag=None, qblock=0, tblock=1):
+                        diag=None, qblock=0, tblock=1, walls_y=False):
     """Periodic nx*ny grid; the cells flagged in ``split`` become two triangles.
 
     ``diag[c]`` = 0 splits cell c along B-C (from (x1,y0) to (x0,y1)), 1 along
     A-D.  Returns (quad_nodes, tri_nodes, pairs) as raw arrays so callers can
     assemble several problems into shared blocks; use :func:`mixed_mesh` for a
-    ready Mesh.
+    ready Mesh.  ``walls_y``: not periodic in y; a fourth value, the boundary
+    faces (bottom boundary 0, top boundary 1), is returned.
     """
     ncell = nx * ny
     if split is None:
@@ -236,15 +276,25 @@ def mixed_quad_tri_mesh(nx, ny, lo=(-5.0, -5.0), hi=(5.0, 5.0), split=None,
         cr = (i + 1) % nx + nx * j
         recs.append(owner[c][1] + owner[cr][3] + ((Lx if i == nx - 1 else 0.0, 0.0),))
         ct = i + nx * ((j + 1) % ny)
-        recs.append(owner[c][2] + owner[ct][0] + ((0.0, Ly if j == ny - 1 else 0.0),))
+        if not (walls_y and j == ny - 1):
+            recs.append(owner[c][2] + owner[ct][0] + ((0.0, Ly if j == ny - 1 else 0.0),))
     qn = np.array(quad_nodes, dtype=np.float64).reshape(-1, 4, 2)
     tn = np.array(tri_nodes, dtype=np.float64).reshape(-1, 3, 2)
-    return qn, tn, _pairs(recs)
+    if not walls_y:
+        return qn, tn, _pairs(recs)
+    faces = [owner[c][0] + (0,) for c in range(nx)] + \
+            [owner[c][2] + (1,) for c in range(nx * (ny - 1), nx * ny)]
+    bcf = np.zeros(len(faces), dtype=BCFACE_DTYPE)
+    for k, (b, e, f, bc) in enumerate(faces):
+        bcf[k] = (b, e, f, bc)
+    return qn, tn, _pairs(recs), bcf
 
 
 def mixed_mesh(nx, ny, lo=(-5.0, -5.0), hi=(5.0, 5.0), order=3, split=None,
-               diag=None):
-    qn, tn, pairs = mixed_quad_tri_mesh(nx, ny, lo, hi, split, diag)
+               diag=None, walls_y=False):
+    out = mixed_quad_tri_mesh(nx, ny, lo, hi, split, diag, walls_y=walls_y)
+    qn, tn, pairs = out[:3]
+    bcf = out[3] if walls_y else None
     blocks = [Block("quad", order, 1, qn), Block("tri", order, 1, tn)]
     if len(tn) == 0:
         blocks = blocks[:1]
@@ -253,7 +303,9 @@ def mixed_mesh(nx, ny, lo=(-5.0, -5.0), hi=(5.0, 5.0), order=3, split=None,
         pairs = pairs.copy()
         pairs["lblock"] = 0
         pairs["rblock"] = 0
+        if bcf is not None:
+            bcf["block"] = 0
         blocks = blocks[1:]
-    return Mesh(2, blocks, pairs,
+    return Mesh(2, blocks, pairs, bcfaces=bcf,
                 info=dict(nx=nx, ny=ny, lo=lo, hi=hi,
                           h=min((hi[0] - lo[0]) / nx, (hi[1] - lo[1]) / ny)))
