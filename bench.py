@@ -34,6 +34,9 @@ WORKLOADS = {
     "curved24": ("curved_freestream_hexes", dict(n=24, order=4), "euler"),
     "tgv24": ("taylor_green_hexes", dict(n=24, order=3), "ns"),
     "batched512": ("batched_vortices", dict(nproblems=512), "euler"),
+    # Couette channels between no-slip isothermal walls (boundary conditions)
+    "couette_mixed64": ("couette", dict(n=64, order=3, etype="mixed", start="constant"), "ns"),
+    "couette_hex32": ("couette", dict(n=32, order=3, etype="hex", start="constant"), "ns"),
 }
 
 STEP_NAMES = {1: "interp_M0", 2: "common_solution", 3: "grad_M6_M4p", 4: "grad_transform",
@@ -108,7 +111,13 @@ def make_solver(workload, prec, P, configs):
         s.nnz[b.etype, b.order] = {k: operator_nnz(P, b.etype, b.order, i)
                                    for k, i in (("M0", 0), ("M3", 1), ("M4p", 2), ("M6", 3),
                                                 ("M1p", 4))}
-    s.npairs = P.check_mesh(w.mesh, w.system)
+    # flux-point interfaces: face pairs, plus boundary faces (one side each)
+    nfp_face = {b: P.reference_operator(blk.etype, blk.order, 6).shape[0] //
+                {"quad": 4, "tri": 3, "hex": 6}[blk.etype] for b, blk in enumerate(w.mesh.blocks)}
+    s.npairs = int(sum(nfp_face[int(b)] for b in w.mesh.pairs["lblock"]))
+    bcf = getattr(w.mesh, "bcfaces", None)
+    if bcf is not None:
+        s.npairs += int(sum(nfp_face[int(b)] for b in bcf["block"]))
     # step 3 with the gradient transform (step 4) fused into its epilogue
     s.fused_gradt = [w.system == "ns" and s.gemm_plan(b, 3)[0] == 0 and s.gemm_plan(b, 3)[2] & 1
                      for b in range(len(w.mesh.blocks))]
