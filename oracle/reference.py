@@ -12,7 +12,12 @@ Everything is built in the most direct form the paper allows:
 * the DG correction functions (section 2, eq. corfn) through their defining
   property: the divergence of the correction field lies in the solution space
   and reproduces the face integral of the jump, i.e. mass-matrix lifting,
-  with every integral done by explicit quadrature.
+  with every integral done by explicit quadrature;
+* the SD and HU correction functions of the vortex super-accuracy test
+  (validation section), which the paper takes from the one-parameter
+  energy-stable family of Vincent, Castonguay and Jameson (VCJH): on tensor
+  elements the correction field of a flux point is the 1-D VCJH polynomial
+  along the face normal times the face Lagrange polynomial of that point.
 """
 from __future__ import annotations
 
@@ -175,11 +180,52 @@ def _tensor_weights(w1, dim):
     return np.prod(ws, axis=1)
 
 
-class RefElement:
-    """Points, basis and operator values of one (element type, order p)."""
+# ---------------------------------------------------------------------------
+# VCJH correction functions in one dimension
+# ---------------------------------------------------------------------------
+CORRECTIONS = ("dg", "sd", "hu")
 
-    def __init__(self, etype: str, p: int):
-        self.etype, self.p = etype, p
+
+def legendre_leading(p):
+    """Leading coefficient a_p = (2p)! / (2^p (p!)^2) of P_p."""
+    return math.factorial(2 * p) / (2 ** p * math.factorial(p) ** 2)
+
+
+def vcjh_c(scheme, p):
+    """The family parameter c of the named scheme: 0 for DG; the SD and HU
+    values of the VCJH family, with (a_p p!)^2 as their common scale."""
+    k = (legendre_leading(p) * math.factorial(p)) ** 2
+    if scheme == "dg":
+        return 0.0
+    if scheme == "sd":
+        return 2.0 * p / ((2 * p + 1) * (p + 1) * k)
+    if scheme == "hu":
+        return 2.0 * (p + 1) / ((2 * p + 1) * p * k)
+    raise ValueError(scheme)
+
+
+def vcjh_left(p, c):
+    """g_L of the VCJH family as a Legendre series: degree p + 1, g_L(-1) = 1,
+    g_L(1) = 0, (-1)^p/2 [P_p - (eta P_{p-1} + P_{p+1}) / (1 + eta)] with
+    eta = c (2p + 1) (a_p p!)^2 / 2.  The right function is g_L(-xi)."""
+    eta = c * (2 * p + 1) * (legendre_leading(p) * math.factorial(p)) ** 2 / 2
+    coef = np.zeros(p + 2)
+    coef[p] = 1.0
+    coef[p - 1] -= eta / (1 + eta)
+    coef[p + 1] -= 1.0 / (1 + eta)
+    return np.polynomial.legendre.Legendre(0.5 * (-1) ** p * coef)
+
+
+class RefElement:
+    """Points, basis and operator values of one (element type, order p,
+    correction scheme)."""
+
+    def __init__(self, etype: str, p: int, correction: str = "dg"):
+        if correction not in CORRECTIONS:
+            raise ValueError(correction)
+        if correction != "dg" and etype == "tri":
+            raise ValueError("SD and HU corrections are defined for tensor elements only")
+        self.etype, self.p, self.correction = etype, p, correction
         self.ndims = 3 if etype == "hex" else 2
         D = self.ndims
         xg, wg = gauss_legendre(p + 1)
@@ -216,6 +262,8 @@ class RefElement:
         self.D_u = np.transpose(g, (2, 0, 1))         # (D, Nu, Nu) [i, rho, nu]
         self._build_quadrature()
         self._build_lifting()
+        if correction != "dg":
+            self.divg = self.vcjh_divg(vcjh_c(correction, p))
 
     # -- basis -----------------------------------------------------------------
     def _init_tri_basis(self):
@@ -312,6 +360,36 @@ class RefElement:
         # face moments of a unit jump at sigma
         self.divg = np.linalg.solve(self.mass, lift)             # (Nu, Nf)
 
+    def vcjh_divg(self, c):
+        """(div g_sigma)(x_rho) for the VCJH member c on a tensor element.
+
+        A flux point sigma on the face with outward normal s e_i carries the
+        field g_sigma = s e_i h(xi_i) prod_{j != i} ell_j(xi_j), h = g_L for
+        s = -1 and g_L(-xi) for s = +1, ell_j the 1-D Lagrange polynomial
+        through the GL nodes that is one at sigma's j-th coordinate; so
+        n.g_sigma is one at sigma and zero at every other flux point, and
+        div g_sigma = s h'(xi_i) prod ell_j."""
+        gl = vcjh_left(self.p, c)
+        dgl = gl.deriv()
+        D = self.ndims
+        out = np.zeros((self.nupts, self.nfpts))
+        for sg in range(self.nfpts):
+            n = self.fnorm[sg]
+            i = int(np.argmax(np.abs(n)))
+            s = float(np.sign(n[i]))
+            xi = self.upts[:, i]
+            dh = dgl(xi) if s < 0 else -dgl(-xi)        # h'(xi_i)
+            val = s * dh
+            tang = np.ones(self.nupts)
+            for j in range(D):
+                if j == i:
+                    continue
+                lj = lagrange_1d(self.gl_nodes, self.upts[:, j])[0].astype(np.float64)
+                k = int(np.argmin(np.abs(self.gl_nodes - self.fpts[sg, j])))
+                tang = tang * lj[:, k]
+            out[:, sg] = val * tang
+        return out
+
 
 def _solve_ld(A, B):
     """Gaussian elimination with partial pivoting in long double."""
@@ -336,8 +414,8 @@ def _solve_ld(A, B):
 _CACHE = {}
 
 
-def ref_element(etype, p):
-    key = (etype, p)
+def ref_element(etype, p, correction="dg"):
+    key = (etype, p, correction)
     if key not in _CACHE:
-        _CACHE[key] = RefElement(etype, p)
+        _CACHE[key] = RefElement(etype, p, correction)
     return _CACHE[key]

@@ -48,7 +48,8 @@ class Discretisation:
         self.params = dict(system=w.system, gamma=w.gamma, mu=w.mu,
                            prandtl=w.prandtl, ldg_beta=w.ldg_beta,
                            ldg_tau=w.ldg_tau)
-        self.refs = [reference.ref_element(b.etype, b.order) for b in w.mesh.blocks]
+        self.refs = [reference.ref_element(b.etype, b.order, getattr(b, "correction", "dg"))
+                     for b in w.mesh.blocks]
         self.geoms = [geometry.BlockGeometry(r, b) for r, b in zip(self.refs, w.mesh.blocks)]
         for g in self.geoms:
             if np.any(g.detJ <= 0) or np.any(g.detJf <= 0):

@@ -139,6 +139,82 @@ def test_dg_correction_is_radau_derivative(p):
 
 
 # --------------------------------------------------------------------------
+# SD and HU correction functions (the VCJH family the super-accuracy test
+# cites): each member against an independent closed form, and the tensor
+# assembly against the DG lifting
+# --------------------------------------------------------------------------
+def _radau_right(k):
+    """Huynh's right Radau polynomial R_k = (-1)^k (P_k - P_{k-1}) / 2: degree
+    k, one at xi = -1, zero at xi = +1."""
+    L = np.polynomial.legendre.Legendre
+    return 0.5 * (-1) ** k * (L.basis(k) - L.basis(k - 1))
+
+
+@pytest.mark.parametrize("etype,p", [("quad", p) for p in range(1, 7)]
+                         + [("hex", p) for p in range(1, 5)])
+def test_vcjh_dg_member_is_the_lifting(etype, p):
+    """c = 0 through the tensor VCJH assembly equals the mass-matrix lifting
+    (two unrelated constructions of the DG correction)."""
+    r = reference.ref_element(etype, p)
+    assert np.max(np.abs(r.vcjh_divg(0.0) - r.divg)) < 1e-12 * np.max(np.abs(r.divg))
+
+
+@pytest.mark.parametrize("p", range(1, 7))
+def test_vcjh_members_closed_forms(p):
+    """DG is the right Radau polynomial R_{p+1}; SD is (1 - xi) P_p (-1)^p / 2,
+    i.e. zero at the p Gauss points, = (p R_p + (p + 1) R_{p+1})/(2p + 1);
+    HU is ((p + 1) R_p + p R_{p+1})/(2p + 1), flat at xi = +1."""
+    L = np.polynomial.legendre.Legendre
+    x = np.linspace(-1.0, 1.0, 41)
+    g = {k: reference.vcjh_left(p, reference.vcjh_c(k, p)) for k in ("dg", "sd", "hu")}
+    R0, R1 = _radau_right(p), _radau_right(p + 1)
+    sd = 0.5 * (-1) ** p * (1 - x) * L.basis(p)(x)
+    assert np.max(np.abs(g["dg"](x) - R1(x))) < 1e-14
+    assert np.max(np.abs(g["sd"](x) - sd)) < 1e-14
+    assert np.max(np.abs(g["sd"](x) - (p * R0(x) + (p + 1) * R1(x)) / (2 * p + 1))) < 1e-14
+    assert np.max(np.abs(g["hu"](x) - ((p + 1) * R0(x) + p * R1(x)) / (2 * p + 1))) < 1e-14
+    xg, _ = reference.gauss_legendre(p)
+    assert np.max(np.abs(g["sd"](xg))) < 1e-14
+    assert abs(g["hu"].deriv()(1.0)) < 1e-12
+    for k, gk in g.items():
+        assert gk.degree() == p + 1
+        assert abs(gk(-1.0) - 1.0) < 1e-14 and abs(gk(1.0)) < 1e-14
+        if k != "hu":
+            assert abs(gk.deriv()(1.0)) > 0.1
+
+
+@pytest.mark.parametrize("scheme", ["sd", "hu"])
+@pytest.mark.parametrize("etype,p", [("quad", 2), ("quad", 3), ("quad", 6), ("hex", 2),
+                                     ("hex", 4)])
+def test_vcjh_tensor_assembly(etype, p, scheme):
+    """div g_sigma of the SD and HU elements: zero off sigma's face-normal
+    line, the derivative of the Radau-combination form along it (sign by the
+    face's outward normal), and sum_rho W_rho div g_sigma(x_rho) = omega_sigma
+    (the face weight), which any correction must give."""
+    r = reference.ref_element(etype, p, scheme)
+    R0, R1 = _radau_right(p), _radau_right(p + 1)
+    a, b = (p, p + 1) if scheme == "sd" else (p + 1, p)
+    gl = (a * R0 + b * R1) / (2 * p + 1)
+    dgl = gl.deriv()
+    for sg in range(r.nfpts):
+        n = r.fnorm[sg]
+        i = int(np.argmax(np.abs(n)))
+        on = np.all(np.abs(np.delete(r.upts - r.fpts[sg], i, axis=1)) < 1e-12, axis=1)
+        assert on.sum() == p + 1
+        col = r.divg[:, sg]
+        assert np.max(np.abs(col[~on])) < 1e-13
+        xi = r.upts[on, i]
+        expect = -dgl(xi) if n[i] < 0 else -dgl(-xi)
+        assert np.max(np.abs(col[on] - expect)) < 1e-11 * np.max(np.abs(expect))
+    assert np.max(np.abs(r.W @ r.divg - r.fweight)) < 1e-12
+
+
+def test_vcjh_rejected_on_triangles():
+    with pytest.raises(ValueError):
+        reference.RefElement("tri", 3, "sd")
+
+
+# --------------------------------------------------------------------------
 # T-5 free-stream preservation and T-6 discrete conservation
 # --------------------------------------------------------------------------
 def _fs(d, vel):
@@ -175,9 +251,14 @@ def _general_curved_hexes(n, order):
 
 @pytest.mark.parametrize("case", ["quad", "tri_mixed", "hex", "hex_ns", "curved_quad_p2",
                                   "curved_hex_p4", "general_curved_hex_p4",
-                                  "general_curved_hex_p2"])
+                                  "general_curved_hex_p2", "curved_quad_p2_hu",
+                                  "general_curved_hex_p4_sd", "general_curved_hex_p4_hu"])
 def test_free_stream_preservation(case):
-    if case == "quad":
+    if case == "curved_quad_p2_hu":
+        w = configs.with_correction(_curved_quads(4, 2), "hu")
+    elif case in ("general_curved_hex_p4_sd", "general_curved_hex_p4_hu"):
+        w = configs.with_correction(_general_curved_hexes(4, 4), case[-2:])
+    elif case == "quad":
         w = configs.vortex_quads(5, 3)
     elif case == "tri_mixed":
         w = _mixed(5, 3)
@@ -210,10 +291,30 @@ def test_free_stream_negative_control():
     assert max(np.abs(x).max() for x in r) > 1e-6
 
 
-@pytest.mark.parametrize("case", ["vortex", "tgv", "mixed_euler", "mixed_ns", "curved"])
+def test_free_stream_sd_below_adjugate_degree():
+    """SD and HU have no quadrature weak form: on Q2 hexes with a general map
+    they preserve a uniform state only once the degree-4 adjugate terms are
+    interpolated exactly (p = 4, above); at p = 3 they do not, while DG does."""
+    for scheme, lo in (("sd", 1e-6), ("dg", None)):
+        d = Discretisation(configs.with_correction(_general_curved_hexes(4, 3), scheme))
+        r = max(np.abs(x).max() for x in d.rhs(_fs(d, (0.9, -0.4, 0.3))))
+        if lo is None:
+            assert r < 1e-11
+        else:
+            assert r > lo
+
+
+@pytest.mark.parametrize("case", ["vortex", "tgv", "mixed_euler", "mixed_ns", "curved",
+                                  "vortex_sd", "tgv_hu", "curved_sd"])
 def test_discrete_conservation(case):
     rng = np.random.default_rng(7)
-    if case == "vortex":
+    if case == "vortex_sd":
+        w = configs.with_correction(configs.vortex_quads(6, 3), "sd")
+    elif case == "tgv_hu":
+        w = configs.with_correction(configs.taylor_green_hexes(3, 3), "hu")
+    elif case == "curved_sd":
+        w = configs.with_correction(configs.curved_freestream_hexes(4, 4), "sd")
+    elif case == "vortex":
         w = configs.vortex_quads(6, 3)
     elif case == "tgv":
         w = configs.taylor_green_hexes(3, 3)
@@ -324,10 +425,12 @@ def _trunc_errors(make, ic, ns, box=None):
     return np.array(errs)
 
 
-def test_vortex_truncation_order():
+@pytest.mark.parametrize("scheme", ["dg", "sd", "hu"])
+def test_vortex_truncation_order(scheme):
     ic = lambda x: fields.isentropic_vortex(x)
     box = lambda x: (np.abs(x[..., 0]) <= 2) & (np.abs(x[..., 1]) <= 2)
-    e = _trunc_errors(lambda n: configs.vortex_quads(n, 3), ic, [10, 20, 40], box)
+    e = _trunc_errors(lambda n: configs.with_correction(configs.vortex_quads(n, 3), scheme),
+                      ic, [10, 20, 40], box)
     rates = np.log2(e[:-1] / e[1:])
     assert rates[-1] >= 2.8, (e, rates)
 

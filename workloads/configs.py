@@ -47,6 +47,41 @@ def vortex_quads(n=20, order=3, nsteps=100, dt=1e-3):
                     ic=lambda b, x: fields.isentropic_vortex(x))
 
 
+def with_correction(w, scheme):
+    """The same workload with every block on the named correction scheme
+    ("dg", "sd" or "hu"); the name gets the scheme as a suffix."""
+    for b in w.mesh.blocks:
+        b.correction = scheme
+    w.name = f"{w.name}_{scheme}"
+    return w
+
+
+# The vortex of the super-accuracy test (validation section): strength 13.5,
+# Mach 0.4, radius 1.5 on [-20, 20]^2 with p = 3 and RK4 steps of 0.00125.
+VORTEX_E1 = dict(S=13.5, M=0.4, R=1.5, L=40.0, order=3, dt=0.00125)
+VORTEX_E1_SPACINGS = {"1/3": 120, "2/7": 140, "1/4": 160, "2/9": 180}
+
+
+def vortex_superaccuracy(n=120, scheme="dg", order=3):
+    """The super-accuracy vortex on n x n quads over [-20, 20]^2 (h = 40/n:
+    n = 120, 140, 160, 180 give the spacings 1/3, 2/7, 1/4, 2/9), here with
+    the free stream along +x: periodic in x, so the vortex is back on the
+    origin every 40 time units, and the faces at y = +-20 held at the free
+    stream through a fixed ghost state (boundaries 0 and 1)."""
+    c = VORTEX_E1
+    h = c["L"] / 2
+    m = meshes.quad_mesh(n, n, (-h, -h), (h, h), order=order, walls_y=True)
+    pinf = 1.0 / (fields.GAMMA * c["M"] ** 2)
+    fixed = {"type": "supersonic-inflow", "rho": 1.0, "v": (1.0, 0.0, 0.0), "p": pinf}
+    m.bcs = (fixed, fixed)
+    for b in m.blocks:
+        b.correction = scheme
+    vortex = dict(S=c["S"], M=c["M"], R=c["R"])
+    return Workload(f"vortex_e1_quad{n}_p{order}_{scheme}", m, "euler", dt=c["dt"],
+                    ic=lambda b, x: fields.isentropic_vortex(x, **vortex),
+                    info=dict(vortex=vortex, period=c["L"]))
+
+
 def taylor_green_hexes(n=16, order=3, nsteps=100, dt=3e-4, Re=1600.0, Ma=0.1):
     """Navier-Stokes Taylor-Green vortex on periodic [0,2pi]^3, n^3 hexes."""
     L = 2.0 * np.pi

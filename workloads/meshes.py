@@ -59,6 +59,7 @@ class Block:
     geom_order: int
     nodes: np.ndarray                  # (nelem, nnodes, ndims) float64
     problem: np.ndarray | None = None  # (nelem,) int32 problem id, or None
+    correction: str = "dg"             # correction-function scheme: "dg", "sd" or "hu"
 
     @property
     def nelem(self) -> int:
