@@ -72,11 +72,19 @@ typedef struct {
                              fastest (memoised per shape in the process)       */
 } fr_config;
 
+/* Correction functions (section 2, eq. corfn).  DG is the mass-matrix
+ * lifting; SD and HU are the members of the VCJH energy-stable family that
+ * the super-accuracy test of the validation section compares with DG, built
+ * on quads and hexes only (tensor products of the 1-D functions along each
+ * face normal). */
+typedef enum { FR_CORR_DG = 0, FR_CORR_SD = 1, FR_CORR_HU = 2 } fr_correction;
+
 typedef struct {          /* one element block: one type, order, geometry order */
   int32_t etype;          /* fr_etype                                          */
   int32_t order;          /* solution order p: quad/tri 1..6, hex 1..4         */
   int32_t geom_order;     /* 1 (straight) or 2 (quadratic)                     */
-  int32_t reserved;
+  int32_t correction;     /* fr_correction; SD and HU on triangles give
+                             FR_EUNSUPPORTED, other values FR_EINVAL           */
   int64_t nelem;          /* >= 1                                              */
   const double *nodes;    /* HOST [nelem][nnodes][ndims]; nodes tensor-
                              lexicographic (xi fastest) on {-1,1} or {-1,0,1}
@@ -205,8 +213,8 @@ fr_status fr_integrate(fr_ctx *ctx, const double *u, int32_t kind, double *out,
                        void *hip_stream);
 
 /* Host-only diagnostics (no device use; callable without a GPU).
- * fr_reference_operator copies one reference-element array of (etype, p)
- * into HOST memory `out` (capacity `cap` doubles) and stores its shape in
+ * fr_reference_operator copies one reference-element array of (etype, p,
+ * fr_correction) into HOST memory `out` (capacity `cap` doubles) and stores its shape in
  * rows/cols.  which: 0 M0 (Nf x Nu), 1 M3 (Nu x Nf), 2 M4 - M6 M0
  * (D Nu x Nu), 3 M6 (D Nu x Nf), 4 M1 - M3 M2 (Nu x D Nu), 5 solution
  * points (Nu x D), 6 flux points (Nf x D), 7 reference normals (Nf x D),
@@ -216,8 +224,8 @@ fr_status fr_integrate(fr_ctx *ctx, const double *u, int32_t kind, double *out,
  * fr_check_mesh runs the host part of fr_setup_mesh (metric terms and flux
  * point pairing) and returns its status; npoint_pairs receives the number of
  * flux-point pairs. */
-fr_status fr_reference_operator(int32_t etype, int32_t order, int32_t which, double *out,
-                                int64_t cap, int32_t *rows, int32_t *cols);
+fr_status fr_reference_operator(int32_t etype, int32_t order, int32_t correction, int32_t which,
+                                double *out, int64_t cap, int32_t *rows, int32_t *cols);
 fr_status fr_check_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *blocks,
                         int64_t npairs, const fr_facepair *pairs, int64_t *npoint_pairs);
 

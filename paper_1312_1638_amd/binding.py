@@ -45,7 +45,7 @@ class FrConfig(ctypes.Structure):
 
 class FrBlock(ctypes.Structure):
     _fields_ = [("etype", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("geom_order", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("geom_order", ctypes.c_int32), ("correction", ctypes.c_int32),
                 ("nelem", ctypes.c_int64), ("nodes", ctypes.c_void_p),
                 ("problem", ctypes.c_void_p)]
 
@@ -57,6 +57,7 @@ BC_C = np.dtype([("type", "<i4"), ("reserved", "<i4"), ("rho", "<f8"), ("v", "<f
 BCFACE_C = np.dtype([("block", "<i4"), ("face", "<i4"), ("elem", "<i8"), ("bc", "<i4"),
                      ("reserved", "<i4")], align=True)
 BCTYPE = {"supersonic-inflow": 0, "subsonic-outflow": 1, "no-slip-isothermal-wall": 2}
+CORRECTION = {"dg": 0, "sd": 1, "hu": 2}      # fr_correction
 
 FACEPAIR_C = np.dtype([("lblock", "<i4"), ("lface", "<i4"), ("lelem", "<i8"),
                        ("rblock", "<i4"), ("rface", "<i4"), ("relem", "<i8"),
@@ -92,7 +93,7 @@ def load_library(path: str = LIB_PATH):
         "fr_stash_len": [vp, ctypes.POINTER(i64)],
         "fr_rk_step_stash": [vp, dp, dp, dp, vp],
         "fr_rk_step_adjoint_stash": [vp, dp, dp, dp, dp, vp],
-        "fr_reference_operator": [i32, i32, i32, dp, i64, ctypes.POINTER(i32),
+        "fr_reference_operator": [i32, i32, i32, i32, dp, i64, ctypes.POINTER(i32),
                                   ctypes.POINTER(i32)],
         "fr_check_mesh": [ctypes.POINTER(FrConfig), i32, ctypes.POINTER(FrBlock), i64, vp,
                           ctypes.POINTER(i64)],
@@ -125,14 +126,15 @@ def _check(st, ctx=None):
         raise FRError(st, msg)
 
 
-def reference_operator(etype: str, order: int, which: int) -> np.ndarray:
+def reference_operator(etype: str, order: int, which: int, correction: str = "dg") -> np.ndarray:
     """Host-side reference operator of the library (no device needed)."""
     L = load_library()
     r, c = ctypes.c_int32(), ctypes.c_int32()
-    _check(L.fr_reference_operator(ETYPE[etype], order, which, None, 0, ctypes.byref(r),
+    k = CORRECTION[correction]
+    _check(L.fr_reference_operator(ETYPE[etype], order, k, which, None, 0, ctypes.byref(r),
                                    ctypes.byref(c)))
     out = np.empty((r.value, c.value))
-    _check(L.fr_reference_operator(ETYPE[etype], order, which, out.ctypes.data, out.size,
+    _check(L.fr_reference_operator(ETYPE[etype], order, k, which, out.ctypes.data, out.size,
                                    ctypes.byref(r), ctypes.byref(c)))
     return out
 
@@ -190,7 +192,8 @@ def _marshal_mesh(mesh):
         if b.problem is not None:
             prob = np.ascontiguousarray(b.problem, dtype=np.int32)
             keep.append(prob)
-        arr[i] = FrBlock(ETYPE[b.etype], b.order, b.geom_order, 0, b.nelem, nodes.ctypes.data,
+        corr = CORRECTION[getattr(b, "correction", "dg")]
+        arr[i] = FrBlock(ETYPE[b.etype], b.order, b.geom_order, corr, b.nelem, nodes.ctypes.data,
                          prob.ctypes.data if prob is not None else None)
     src = mesh.pairs
     pairs = np.zeros(len(src), dtype=FACEPAIR_C)

@@ -972,7 +972,7 @@ fr_status fr_setup_mesh_bc(const fr_config *cfg, int32_t nblocks, const fr_block
   hipStream_t s = (hipStream_t)hip_stream;
   const int D = c->D, NV = c->NV;
   try {
-    std::map<std::pair<int, int>, int> refmap;
+    std::map<std::tuple<int, int, int>, int> refmap;
     std::vector<fr::BlockGeom> geoms;
     std::vector<int> block_ref;
     int64_t uoff = 0, ufoff = 0, qfoff = 0, ftoff = 0, poff = 0;
@@ -981,10 +981,10 @@ fr_status fr_setup_mesh_bc(const fr_config *cfg, int32_t nblocks, const fr_block
       if (B.nelem < 1 || !B.nodes) throw Fail{FR_EINVAL, "block without elements or nodes"};
       if ((B.etype == FR_HEX) != (D == 3) || B.etype < 0 || B.etype > 2)
         throw Fail{FR_EINVAL, "element type does not match ndims"};
-      auto key = std::make_pair(B.etype, B.order);
+      auto key = std::make_tuple(B.etype, B.order, B.correction);
       if (!refmap.count(key)) {
         refmap[key] = (int)c->refs.size();
-        c->refs.push_back(fr::build_ref(B.etype, B.order));
+        c->refs.push_back(fr::build_ref(B.etype, B.order, B.correction));
       }
       BlockRT rt;
       rt.ref = refmap[key];
@@ -1306,10 +1306,10 @@ fr_status fr_integrate(fr_ctx *c, const double *u, int32_t kind, double *out, vo
   return FR_OK;
 }
 
-fr_status fr_reference_operator(int32_t etype, int32_t order, int32_t which, double *out,
-                                int64_t cap, int32_t *rows, int32_t *cols) {
+fr_status fr_reference_operator(int32_t etype, int32_t order, int32_t correction, int32_t which,
+                                double *out, int64_t cap, int32_t *rows, int32_t *cols) {
   try {
-    fr::RefOps R = fr::build_ref(etype, order);
+    fr::RefOps R = fr::build_ref(etype, order, correction);
     const int D = R.ndims, Nu = R.nupts, Nf = R.nfpts;
     const std::vector<double> *v = nullptr;
     int r = 0, cc = 0;
@@ -1347,7 +1347,7 @@ fr_status fr_check_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *b
   if (D != 2 && D != 3) return fail(nullptr, FR_EINVAL, "ndims must be 2 or 3");
   try {
     std::vector<fr::RefOps> refs;
-    std::map<std::pair<int, int>, int> refmap;
+    std::map<std::tuple<int, int, int>, int> refmap;
     std::vector<fr::BlockGeom> geoms;
     std::vector<int> block_ref;
     for (int bi = 0; bi < nblocks; ++bi) {
@@ -1355,8 +1355,11 @@ fr_status fr_check_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *b
       if (B.nelem < 1 || !B.nodes) return fail(nullptr, FR_EINVAL, "block without elements");
       if ((B.etype == FR_HEX) != (D == 3) || B.etype < 0 || B.etype > 2)
         return fail(nullptr, FR_EINVAL, "element type does not match ndims");
-      auto key = std::make_pair(B.etype, B.order);
-      if (!refmap.count(key)) { refmap[key] = (int)refs.size(); refs.push_back(fr::build_ref(B.etype, B.order)); }
+      auto key = std::make_tuple(B.etype, B.order, B.correction);
+      if (!refmap.count(key)) {
+        refmap[key] = (int)refs.size();
+        refs.push_back(fr::build_ref(B.etype, B.order, B.correction));
+      }
       block_ref.push_back(refmap[key]);
       geoms.push_back(fr::build_geom(refs[refmap[key]], B.geom_order, B.nelem, B.nodes,
                                      round_up(B.nelem, 16)));

@@ -263,12 +263,48 @@ static void face_point(int etype, int f, const double *t, double *x, double *nrm
   }
 }
 
-RefOps build_ref(int etype, int p) {
+// ---------------------------------------------------------------------------
+// The VCJH family of correction functions (Vincent, Castonguay and Jameson's
+// energy-stable FR schemes, which the paper cites for its DG, SD and HU
+// runs).  In one dimension the left correction is
+//   g_L = (-1)^p / 2 [P_p - (eta P_{p-1} + P_{p+1}) / (1 + eta)],
+//   eta = c (2p + 1) (a_p p!)^2 / 2,  a_p p! = (2p)! / (2^p p!) = (2p - 1)!!,
+// with g_L(-1) = 1, g_L(1) = 0, and the right one g_R(xi) = g_L(-xi).
+// c = 0 is DG (the right Radau polynomial); SD and HU are
+//   c_SD = 2p / ((2p + 1)(p + 1)(a_p p!)^2),  c_HU = 2(p + 1) / ((2p + 1) p (a_p p!)^2).
+// ---------------------------------------------------------------------------
+static ld_t vcjh_eta(int corr, int p) {
+  ld_t k = 1;  // (2p - 1)!!
+  for (int j = 1; j <= p; ++j) k *= 2 * j - 1;
+  const ld_t scale = k * k;
+  ld_t c = 0;
+  if (corr == CORR_SD) c = (ld_t)(2 * p) / ((2 * p + 1) * (ld_t)(p + 1) * scale);
+  if (corr == CORR_HU) c = (ld_t)(2 * (p + 1)) / ((2 * p + 1) * (ld_t)p * scale);
+  return c * (2 * p + 1) * scale / 2;
+}
+
+// d g_L / d xi at x; P_k' from P_{k+1}' = P_{k-1}' + (2k + 1) P_k.
+static ld_t vcjh_left_deriv(int p, ld_t eta, ld_t x) {
+  std::vector<ld_t> P(p + 2), dP(p + 2);
+  P[0] = 1; dP[0] = 0;
+  P[1] = x; dP[1] = 1;
+  for (int k = 1; k <= p; ++k) {
+    P[k + 1] = ((2 * k + 1) * x * P[k] - k * P[k - 1]) / (k + 1);
+    dP[k + 1] = dP[k - 1] + (2 * k + 1) * P[k];
+  }
+  const ld_t sg = (p % 2) ? -0.5L : 0.5L;
+  return sg * (dP[p] - (eta * dP[p - 1] + dP[p + 1]) / (1 + eta));
+}
+
+RefOps build_ref(int etype, int p, int corr) {
   if (etype < 0 || etype > 2) throw SetupError(1, "bad element type");
   int pmax = etype == ET_HEX ? 4 : 6;
   if (p < 1 || p > pmax) throw SetupError(3, "unsupported order " + std::to_string(p));
+  if (corr < CORR_DG || corr > CORR_HU) throw SetupError(1, "bad correction scheme");
+  if (corr != CORR_DG && etype == ET_TRI)
+    throw SetupError(3, "SD and HU correction functions are built for quads and hexes only");
   RefOps R;
-  R.etype = etype; R.p = p;
+  R.etype = etype; R.p = p; R.corr = corr;
   const int D = R.ndims = etype == ET_HEX ? 3 : 2;
   const int n1 = p + 1;
   std::vector<double> xg, wg;
@@ -337,6 +373,27 @@ RefOps build_ref(int etype, int p) {
       for (int k = 0; k < Nu; ++k) acc += psu[r * Nu + k] * psf[s * Nu + k];
       R.M3[(size_t)r * Nf + s] = (double)(acc * R.fweight[s]);
     }
+  // SD / HU on tensor elements: g_sigma = n~_sigma h(xi_i) ell_sigma(xi_tangent)
+  // with the face normal n~_sigma = s e_i, h = g_L (s = -1) or g_R (s = +1)
+  // and ell_sigma the face Lagrange polynomial that is one at sigma.  At the
+  // GL solution points ell_sigma is one on sigma's face-normal line and zero
+  // elsewhere, so div g_sigma(x_rho) = -g_L'(-s xi_i(rho)) on that line.
+  if (corr != CORR_DG) {
+    const ld_t eta = vcjh_eta(corr, p);
+    for (int s = 0; s < Nf; ++s) {
+      int i = 0;
+      for (int d = 1; d < D; ++d)
+        if (std::fabs(R.fnorm[s * D + d]) > std::fabs(R.fnorm[s * D + i])) i = d;
+      const double sg = R.fnorm[s * D + i];
+      for (int r = 0; r < Nu; ++r) {
+        bool on = true;
+        for (int d = 0; d < D; ++d)
+          if (d != i && std::fabs(R.upts[r * D + d] - R.fpts[s * D + d]) > 1e-9) on = false;
+        R.M3[(size_t)r * Nf + s] =
+            on ? (double)-vcjh_left_deriv(p, eta, -(ld_t)sg * R.upts[r * D + i]) : 0.0;
+      }
+    }
+  }
   // M6[i Nu + rho][sigma] = n~_sigma,i M3[rho][sigma];  M2[sigma][i Nu + rho] = n~_sigma,i M0
   R.M6.assign((size_t)D * Nu * Nf, 0);
   R.M2.assign((size_t)Nf * D * Nu, 0);

@@ -18,11 +18,13 @@ struct SetupError : std::runtime_error {
 };
 
 enum { ET_QUAD = 0, ET_TRI = 1, ET_HEX = 2 };
+// Correction-function schemes (members of the VCJH family): DG, SD, HU.
+enum { CORR_DG = 0, CORR_SD = 1, CORR_HU = 2 };
 
 // Reference element of one (type, order): points and the Appendix A
 // operators, all row-major.
 struct RefOps {
-  int etype = 0, p = 0, ndims = 0, nupts = 0, nfpts = 0, nfaces = 0, nfp_face = 0;
+  int etype = 0, p = 0, corr = CORR_DG, ndims = 0, nupts = 0, nfpts = 0, nfaces = 0, nfp_face = 0;
   std::vector<double> upts, fpts, fnorm;   // [n][ndims]
   std::vector<int> fface;                  // face of each flux point
   std::vector<double> fweight;             // omega_sigma: face quadrature weight
@@ -36,7 +38,9 @@ struct RefOps {
   std::vector<double> M1, M2, M4;          // kept for tests of the identities
 };
 
-RefOps build_ref(int etype, int p);
+// corr: CORR_DG for every element type; CORR_SD and CORR_HU for quads and
+// hexes only (SetupError status 3 otherwise).
+RefOps build_ref(int etype, int p, int corr = CORR_DG);
 
 // Metric terms of one element block, device layout ([component][rho][ld]).
 struct BlockGeom {

@@ -51,13 +51,42 @@ def test_operators_match_oracle(etype, p):
     assert np.allclose(P.reference_operator(etype, p, 9)[:, 0], r.fweight, atol=1e-14)
 
 
+@pytest.mark.parametrize("scheme", ["sd", "hu"])
+@pytest.mark.parametrize("etype,p", [("quad", p) for p in range(1, 7)]
+                         + [("hex", p) for p in range(1, 5)])
+def test_sd_hu_correction_matches_oracle(etype, p, scheme):
+    """The library's SD/HU correction divergence (VCJH closed form through
+    the Legendre recurrences) against the oracle's (Legendre series and
+    Lagrange factors); the other operators are those of DG."""
+    _lib()
+    r = oref.ref_element(etype, p, scheme)
+    M3 = P.reference_operator(etype, p, 1, scheme)
+    assert np.max(np.abs(M3 - r.divg)) < 1e-13 * max(1.0, np.max(np.abs(r.divg)))
+    assert np.allclose(P.reference_operator(etype, p, 0, scheme), P.reference_operator(etype, p, 0))
+    assert np.allclose(P.reference_operator(etype, p, 10, scheme),
+                       P.reference_operator(etype, p, 10))
+
+
+def test_sd_hu_rejected_on_triangles():
+    _lib()
+    with pytest.raises(P.FRError) as e:
+        P.reference_operator("tri", 3, 1, "sd")
+    assert e.value.status == P.binding.FR_EUNSUPPORTED
+    L = P.binding.load_library()
+    import ctypes
+    assert L.fr_reference_operator(0, 3, 7, 1, None, 0, None, None) == P.binding.FR_EINVAL
+
+
+@pytest.mark.parametrize("scheme", ["dg", "sd", "hu"])
 @pytest.mark.parametrize("etype,p", [("quad", 3), ("tri", 3), ("hex", 3), ("hex", 4)])
-def test_premultiplied_operators_reproduce_direct_form(etype, p):
+def test_premultiplied_operators_reproduce_direct_form(etype, p, scheme):
     """Appendix A: M6 C + (M4 - M6 M0) U equals the direct transformed
     gradient (eq. transqu) and M3 D + (M1 - M3 M2) F the direct divergence
     (eq. tdivflux), on random data, with the oracle's operator values."""
+    if etype == "tri" and scheme != "dg":
+        pytest.skip("SD and HU are built for tensor elements only")
     _lib()
-    r = oref.ref_element(etype, p)
+    r = oref.ref_element(etype, p, scheme)
     D, Nu, Nf = r.ndims, r.nupts, r.nfpts
     rng = np.random.default_rng(p)
     m = 7
@@ -65,10 +94,10 @@ def test_premultiplied_operators_reproduce_direct_form(etype, p):
     C = rng.standard_normal((Nf, m))
     Fd = rng.standard_normal((Nf, m))
     Ft = rng.standard_normal((D, Nu, m))
-    M6 = P.reference_operator(etype, p, 3)
-    M4p = P.reference_operator(etype, p, 2)
-    M3 = P.reference_operator(etype, p, 1)
-    M1p = P.reference_operator(etype, p, 4)
+    M6 = P.reference_operator(etype, p, 3, scheme)
+    M4p = P.reference_operator(etype, p, 2, scheme)
+    M3 = P.reference_operator(etype, p, 1, scheme)
+    M1p = P.reference_operator(etype, p, 4, scheme)
     lib_q = (M6 @ C + M4p @ U).reshape(D, Nu, m)
     uf = r.L_f @ U
     direct_q = np.einsum("irv,vm->irm", r.D_u, U) + np.einsum("rs,si,sm->irm", r.divg, r.fnorm, C - uf)
