@@ -37,6 +37,11 @@ WORKLOADS = {
     # Couette channels between no-slip isothermal walls (boundary conditions)
     "couette_mixed64": ("couette", dict(n=64, order=3, etype="mixed", start="constant"), "ns"),
     "couette_hex32": ("couette", dict(n=32, order=3, etype="hex", start="constant"), "ns"),
+    # the super-accuracy vortex on its finest mesh (h = 2/9, p = 3) with each
+    # correction scheme: same kernels, different operator values
+    "vortex_e1_dg": ("vortex_superaccuracy", dict(n=180, scheme="dg"), "euler"),
+    "vortex_e1_sd": ("vortex_superaccuracy", dict(n=180, scheme="sd"), "euler"),
+    "vortex_e1_hu": ("vortex_superaccuracy", dict(n=180, scheme="hu"), "euler"),
 }
 
 STEP_NAMES = {1: "interp_M0", 2: "common_solution", 3: "grad_M6_M4p", 4: "grad_transform",
@@ -47,11 +52,11 @@ PEAK_MFMA = {"fp64": 78.6e12, "fp32": 157.3e12}             # dense FLOP/s
 ROCPROF_TRAFFIC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "hbm_traffic.md")
 
 
-def operator_nnz(P, etype, order, which):
+def operator_nnz(P, etype, order, which, correction="dg"):
     """Structural non-zeros of a reference operator (entries above 1e-13 of
     their row's largest magnitude; the rest is rounding residue)."""
     import numpy as np
-    A = P.reference_operator(etype, order, which)
+    A = P.reference_operator(etype, order, which, correction)
     mx = np.abs(A).max(axis=1, keepdims=True)
     return int((np.abs(A) > 1e-13 * mx).sum())
 
@@ -108,7 +113,7 @@ def make_solver(workload, prec, P, configs):
     s.nfpts, s.nnz = {}, {}
     for b in w.mesh.blocks:
         s.nfpts[b.etype, b.order] = P.reference_operator(b.etype, b.order, 6).shape[0]
-        s.nnz[b.etype, b.order] = {k: operator_nnz(P, b.etype, b.order, i)
+        s.nnz[b.etype, b.order] = {k: operator_nnz(P, b.etype, b.order, i, b.correction)
                                    for k, i in (("M0", 0), ("M3", 1), ("M4p", 2), ("M6", 3),
                                                 ("M1p", 4))}
     # flux-point interfaces: face pairs, plus boundary faces (one side each)
