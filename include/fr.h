@@ -180,6 +180,37 @@ fr_status fr_rhs(fr_ctx *ctx, const double *u, double *dudt, void *hip_stream);
 fr_status fr_rk_step(fr_ctx *ctx, double *u, const double *dt_dev, int32_t nsteps,
                      void *hip_stream);
 
+/* The other time steppers of the paper's functionality table (Table 1 of
+ * the implementation section): forward Euler and adaptive DOPRI5.
+ *
+ * fr_euler_step: nsteps steps u <- u + dt R(u) in place, dt_dev as for
+ * fr_rk_step (one captured graph per step).
+ *
+ * fr_dopri5_step: `nattempts` attempts of the Dormand-Prince 5(4) pair in
+ * place on u, each problem on its own.  All step-size state is DEVICE
+ * float64 memory of [nproblems] entries, read and updated by the kernels
+ * (no host synchronisation; attempts replay one captured graph):
+ *   t      time of each problem, advanced by accepted steps;
+ *   dt     the next step to try; replaced by the controller's proposal;
+ *   tend   NULL, or end times: steps are cut to reach them exactly and a
+ *          problem at its end time stands still (dt <= 0 also stands still);
+ *   counts NULL, or DEVICE int32 [nproblems][2]: accepted and rejected
+ *          attempts are added to it.
+ * The error of an attempt is the RMS over the problem's degrees of freedom
+ * of e_i / (atol + rtol max(|u_i|, |u5_i|)), e = h sum (b_j - bhat_j) k_j;
+ * the step is accepted when it is below 1.  The next step is h min(10,
+ * 0.9 err^-1/5) after an acceptance (10 when err = 0; at most h when the same
+ * step had a rejection) and h max(0.2, 0.9 err^-1/5) after a rejection.  The
+ * rejection flag of each problem lives in the context between calls, so a
+ * step may span calls.  Each call evaluates R(u) once before its attempts
+ * (the first stage), then six right-hand sides per attempt.  atol, rtol > 0
+ * and finite, else FR_EINVAL. */
+fr_status fr_euler_step(fr_ctx *ctx, double *u, const double *dt_dev, int32_t nsteps,
+                        void *hip_stream);
+fr_status fr_dopri5_step(fr_ctx *ctx, double *u, double *t, double *dt, const double *tend,
+                         int32_t nattempts, double atol, double rtol, int32_t *counts,
+                         void *hip_stream);
+
 /* Vector-Jacobian product of the right-hand side: ulam = (dR/du)(u)^T lam.
  * ulam must not alias u or lam. */
 fr_status fr_rhs_adjoint(fr_ctx *ctx, const double *u, const double *lam, double *ulam,

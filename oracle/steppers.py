@@ -111,11 +111,17 @@ class Dopri5:
         u5 = y                                     # stage 7 is taken at the new state
         e_w = [float(bb - bh) for bb, bh in zip(DP_B, DP_BHAT)]
         ssq = np.zeros(self.nprob)
+        msq = np.zeros(self.nprob)          # diagnostics only: the same norm of sum |E_j k_j|
         for b, ub in enumerate(u):
             e = self._per_elem(h, b) * sum(e_w[j] * k[j][b] for j in range(7))
             sc = self.atol + self.rtol * np.maximum(np.abs(ub), np.abs(u5[b]))
             np.add.at(ssq, self.prob[b], np.sum((e / sc) ** 2, axis=(0, 1)))
+            m = self._per_elem(h, b) * sum(abs(e_w[j]) * np.abs(k[j][b]) for j in range(7))
+            np.add.at(msq, self.prob[b], np.sum((m / sc) ** 2, axis=(0, 1)))
         err = np.sqrt(ssq / self.ndof)
+        # amplification of relative perturbations of the slopes into err
+        with np.errstate(divide="ignore", invalid="ignore"):
+            cond = np.sqrt(msq / self.ndof) / err
         active = h > 0
         accept = active & (err < 1.0)
         reject = active & ~accept
@@ -128,7 +134,8 @@ class Dopri5:
         t_new = self.t + h
         if self.tend is not None:
             t_new = np.where(h >= self.tend - self.t, self.tend, t_new)
-        self.log.append(dict(h=h.copy(), err=err, accept=accept.copy(), reject=reject.copy()))
+        self.log.append(dict(h=h.copy(), err=err, cond=cond, accept=accept.copy(),
+                             reject=reject.copy()))
         self.t = np.where(accept, t_new, self.t)
         self.h = np.where(accept, h * grow, np.where(reject, h * shrink, h))
         self.rejected = np.where(accept, False, np.where(reject, True, self.rejected))

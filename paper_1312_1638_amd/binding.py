@@ -22,7 +22,7 @@ SYSTEM = {"euler": 0, "ns": 1}
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 EXPORTS = ("fr_setup_mesh", "fr_setup_mesh_bc", "fr_get_layout", "fr_get_solution_points", "fr_get_quadrature",
-           "fr_rhs", "fr_rk_step", "fr_rhs_adjoint", "fr_rk_step_adjoint", "fr_integrate",
+           "fr_rhs", "fr_rk_step", "fr_euler_step", "fr_dopri5_step", "fr_rhs_adjoint", "fr_rk_step_adjoint", "fr_integrate",
            "fr_reference_operator", "fr_check_mesh", "fr_debug_stage", "fr_debug_scratch_len", "fr_bench_step",
            "fr_debug_gemm", "fr_measure_ceiling", "fr_bench_gemm", "fr_get_gemm_plan", "fr_integrate_grad", "fr_stash_len", "fr_rk_step_stash",
            "fr_rk_step_adjoint_stash", "fr_debug_set_plan",
@@ -86,6 +86,8 @@ def load_library(path: str = LIB_PATH):
         "fr_get_quadrature": [vp, i32, dp],
         "fr_rhs": [vp, dp, dp, vp],
         "fr_rk_step": [vp, dp, dp, i32, vp],
+        "fr_euler_step": [vp, dp, dp, i32, vp],
+        "fr_dopri5_step": [vp, dp, dp, dp, dp, i32, ctypes.c_double, ctypes.c_double, vp, vp],
         "fr_rhs_adjoint": [vp, dp, dp, dp, vp],
         "fr_rk_step_adjoint": [vp, dp, dp, dp, dp, vp],
         "fr_integrate": [vp, dp, i32, dp, vp],
@@ -345,6 +347,32 @@ class Solver:
         assert d.dtype == self.torch.float64 and d.is_cuda and d.numel() >= self.nproblems
         _check(self.L.fr_rk_step(self.ctx, self._ptr(u), d.data_ptr(), nsteps, self._stream()),
                self.ctx)
+        return u
+
+    def euler_step(self, u, dt, nsteps=1):
+        """nsteps forward Euler steps in place on u (dt as for step)."""
+        d = self.dt_tensor(dt)
+        assert d.dtype == self.torch.float64 and d.is_cuda and d.numel() >= self.nproblems
+        _check(self.L.fr_euler_step(self.ctx, self._ptr(u), d.data_ptr(), nsteps, self._stream()),
+               self.ctx)
+        return u
+
+    def dopri5(self, u, t, dt, nattempts, atol, rtol, tend=None, counts=None):
+        """nattempts adaptive DOPRI5 attempts in place on u.  t, dt (and tend):
+        device float64 tensors [nproblems], updated in place; counts: device
+        int32 [nproblems, 2] (accepted, rejected attempts added) or None."""
+        T = self.torch
+        for a in (t, dt) + ((tend,) if tend is not None else ()):
+            assert a.dtype == T.float64 and a.is_cuda and a.is_contiguous()
+            assert a.numel() >= self.nproblems
+        if counts is not None:
+            assert counts.dtype == T.int32 and counts.is_cuda and counts.is_contiguous()
+            assert counts.numel() >= 2 * self.nproblems
+        _check(self.L.fr_dopri5_step(self.ctx, self._ptr(u), t.data_ptr(), dt.data_ptr(),
+                                     tend.data_ptr() if tend is not None else None, nattempts,
+                                     float(atol), float(rtol),
+                                     counts.data_ptr() if counts is not None else None,
+                                     self._stream()), self.ctx)
         return u
 
     def rhs_adjoint(self, u, lam, out=None):

@@ -19,7 +19,7 @@ ARCH = "gfx950"
 HIPFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wno-unused-command-line-argument"]
-SOURCES = ["gemm_f64.hip", "gemm_f32.hip", "gemm_bf16.hip", "kernels.hip", "ceilings.hip", "adjoint.hip", "spop.hip", "spop_fields.hip", "spop_lds_f64.hip", "spop_lds_f32.hip", "gemm_host.cpp", "api.cpp",
+SOURCES = ["gemm_f64.hip", "gemm_f32.hip", "gemm_bf16.hip", "kernels.hip", "ceilings.hip", "adjoint.hip", "spop.hip", "spop_fields.hip", "spop_lds_f64.hip", "spop_lds_f32.hip", "steppers.hip", "gemm_host.cpp", "api.cpp",
            "setup.cpp"]
 
 

@@ -16,6 +16,7 @@
 #include "adjoint.h"
 #include "kernels.h"
 #include "setup.h"
+#include "steppers.h"
 
 namespace {
 
@@ -134,11 +135,34 @@ struct fr_ctx {
   struct Bufs {
     void *uf, *qf, *ft, *df, *fto;
     double *stage_out;
+    double *acc;  // RK register of the last-stage epilogue (null: d_acc)
   } cur{};
   bool adj_ready = false, adj_tuned = false;
   double *d_ufb = nullptr, *d_ftb = nullptr, *d_qfb = nullptr, *d_lt = nullptr;
   double *d_lc = nullptr, *d_kb = nullptr, *d_w = nullptr, *d_k = nullptr;
   double *d_st[3] = {nullptr, nullptr, nullptr};
+  // other steppers: forward Euler (one graph per step), DOPRI5 (slopes
+  // k1..k7, the stage/new state y, per-problem error sums, DOF counts,
+  // accept and rejection flags, one graph per attempt)
+  hipGraph_t eu_graph = nullptr;
+  hipGraphExec_t eu_exec = nullptr;
+  const double *eu_u = nullptr, *eu_dt = nullptr;
+  std::vector<double> ndof_host;
+  bool dp_ready = false;
+  double *d_dpk[7] = {};
+  double *d_dpy = nullptr, *d_dp_ssq = nullptr, *d_dp_ndof = nullptr;
+  int32_t *d_dp_acc = nullptr, *d_dp_rej = nullptr;
+  hipGraph_t dp_graph = nullptr;
+  hipGraphExec_t dp_exec = nullptr;
+  struct DpKey {
+    const double *u, *t, *dt, *tend;
+    const int32_t *counts;
+    double atol, rtol;
+    bool operator==(const DpKey &o) const {
+      return u == o.u && t == o.t && dt == o.dt && tend == o.tend && counts == o.counts &&
+             atol == o.atol && rtol == o.rtol;
+    }
+  } dp_key{};
   std::vector<void *> allocs;
 };
 
@@ -441,7 +465,7 @@ void run_step(fr_ctx *c, int st, const double *u, double *dudt, int epi, const f
       g.rcpdjac = b.d_rcpdjac; g.ld = b.ld; g.nelem = b.nelem;
       g.out = dudt + b.uoff;
       if (epi == fr::EPI_RK) {
-        g.acc = c->d_acc + b.uoff;
+        g.acc = (c->cur.acc ? c->cur.acc : c->d_acc) + b.uoff;
         g.stage = c->cur.stage_out ? c->cur.stage_out + b.uoff : nullptr;
         g.dt = dt; g.prob = b.d_prob; g.rk = *rk;
       }
@@ -930,6 +954,117 @@ void release_graph(fr_ctx *c) {
   c->graph_exec = nullptr; c->graph = nullptr; c->graph_u = nullptr; c->graph_dt = nullptr;
 }
 
+void release_stepper_graphs(fr_ctx *c) {
+  if (c->eu_exec) hipGraphExecDestroy(c->eu_exec);
+  if (c->eu_graph) hipGraphDestroy(c->eu_graph);
+  c->eu_exec = nullptr; c->eu_graph = nullptr; c->eu_u = nullptr; c->eu_dt = nullptr;
+  if (c->dp_exec) hipGraphExecDestroy(c->dp_exec);
+  if (c->dp_graph) hipGraphDestroy(c->dp_graph);
+  c->dp_exec = nullptr; c->dp_graph = nullptr; c->dp_key = fr_ctx::DpKey{};
+}
+
+// Capture `body` on the context's capture stream into (graph, exec).
+template <typename F>
+void capture(fr_ctx *c, hipGraph_t &graph, hipGraphExec_t &exec, F body) {
+  hip_check(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "capture");
+  try {
+    body(c->cap_stream);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    hipStreamEndCapture(c->cap_stream, &g);
+    if (g) hipGraphDestroy(g);
+    throw;
+  }
+  hip_check(hipStreamEndCapture(c->cap_stream, &graph), "end capture");
+  hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "instantiate");
+}
+
+// One forward Euler step in place: the last-stage RK epilogue with b = 1 and
+// the state itself as the register (u <- u + dt R(u)).
+void euler_step(fr_ctx *c, double *u, const double *dt, hipStream_t s) {
+  fr::RkCoef rk;
+  rk.a_next = 0.0; rk.b = 1.0; rk.first = 1; rk.last = 1;
+  const fr_ctx::Bufs saved = c->cur;
+  c->cur.acc = u;
+  try {
+    rhs_chain(c, u, u, fr::EPI_RK, &rk, dt, s);
+  } catch (...) {
+    c->cur = saved;
+    throw;
+  }
+  c->cur = saved;
+}
+
+// Dormand-Prince 5(4): stage matrix (lower triangle), and the error weights
+// b - bhat of the fifth- and embedded fourth-order solutions (Dormand and
+// Prince 1980).  The seventh stage is taken at the new state (its row is b).
+const double kDpA[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5, 0, 0, 0, 0, 0},
+    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+    {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+const double kDpBhat[7] = {5179.0 / 57600, 0, 7571.0 / 16695, 393.0 / 640,
+                           -92097.0 / 339200, 187.0 / 2100, 1.0 / 40};
+
+void ensure_dopri(fr_ctx *c, hipStream_t s) {
+  if (c->dp_ready) return;
+  for (auto &k : c->d_dpk) k = dev_alloc<double>(c, c->total_len);
+  c->d_dpy = dev_alloc<double>(c, c->total_len);
+  c->d_dp_ssq = dev_alloc<double>(c, c->nproblems);
+  c->d_dp_ndof = dev_upload(c, c->ndof_host.data(), c->ndof_host.size(), s);
+  c->d_dp_acc = dev_alloc<int32_t>(c, c->nproblems);
+  c->d_dp_rej = dev_alloc<int32_t>(c, c->nproblems);
+  c->dp_ready = true;
+}
+
+// One attempt on every problem: stages 2..7 (y_i = u + h sum_j a_ij k_j,
+// k_i = R(y_i)), the error norms, the controller and the commit.  k1 = R(u)
+// on entry; y ends as the fifth-order solution.
+void dopri_attempt(fr_ctx *c, double *u, double *t, double *dt, const double *tend,
+                   int32_t *counts, double atol, double rtol, hipStream_t s) {
+  double *const *k = c->d_dpk;
+  for (int i = 1; i < 7; ++i) {
+    for (auto &b : c->blocks) {
+      fr::DpStage st{};
+      for (int j = 0; j < i; ++j) {
+        st.a[j] = kDpA[i][j];
+        st.k[j] = k[j] + b.uoff;
+      }
+      hip_check(fr::launch_dp_stage(i, (int64_t)b.Nu * c->NV * b.ld, b.ld, b.nelem, b.d_prob, dt,
+                                    st, u + b.uoff, c->d_dpy + b.uoff, s),
+                "dopri5 stage");
+    }
+    rhs_chain(c, c->d_dpy, k[i], fr::EPI_NEGDIV, nullptr, nullptr, s);
+  }
+  for (auto &b : c->blocks) {
+    fr::DpError er{};
+    for (int j = 0; j < 7; ++j) {
+      er.E[j] = (j < 6 ? kDpA[6][j] : 0.0) - kDpBhat[j];
+      er.k[j] = er.E[j] != 0.0 ? k[j] + b.uoff : nullptr;
+    }
+    er.atol = atol; er.rtol = rtol;
+    hip_check(fr::launch_dp_error(c->NV, b.Nu, b.ld, b.nelem, c->nchunk, c->nelem_total,
+                                  b.d_prob, dt, er, u + b.uoff, c->d_dpy + b.uoff,
+                                  c->d_part + b.part_off, s),
+              "dopri5 error");
+  }
+  hip_check(fr::launch_problem_sums(1, c->nproblems, c->nchunk, c->nelem_total, c->nslice,
+                                    c->slice_len, c->d_pstart, c->d_plist, c->d_part, c->d_part2,
+                                    c->d_dp_ssq, s),
+            "dopri5 error sums");
+  hip_check(fr::launch_dp_control(c->nproblems, c->d_dp_ssq, c->d_dp_ndof, t, dt, tend,
+                                  c->d_dp_acc, c->d_dp_rej, counts, s),
+            "dopri5 control");
+  for (auto &b : c->blocks)
+    hip_check(fr::launch_dp_commit((int64_t)b.Nu * c->NV * b.ld, b.ld, b.nelem, b.d_prob,
+                                   c->d_dp_acc, c->d_dpy + b.uoff, k[6] + b.uoff, u + b.uoff,
+                                   k[0] + b.uoff, s),
+              "dopri5 commit");
+}
+
 }  // namespace
 
 extern "C" {
@@ -1109,10 +1244,12 @@ fr_status fr_setup_mesh_bc(const fr_config *cfg, int32_t nblocks, const fr_block
     c->d_part = dev_alloc<double>(c.get(), (size_t)c->nchunk * c->nelem_total * (NV + 1));
     {
       std::vector<std::vector<int64_t>> lists(c->nproblems);
+      c->ndof_host.assign(c->nproblems, 0.0);
       for (size_t bi = 0; bi < c->blocks.size(); ++bi)
         for (int64_t n = 0; n < c->blocks[bi].nelem; ++n) {
           int pr = blocks[bi].problem ? blocks[bi].problem[n] : 0;
           lists[pr].push_back(c->blocks[bi].part_off + n);
+          c->ndof_host[pr] += (double)c->blocks[bi].Nu * NV;
         }
       std::vector<int64_t> start(1, 0), flat;
       size_t maxlen = 0;
@@ -1212,6 +1349,65 @@ fr_status fr_rk_step(fr_ctx *c, double *u, const double *dt_dev, int32_t nsteps,
       c->graph_u = u; c->graph_dt = dt_dev;
     }
     for (int i = 0; i < nsteps; ++i) hip_check(hipGraphLaunch(c->graph_exec, s), "graph launch");
+    if (c->cfg.check_finite) {
+      int32_t h = 0;
+      hip_check(hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), s), "memset");
+      hip_check(fr::launch_check_finite(u, c->total_len, c->d_flag, s), "check_finite");
+      hip_check(hipMemcpyAsync(&h, c->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s), "copy");
+      hip_check(hipStreamSynchronize(s), "sync");
+      if (h) return fail(c, FR_ENONFINITE, "state contains NaN or Inf");
+    }
+  } catch (const Fail &f) {
+    return fail(c, f.st, f.msg);
+  }
+  return FR_OK;
+}
+
+fr_status fr_euler_step(fr_ctx *c, double *u, const double *dt_dev, int32_t nsteps,
+                        void *hip_stream) {
+  if (!c) return FR_EINVAL;
+  if (!u || !dt_dev || nsteps < 0) return fail(c, FR_EINVAL, "bad euler_step arguments");
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    if (nsteps > 0 && (c->eu_u != u || c->eu_dt != dt_dev || !c->eu_exec)) {
+      if (c->eu_exec) hipGraphExecDestroy(c->eu_exec);
+      if (c->eu_graph) hipGraphDestroy(c->eu_graph);
+      c->eu_exec = nullptr; c->eu_graph = nullptr;
+      capture(c, c->eu_graph, c->eu_exec,
+              [&](hipStream_t cs) { euler_step(c, u, dt_dev, cs); });
+      c->eu_u = u; c->eu_dt = dt_dev;
+    }
+    for (int i = 0; i < nsteps; ++i) hip_check(hipGraphLaunch(c->eu_exec, s), "graph launch");
+  } catch (const Fail &f) {
+    return fail(c, f.st, f.msg);
+  }
+  return FR_OK;
+}
+
+fr_status fr_dopri5_step(fr_ctx *c, double *u, double *t, double *dt, const double *tend,
+                         int32_t nattempts, double atol, double rtol, int32_t *counts,
+                         void *hip_stream) {
+  if (!c) return FR_EINVAL;
+  if (!u || !t || !dt || nattempts < 0) return fail(c, FR_EINVAL, "bad dopri5_step arguments");
+  if (!(atol > 0) || !(rtol > 0) || !std::isfinite(atol) || !std::isfinite(rtol))
+    return fail(c, FR_EINVAL, "tolerances must be positive and finite");
+  if (nattempts == 0) return FR_OK;
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    ensure_dopri(c, s);
+    const fr_ctx::DpKey key{u, t, dt, tend, counts, atol, rtol};
+    if (!c->dp_exec || !(c->dp_key == key)) {
+      if (c->dp_exec) hipGraphExecDestroy(c->dp_exec);
+      if (c->dp_graph) hipGraphDestroy(c->dp_graph);
+      c->dp_exec = nullptr; c->dp_graph = nullptr;
+      capture(c, c->dp_graph, c->dp_exec, [&](hipStream_t cs) {
+        dopri_attempt(c, u, t, dt, tend, counts, atol, rtol, cs);
+      });
+      c->dp_key = key;
+    }
+    hip_check(fr::launch_dp_clamp(c->nproblems, t, tend, dt, s), "dopri5 clamp");
+    rhs_chain(c, u, c->d_dpk[0], fr::EPI_NEGDIV, nullptr, nullptr, s);
+    for (int i = 0; i < nattempts; ++i) hip_check(hipGraphLaunch(c->dp_exec, s), "graph launch");
     if (c->cfg.check_finite) {
       int32_t h = 0;
       hip_check(hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), s), "memset");
@@ -1605,6 +1801,7 @@ void fr_destroy(fr_ctx *c) {
   if (!c) return;
   hipDeviceSynchronize();
   release_graph(c);
+  release_stepper_graphs(c);
   if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   for (void *p : c->allocs) hipFree(p);
   delete c;

@@ -189,7 +189,7 @@ hipError_t launch_elem_integrals(int nvars, int ndims, int nupts, int64_t ld, in
 // sum the partials per problem in fixed order: element lists in CSR form
 // (pstart[nprob+1], plist), nslice workgroups of `per` list entries per
 // problem (per a multiple of 64, nslice * per >= longest list), part2 holds
-// nprob * nslice * ncomp slice sums when nslice > 1; ncomp is 5 or 6
+// nprob * nslice * ncomp slice sums when nslice > 1; ncomp is 1, 5 or 6
 hipError_t launch_problem_sums(int ncomp, int nprob, int nchunk, int64_t pstride, int nslice,
                                int64_t per, const int64_t *pstart, const int64_t *plist,
                                const double *part, double *part2, double *out, hipStream_t s);

@@ -511,7 +511,9 @@ hipError_t launch_problem_sums(int ncomp, int nprob, int nchunk, int64_t pstride
                                int64_t per, const int64_t *pstart, const int64_t *plist,
                                const double *part, double *part2, double *out, hipStream_t s) {
   if (per < 64 || per % 64 || nslice < 1) return hipErrorInvalidValue;
-  if (ncomp == 5)
+  if (ncomp == 1)
+    problem_sums_t<1>(nprob, nchunk, pstride, nslice, per, pstart, plist, part, part2, out, s);
+  else if (ncomp == 5)
     problem_sums_t<5>(nprob, nchunk, pstride, nslice, per, pstart, plist, part, part2, out, s);
   else if (ncomp == 6)
     problem_sums_t<6>(nprob, nchunk, pstride, nslice, per, pstart, plist, part, part2, out, s);
