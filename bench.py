@@ -148,6 +148,39 @@ def time_steps(s, u, dt, steps, warmup, torch):
     return time.perf_counter() - t0
 
 
+def stepper_costs(s, u0, dt, steps, torch, atol=1e-8, rtol=1e-8):
+    """The other time steppers on the same mesh: forward Euler (ms per
+    step, one right-hand side) and adaptive DOPRI5 from dt (ms per attempt,
+    six right-hand sides; one more per call), with the controller's accepted
+    and rejected counts over `steps` attempts."""
+    out = {}
+    u = s.pack(u0)
+    s.euler_step(u, dt, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.euler_step(u, dt, steps)
+    torch.cuda.synchronize()
+    out["euler_ms_per_step"] = (time.perf_counter() - t0) / steps * 1e3
+    n = s.nproblems
+    for rep in range(2):                       # the first call captures the graph
+        u = s.pack(u0)
+        t = torch.zeros(n, dtype=torch.float64, device="cuda")
+        h = torch.full((n,), float(dt), dtype=torch.float64, device="cuda")
+        cnt = torch.zeros((n, 2), dtype=torch.int32, device="cuda")
+        k = 2 if rep == 0 else steps
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.dopri5(u, t, h, k, atol, rtol, counts=cnt)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    c = cnt.cpu().numpy()
+    out["dopri5"] = dict(ms_per_attempt=el / steps * 1e3, rhs_per_attempt=6, atol=atol, rtol=rtol,
+                         first_dt=float(dt), attempts=steps, accepted=int(c[:, 0].sum()),
+                         rejected=int(c[:, 1].sum()), final_t=float(t.max().item()),
+                         final_dt=float(h.max().item()))
+    return out
+
+
 def plan_name(plan, step=0):
     mbw, nc, wm = plan
     if mbw == 0 and wm & 4:
@@ -250,6 +283,8 @@ def main():
                     help="RK4 steps of the oracle for the CPU baseline (0: skip)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-steppers", action="store_true",
+                    help="skip the forward Euler and DOPRI5 timings")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="diagnostic: run only the adjoint cost measurement and print it")
     args = ap.parse_args()
@@ -317,6 +352,10 @@ def main():
                                plans={STEP_NAMES[k]: plan_name(sr.gemm_plan(0, k), k) for k in ktr
                                       if k in (1, 3, 5, 8)})
             sr.close()
+
+    if not args.no_steppers:
+        extra["steppers"] = stepper_costs(s, u0, w.dt, args.steps, torch)
+        extra["steppers"]["rk4_ms_per_step"] = ms
 
     if not args.no_adjoint:
         extra["adjoint"] = adjoint_ratio(P, configs, torch)
