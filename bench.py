@@ -81,13 +81,15 @@ def step_model(s, step, ts):
             byts += cols * (nf * ts + nu * 8 + D * nu * ts)
             if s.fused_gradt[bi]:        # step 4 in the epilogue: S = adj J and 1/J
                 byts += (D * D + 1) * nu * ne * 8
+            if s.fused_flux[bi]:         # step 6 too: F~ written (u is panel 2)
+                byts += D * nu * cols * ts
         elif step == 4:
             if not s.fused_gradt[bi]:
                 byts += 2.0 * D * nu * cols * ts + (D * D + 1) * nu * ne * 8
         elif step == 5:
             flops += 2.0 * D * nnz["M0"] * cols
             byts += D * cols * (nu + nf) * ts
-        elif step == 6:
+        elif step == 6 and not s.fused_flux[bi]:
             byts += nu * ne * (NV * 8 + D * D * 8 + D * NV * ts)
             if s.system == "ns":
                 byts += nu * ne * D * NV * ts
@@ -126,6 +128,9 @@ def make_solver(workload, prec, P, configs):
     # step 3 with the gradient transform (step 4) fused into its epilogue
     s.fused_gradt = [w.system == "ns" and s.gemm_plan(b, 3)[0] == 0 and s.gemm_plan(b, 3)[2] & 1
                      for b in range(len(w.mesh.blocks))]
+    # ... and the transformed flux (step 6) as well
+    s.fused_flux = [bool(f) and s.gemm_plan(b, 3)[2] & 15 == 11
+                    for b, f in enumerate(s.fused_gradt)]
     u0 = [np.ascontiguousarray(np.transpose(w.ic(b, s.solution_points(b)), (1, 2, 0)))
           for b in range(len(w.mesh.blocks))]
     s.bench_dt = w.dt
@@ -187,7 +192,8 @@ def plan_name(plan, step=0):
         return "sparse-row LDS-staged" + (" + fused J^-T (step 4)" if step == 3 and wm & 1 else "")
     if mbw == 0:
         return (f"sparse-row rpg={nc}" + (" all fields per thread" if wm & 2 else "")
-                + (" + fused J^-T (step 4)" if step == 3 and wm & 1 else ""))
+                + (" + fused J^-T (step 4)" if step == 3 and wm & 1 else "")
+                + (" + fused transformed flux (step 6)" if step == 3 and wm & 8 else ""))
     return f"mfma {mbw}x{nc} wm={wm}"
 
 

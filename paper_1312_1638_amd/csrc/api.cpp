@@ -39,8 +39,10 @@ const double kSparseDrop = 1e-13;
 // Sparse-row plans: MBW = 0, NC = operator rows per workgroup, WM = flags
 // (bit 0: the gradient transform fused into step 3, bit 1: every field of
 // an element in one thread, bit 2: the LDS-staged kernel, which takes all
-// rows of 64 columns per workgroup and ignores NC).
-const int kPlanFusedGradT = 1, kPlanFields = 2, kPlanStaged = 4;
+// rows of 64 columns per workgroup and ignores NC, bit 3: with bits 0 and 1,
+// the transformed flux of step 6 fused into step 3 as well).
+const int kPlanFusedGradT = 1, kPlanFields = 2, kPlanStaged = 4, kPlanFusedFlux = 8;
+const int kPlanFusedAll = kPlanFusedGradT | kPlanFields | kPlanFusedFlux;
 
 void apply_sparse_plan(GemmOp &op, const fr::GemmPlan &p, int nvars) {
   op.sp.rpg = p.NC;
@@ -68,7 +70,7 @@ void sparse_candidates(const GemmOp &op, int step, int D, std::vector<fr::GemmPl
   for (int f : {0, kPlanFields})
     for (int rpg : {1, 2, 4, 8, 16, 32, 64}) cands.push_back(fr::GemmPlan{0, rpg, f});
   if (step == 3)
-    for (int f : {0, kPlanFields}) {
+    for (int f : {0, kPlanFields, kPlanFields | kPlanFusedFlux}) {
       if (f && op.sp.width > FR_SPOP_GRADT_FIELDS_WMAX) continue;
       for (int rpg : {1, 2, 4, 8, 16}) cands.push_back(fr::GemmPlan{0, rpg, kPlanFusedGradT | f});
     }
@@ -104,6 +106,7 @@ struct fr_ctx {
   std::vector<BlockRT> blocks;
   int64_t total_len = 0, uf_len = 0, qf_len = 0, ft_len = 0, nelem_total = 0;
   void *d_uf = nullptr, *d_qf = nullptr, *d_ft = nullptr;
+  void *d_fto = nullptr;  // F~ (Navier-Stokes; Euler writes F~ over Q's storage)
   double *d_acc = nullptr, *d_stage = nullptr;
   // pairs
   int64_t npairs = 0;
@@ -316,6 +319,12 @@ bool gradt_fused(const fr_ctx *c, const BlockRT &b) {
   return c->ns && !c->no_fuse && b.s3.MBW == 0 && (b.s3.WM & kPlanFusedGradT);
 }
 
+// Step 6 done in step 3's epilogue (needs F~ apart from Q: step 5 reads Q).
+bool flux_fused(const fr_ctx *c, const BlockRT &b) {
+  return gradt_fused(c, b) && (b.s3.WM & kPlanFusedAll) == kPlanFusedAll &&
+         !(b.s3.WM & kPlanStaged) && c->cur.fto != c->cur.ft;
+}
+
 // Launch an operator product with whichever kernel its plan names.
 hipError_t launch_op(const GemmOp &op, int gprec, int epi, const fr::GemmArgs &g, int batch,
                      hipStream_t s) {
@@ -439,7 +448,13 @@ void run_step(fr_ctx *c, int st, const double *u, double *dudt, int epi, const f
       if (gradt_fused(c, b)) {
         g.rcpdjac = b.d_rcpdjac; g.ld = b.ld; g.nelem = b.nelem;
         g.smat = b.d_smat; g.D = D; g.Nu = b.Nu;
-        hip_check(launch_op(b.s3, gprec, fr::EPI_GRADT, g, 1, s), "gemm M6|M4' + J^-T");
+        if (flux_fused(c, b)) {
+          g.fout = elem(c->cur.fto, b.ftoff, ts);
+          g.gamma = c->cfg.gamma; g.mu = c->cfg.mu; g.prandtl = c->cfg.prandtl;
+          hip_check(launch_op(b.s3, gprec, fr::EPI_GRADTF, g, 1, s), "gemm M6|M4' + J^-T + flux");
+        } else {
+          hip_check(launch_op(b.s3, gprec, fr::EPI_GRADT, g, 1, s), "gemm M6|M4' + J^-T");
+        }
       } else {
         hip_check(launch_op(b.s3, gprec, fr::EPI_STORE, g, 1, s), "gemm M6|M4'");
       }
@@ -456,7 +471,8 @@ void run_step(fr_ctx *c, int st, const double *u, double *dudt, int epi, const f
       g.sC = (int64_t)b.Nf * N;
       hip_check(launch_op(b.m5, gprec, fr::EPI_STORE, g, D, s), "gemm M5");
     } else if (st == 6) {
-      hip_check(fr::launch_tflux(point_args(c, b, u), c->ns, s), "tflux");
+      if (!flux_fused(c, b))
+        hip_check(fr::launch_tflux(point_args(c, b, u), c->ns, s), "tflux");
     } else if (st == 8) {
       fr::GemmArgs g = gemm_args(b.s8);
       g.B1 = elem(c->cur.df, b.ufoff, ts); g.ldb1 = N; g.b1_f32 = f32;
@@ -517,8 +533,9 @@ void tune_op(fr_ctx *c, GemmOp &op, int step, BlockRT &b, hipStream_t s) {
     hip_check(hipEventCreate(&e1), "event");
     float best_ms = 1e30f;
     std::vector<fr::GemmPlan> cands = fr::gemm_candidates(op.M, N, c->prec);
-    // step 3: also the plans with the gradient transform fused; every
-    // candidate is timed together with step 4 (a no-op when fused)
+    // step 3: also the plans with the gradient transform (and the flux)
+    // fused; every candidate is timed together with steps 4 and 6 (no-ops
+    // when fused)
     sparse_candidates(op, step, c->D, cands);
     for (const fr::GemmPlan &p : cands) {
       void *d = p.MBW ? pack_upload(c, op, p, s, false) : nullptr;
@@ -530,12 +547,18 @@ void tune_op(fr_ctx *c, GemmOp &op, int step, BlockRT &b, hipStream_t s) {
       try {
         for (int w = 0; w < 2; ++w) {
           run_step(c, step, c->d_stage, c->d_acc, epi, rkp, dtp, s);
-          if (step == 3) run_step(c, 4, c->d_stage, c->d_acc, epi, nullptr, nullptr, s);
+          if (step == 3) {
+            run_step(c, 4, c->d_stage, c->d_acc, epi, nullptr, nullptr, s);
+            run_step(c, 6, c->d_stage, c->d_acc, epi, nullptr, nullptr, s);
+          }
         }
         hip_check(hipEventRecord(e0, s), "record");
         for (int w = 0; w < 5; ++w) {
           run_step(c, step, c->d_stage, c->d_acc, epi, rkp, dtp, s);
-          if (step == 3) run_step(c, 4, c->d_stage, c->d_acc, epi, nullptr, nullptr, s);
+          if (step == 3) {
+            run_step(c, 4, c->d_stage, c->d_acc, epi, nullptr, nullptr, s);
+            run_step(c, 6, c->d_stage, c->d_acc, epi, nullptr, nullptr, s);
+          }
         }
         hip_check(hipEventRecord(e1, s), "record");
         hip_check(hipEventSynchronize(e1), "sync");
@@ -1231,9 +1254,13 @@ fr_status fr_setup_mesh_bc(const fr_config *cfg, int32_t nblocks, const fr_block
     if (c->ns)
       c->d_qf = c->prec == FR_FP64 ? (void *)dev_alloc<double>(c.get(), c->qf_len)
                                     : (void *)dev_alloc<float>(c.get(), c->qf_len);
+    if (c->ns)
+      c->d_fto = c->prec == FR_FP64 ? (void *)dev_alloc<double>(c.get(), c->ft_len)
+                                     : (void *)dev_alloc<float>(c.get(), c->ft_len);
     c->d_acc = dev_alloc<double>(c.get(), c->total_len);
     c->d_stage = dev_alloc<double>(c.get(), c->total_len);
-    c->cur = fr_ctx::Bufs{c->d_uf, c->d_qf, c->d_ft, c->d_uf, c->d_ft, c->d_stage};
+    c->cur = fr_ctx::Bufs{c->d_uf, c->d_qf, c->d_ft, c->d_uf, c->ns ? c->d_fto : c->d_ft,
+                          c->d_stage};
     // reductions: element partials and per-problem element lists
     {
       // enough workgroups to fill the chip on small meshes
@@ -1593,6 +1620,7 @@ fr_status fr_debug_stage(fr_ctx *c, const double *u, int32_t stage, double *out,
     if (stage == 1 || stage == 7) { src = c->d_uf; n = c->uf_len; }
     else if (stage == 2) { src = c->d_qf; n = c->qf_len; }
     else if (stage == 5) { src = c->d_qf; n = c->qf_len; }
+    else if (stage == 6) { src = c->cur.fto; n = c->ft_len; }
     else { src = c->d_ft; n = c->ft_len; }
     hip_check(hipMemcpyAsync(out, src, n * sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
   } catch (const Fail &f) {
@@ -1761,7 +1789,10 @@ fr_status fr_debug_set_plan(fr_ctx *c, int32_t block, int32_t step, int32_t mbw,
     } else {
       if (!op->sp.colidx) throw Fail{FR_EINVAL, "operator has no sparse-row form"};
       const bool staged = wm & kPlanStaged, fused = wm & kPlanFusedGradT;
-      if (nc < 1 || wm < 0 || wm > 7 || (fused && step != 3) ||
+      const bool fflux = wm & kPlanFusedFlux;
+      if (nc < 1 || wm < 0 || wm > 15 || (fused && step != 3) ||
+          (fflux && (wm & ~kPlanStaged) != kPlanFusedAll) || (fflux && staged) ||
+          (fflux && op->sp.width > FR_SPOP_GRADT_FIELDS_WMAX) ||
           (staged && ((wm & kPlanFields) || !staged_ok(*op, fused, c->D))) ||
           (wm == (kPlanFusedGradT | kPlanFields) && op->sp.width > FR_SPOP_GRADT_FIELDS_WMAX) ||
           (step == 13 && c->ns && (wm & kPlanFields) && op->sp.width > FR_SPOP_GRADT_FIELDS_WMAX))
@@ -1771,7 +1802,9 @@ fr_status fr_debug_set_plan(fr_ctx *c, int32_t block, int32_t step, int32_t mbw,
     }
     op->MBW = mbw; op->NC = nc; op->WM = wm;
     hip_check(hipStreamSynchronize(s), "sync");
-    release_graph(c);  // a captured step holds the previous plan's launches
+    // captured steps hold the previous plan's launches
+    release_graph(c);
+    release_stepper_graphs(c);
   } catch (const Fail &f) {
     return fail(c, f.st, f.msg);
   }

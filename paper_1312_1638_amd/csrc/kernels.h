@@ -19,10 +19,14 @@ enum GemmEpi {
   EPI_ADD = 3,     // C[row][col] += acc (FP64 only; adjoint accumulation)
   EPI_GRADT = 4,   // sparse-row kernel only: the D rows d Nu + rho of one point
                    // are transformed by J^-T = S^T / det J before the store
-  EPI_ADDT = 5     // sparse-row kernel only (adjoint, FP64): row rho of the D
+  EPI_ADDT = 5,    // sparse-row kernel only (adjoint, FP64): row rho of the D
                    // batch slices is added to C, then the D sums of one point
                    // are transformed by J^-1 = S / det J (the reverse of the
                    // gradient transform); padding columns are only added
+  EPI_GRADTF = 6   // sparse-row kernel, every field of an element per thread
+                   // (Navier-Stokes): EPI_GRADT, then the transformed flux
+                   // F~ = S f(u, Q) of the point from the stored Q and the
+                   // state (panel 2) into fout; padding columns get 0
 };
 
 enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };
@@ -54,6 +58,7 @@ struct GemmArgs {
   const double *dt; const int32_t *prob;      // per-problem step size, element -> problem
   RkCoef rk;
   const double *smat; int D; int Nu;          // EPI_GRADT: S = adj J [D][D][Nu][ld]
+  void *fout; double gamma, mu, prandtl;      // EPI_GRADTF: F~ (type TC, layout of C)
 };
 
 // Pack A (M x (K1 + K2), row-major, panel 2 columns follow panel 1) into the

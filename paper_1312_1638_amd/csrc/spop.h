@@ -24,6 +24,7 @@
 #pragma once
 
 #include "kernels.h"
+#include "physics.h"
 
 namespace fr {
 
@@ -42,13 +43,14 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
   const int64_t t = tile * 256 + threadIdx.x;
   if (t >= (F == 1 ? g.N : g.ld)) return;
   const int r0 = rgrp * rpg;
-  const int rmax = EPI == EPI_GRADT ? g.Nu : g.M;  // EPI_ADDT: M = Nu
+  constexpr bool GT = EPI == EPI_GRADT || EPI == EPI_GRADTF;
+  const int rmax = GT ? g.Nu : g.M;  // EPI_ADDT: M = Nu
   const int r1 = r0 + rpg < rmax ? r0 + rpg : rmax;
   const TB1 *__restrict__ B1b = (const TB1 *)g.B1 + (int64_t)blockIdx.y * g.sB1;
   const TB1 *__restrict__ B1 = B1b + t;
   const TB2 *__restrict__ B2 = (const TB2 *)g.B2 + t;
   int64_t n = 0;
-  if (EPI == EPI_NEGDIV || EPI == EPI_RK || EPI == EPI_GRADT || EPI == EPI_ADDT)
+  if (EPI == EPI_NEGDIV || EPI == EPI_RK || GT || EPI == EPI_ADDT)
     n = F == 1 ? t % g.ld : t;
   const bool live = n < g.nelem;
   double dtv = 0;
@@ -132,8 +134,9 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
     }
     return;
   }
-  if constexpr (EPI == EPI_GRADT) {
+  if constexpr (GT) {
     // rows d Nu + rho, d < DG, of the points rho in [r0, r1) (r1 <= Nu)
+    static_assert(EPI != EPI_GRADTF || F == DG + 2, "the flux needs every field of a point");
     const int64_t plane = (int64_t)g.Nu * g.ld;
     TC *C = (TC *)g.C;
     for (int rho = r0; rho < r1; ++rho) {
@@ -148,6 +151,8 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
         for (int i = 0; i < DG; ++i)
 #pragma unroll
           for (int jj = 0; jj < DG; ++jj) S[i][jj] = g.smat[(i * DG + jj) * plane + pt];
+        // Q of the point as stored (rounded to TC), kept for the flux
+        double q[DG][F];
 #pragma unroll
         for (int a = 0; a < F; ++a)
 #pragma unroll
@@ -155,14 +160,42 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
             double sj = 0;
 #pragma unroll
             for (int i = 0; i < DG; ++i) sj += S[i][jj] * (double)qt[i][a];
-            C[(int64_t)(jj * g.Nu + rho) * g.ldc + t + a * fs] = (TC)(rj * sj);
+            const TC qv = (TC)(rj * sj);
+            C[(int64_t)(jj * g.Nu + rho) * g.ldc + t + a * fs] = qv;
+            q[jj][a] = (double)qv;
           }
+        if constexpr (EPI == EPI_GRADTF) {
+          // the state of the point is panel 2 (u, rows rho of every field)
+          const double *__restrict__ up = (const double *)g.B2 + (int64_t)rho * ldb2 + t;
+          double u[F], f[DG][F], fv[DG][F], p, v[DG];
+#pragma unroll
+          for (int a = 0; a < F; ++a) u[a] = up[a * fs];
+          inviscid_flux<DG>(u, g.gamma, f, p, v);
+          viscous_flux<DG>(u, q, g.gamma, g.mu, g.prandtl, fv);
+#pragma unroll
+          for (int jj = 0; jj < DG; ++jj)
+#pragma unroll
+            for (int a = 0; a < F; ++a) f[jj][a] -= fv[jj][a];
+          TC *Fo = (TC *)g.fout;
+#pragma unroll
+          for (int i = 0; i < DG; ++i)
+#pragma unroll
+            for (int a = 0; a < F; ++a) {
+              double sf = 0;
+#pragma unroll
+              for (int jj = 0; jj < DG; ++jj) sf += S[i][jj] * f[jj][a];
+              Fo[(int64_t)(i * g.Nu + rho) * g.ldc + t + a * fs] = (TC)sf;
+            }
+        }
       } else {
 #pragma unroll
         for (int a = 0; a < F; ++a)
 #pragma unroll
-          for (int jj = 0; jj < DG; ++jj)
+          for (int jj = 0; jj < DG; ++jj) {
             C[(int64_t)(jj * g.Nu + rho) * g.ldc + t + a * fs] = (TC)qt[jj][a];
+            if constexpr (EPI == EPI_GRADTF)
+              ((TC *)g.fout)[(int64_t)(jj * g.Nu + rho) * g.ldc + t + a * fs] = (TC)0;
+          }
       }
     }
     return;
@@ -226,14 +259,14 @@ void spop_launch_w(const GemmArgs &g, const SparseOp &sp, int batch, hipStream_t
   }
 }
 
-template <typename T, int W, int DG, int F>
+template <typename T, int EPI, int W, int DG, int F>
 void spop_launch_gradt(const GemmArgs &g, const SparseOp &sp, hipStream_t s) {
   const int ngroups = (g.Nu + sp.rpg - 1) / sp.rpg;
   dim3 grid((unsigned)(spop_tiles<F>(g) * ngroups), 1);
   if constexpr (sizeof(T) == 8)
-    spop_kernel<T, EPI_GRADT, W, double, double, double, DG, F><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
+    spop_kernel<T, EPI, W, double, double, double, DG, F><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
   else  // FP32 contexts: C^f in FP32 scratch (panel 1), the FP64 state (panel 2)
-    spop_kernel<T, EPI_GRADT, W, float, double, float, DG, F><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
+    spop_kernel<T, EPI, W, float, double, float, DG, F><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
 }
 
 template <int W, int DG, int F>
@@ -265,21 +298,25 @@ hipError_t spop_addt_t(const GemmArgs &g, const SparseOp &sp, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename T, int F>
+template <typename T, int F, int EPI = EPI_GRADT>
 hipError_t spop_gradt_t(const GemmArgs &g, const SparseOp &sp, hipStream_t s) {
   if ((g.D != 2 && g.D != 3) || g.Nu * g.D != g.M || !g.smat) return hipErrorInvalidValue;
   if (sizeof(T) == 4 && (!g.b1_f32 || g.b2_f32 || !g.c_f32)) return hipErrorInvalidValue;
   // all fields per thread: F is the field count D + 2
   constexpr int DG = F == 4 ? 2 : 3;
   if (F > 1 && g.D != DG) return hipErrorInvalidValue;
+  if constexpr (EPI == EPI_GRADTF) {
+    if (F == 1 || !g.fout || g.fout == g.C) return hipErrorInvalidValue;
+  }
   switch (sp.width) {
-#define FR_W(W_)                                                          \
-  case W_:                                                                \
-    if constexpr (F > 1 && W_ > FR_SPOP_GRADT_FIELDS_WMAX)                \
-      return hipErrorInvalidValue;                                        \
-    else if constexpr (F > 1) spop_launch_gradt<T, W_, DG, F>(g, sp, s);  \
-    else if (g.D == 3) spop_launch_gradt<T, W_, 3, F>(g, sp, s);          \
-    else spop_launch_gradt<T, W_, 2, F>(g, sp, s);                        \
+#define FR_W(W_)                                                               \
+  case W_:                                                                     \
+    if constexpr (F > 1 && W_ > FR_SPOP_GRADT_FIELDS_WMAX)                     \
+      return hipErrorInvalidValue;                                             \
+    else if constexpr (F > 1) spop_launch_gradt<T, EPI, W_, DG, F>(g, sp, s);  \
+    else if constexpr (EPI == EPI_GRADTF) return hipErrorInvalidValue;         \
+    else if (g.D == 3) spop_launch_gradt<T, EPI, W_, 3, F>(g, sp, s);          \
+    else spop_launch_gradt<T, EPI, W_, 2, F>(g, sp, s);                        \
     break;
     FR_SPOP_WIDTHS(FR_W)
 #undef FR_W
@@ -316,6 +353,16 @@ hipError_t launch_spop_f(int prec, int epi, const GemmArgs &g, const SparseOp &s
     if (prec == PREC_F64) return spop_gradt_t<double, F>(g, sp, s);
     if (prec == PREC_F32) return spop_gradt_t<float, F>(g, sp, s);
     return hipErrorInvalidValue;
+  }
+  if (epi == EPI_GRADTF) {
+    if constexpr (F == 1) {
+      return hipErrorInvalidValue;
+    } else {
+      if (batch != 1) return hipErrorInvalidValue;
+      if (prec == PREC_F64) return spop_gradt_t<double, F, EPI_GRADTF>(g, sp, s);
+      if (prec == PREC_F32) return spop_gradt_t<float, F, EPI_GRADTF>(g, sp, s);
+      return hipErrorInvalidValue;
+    }
   }
   if (prec == PREC_F64) {
     switch (epi) {

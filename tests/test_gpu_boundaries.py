@@ -55,7 +55,8 @@ def test_boundary_rhs_fp32(name):
     assert err < tol
 
 
-@pytest.mark.parametrize("variant", ["mfma", "sparse", "fused_fields", "staged_fused"])
+@pytest.mark.parametrize("variant", ["mfma", "sparse", "fused_fields", "fused_flux",
+                                     "staged_fused"])
 @pytest.mark.parametrize("name", ["couette_mixed5_p2", "couette_hex3_p2"])
 def test_boundary_every_kernel_variant(name, variant):
     from test_gpu_parity import _force_plans

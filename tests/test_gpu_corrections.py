@@ -83,7 +83,7 @@ def test_corrections_bf16x3(name):
 
 
 @pytest.mark.parametrize("variant", ["mfma", "sparse", "fused", "fields", "fused_fields",
-                                     "staged", "staged_fused"])
+                                     "fused_flux", "staged", "staged_fused"])
 @pytest.mark.parametrize("name", ["tgv3_p4_sd", "vortex7_p3_hu"])
 def test_corrections_every_kernel_variant(name, variant):
     from test_gpu_parity import _force_plans

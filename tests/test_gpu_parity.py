@@ -72,8 +72,10 @@ def _force_plans(s, w, variant):
     'mfma' (matrix cores), 'sparse' (sparse-row, 4 rows per workgroup),
     'fused' (sparse-row, the gradient transform fused into step 3), the
     same two with every field of an element in one thread ('fields',
-    'fused_fields'), and the LDS-staged kernel ('staged', 'staged_fused').
-    Dense triangle operators have no sparse-row form and keep their plan."""
+    'fused_fields'), the latter with the transformed flux of step 6 fused
+    as well ('fused_flux'), and the LDS-staged kernel ('staged',
+    'staged_fused').  Dense triangle operators have no sparse-row form and
+    keep their plan."""
     import paper_1312_1638_amd as P
     steps = [1, 3, 5, 8] if w.system == "ns" else [1, 8]
     forced = 0
@@ -94,6 +96,8 @@ def _force_plans(s, w, variant):
                 plan = (0, 64, 4)
             elif variant == "staged_fused":
                 plan = (0, 64, 5) if st == 3 else (0, 64, 4)
+            elif variant == "fused_flux":
+                plan = (0, 2, 11) if st == 3 else (0, 3, 2)
             else:
                 plan = (0, 2, 3) if st == 3 else (0, 3, 2)
             try:
@@ -111,7 +115,7 @@ def _force_plans(s, w, variant):
 @pytest.mark.parametrize("name", ["tgv3_p4", "mixed5_p2_ns", "curved3_p2_ns", "vortex7_p3",
                                   "mixed6_p3_euler"])
 @pytest.mark.parametrize("variant", ["mfma", "sparse", "fused", "fields", "fused_fields",
-                                     "staged", "staged_fused"])
+                                     "fused_flux", "staged", "staged_fused"])
 def test_every_kernel_variant(name, variant):
     """du/dt and u after 3 RK4 steps (captured graph) with every operator
     product forced onto one kernel family."""
@@ -127,7 +131,26 @@ def test_every_kernel_variant(name, variant):
     assert err < 1e-12 and eu < 1e-12
 
 
-@pytest.mark.parametrize("variant", ["fused", "fused_fields", "staged_fused"])
+@pytest.mark.parametrize("name", ["tgv3_p4", "mixed5_p2_ns", "curved3_p2_ns"])
+def test_fused_flux_matches_the_separate_flux(name):
+    """FP64: the transformed flux computed in step 3's epilogue is the same
+    formula as step 6's kernel; only the compiler's multiply-add
+    contraction may differ between the two kernels, so du/dt agrees to the
+    case's rounding floor."""
+    w = C.SMALL[name]()
+    d, s, u = _both(w)
+    t = s.pack(u)
+    out = []
+    for variant in ("fused_fields", "fused_flux"):
+        _force_plans(s, w, variant)
+        out.append(s.unpack(s.rhs(t)))
+    _tol, _ext, floor = C.floor_tolerance(d, u, 1e-12)
+    diff = C.rel_l2(out[1], out[0])
+    print(f"{name}: fused vs separate flux rel L2 {diff:.2e} (floor {floor:.2e})")
+    assert diff <= max(floor, 1e-15)
+
+
+@pytest.mark.parametrize("variant", ["fused", "fused_fields", "fused_flux", "staged_fused"])
 def test_fused_gradient_transform_fp32(variant):
     w = C.SMALL["tgv5_p3"]()
     d, s, u = _both(w, "fp32")
