@@ -226,9 +226,14 @@ def time_kernels(s, u, torch, nrep=50):
 def adjoint_ratio(P, configs, torch, n=24, nsteps=200, ckpt=20):
     """Wall time of the full gradient of E_k(u_N) with respect to u_0 (forward
     with checkpoints, segment replay, hand-written RK4 adjoint) over the wall
-    time of the N forward steps: Taylor-Green, n^3 hexes, p=3, FP64."""
+    time of the N forward steps: Taylor-Green, n^3 hexes, p=3, FP64.  value:
+    the default stash budget (free device memory less a reserve: segments
+    that fit keep their stash and are never replayed), a repeated gradient
+    (the stash memory already mapped); value_first_call: the first gradient,
+    which also maps that memory; value_replay_all: budget 0 (every segment
+    but the last replayed from its checkpoint)."""
     import numpy as np
-    from paper_1312_1638_amd.autograd import KineticEnergy, integrate_steps
+    from paper_1312_1638_amd.autograd import KineticEnergy, integrate_steps, stash_segments
     w = configs.adjoint_tgv(n=n, order=3, nsteps=nsteps, ckpt=ckpt)
     s = P.Solver(w.mesh, system=w.system, gamma=w.gamma, mu=w.mu, prandtl=w.prandtl,
                  ldg_beta=w.ldg_beta, ldg_tau=w.ldg_tau)
@@ -246,16 +251,32 @@ def adjoint_ratio(P, configs, torch, n=24, nsteps=200, ckpt=20):
     u0g = u0.clone().requires_grad_(True)
     J = KineticEnergy.apply(integrate_steps(s, u0g, w.dt, 1, 1), s)   # warm the adjoint
     torch.autograd.grad(J, u0g)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    J = KineticEnergy.apply(integrate_steps(s, u0g, w.dt, nsteps, ckpt), s)
-    (g,) = torch.autograd.grad(J, u0g)
-    torch.cuda.synchronize()
-    t_grad = time.perf_counter() - t0
+    out = {}
+    nseg = -(-nsteps // ckpt)
+    for key, budget in (("replay_all", 0), ("default", None)):
+        resident = min(nseg, max(1, int(stash_segments(s.stash_len(), ckpt, budget, u0.device))))
+        times = []
+        for _rep in range(2):               # the first call also maps the stash memory
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            J = KineticEnergy.apply(integrate_steps(s, u0g, w.dt, nsteps, ckpt, budget), s)
+            (g,) = torch.autograd.grad(J, u0g)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            del J, g
+        out[key] = (times, resident)
+    seg_gb = s.stash_len() * ckpt * 8 / 1e9
     s.close()
+    torch.cuda.empty_cache()
+    (first, t_grad), resident = out["default"]
     return dict(value=t_grad / t_fwd, unit="gradient wall time / forward wall time",
                 workload=w.name, steps=nsteps, checkpoint_every=ckpt,
-                forward_s=t_fwd, gradient_s=t_grad, objective="kinetic energy at t_N")
+                segments=nseg, segments_resident=resident, stash_GB_per_segment=seg_gb,
+                value_replay_all=out["replay_all"][0][1] / t_fwd,
+                value_first_call=first / t_fwd,
+                forward_s=t_fwd, gradient_s=t_grad, gradient_first_call_s=first,
+                gradient_replay_all_s=out["replay_all"][0][1],
+                objective="kinetic energy at t_N")
 
 
 def cpu_baseline(w, nsteps):

@@ -1,14 +1,18 @@
 """torch.autograd wrapper of RK4 time stepping with a checkpointed adjoint.
 
-Forward: nsteps classical RK4 steps (the library's captured step graph),
-keeping the state every `ckpt` steps; the steps of the last segment use the
-library's stashing step instead, which leaves their stage states and primal
-intermediates in device memory (~40 states per step for Navier-Stokes), so
-that segment is never replayed.  Backward: segments from last to first;
-each earlier segment is replayed forward from its checkpoint with the
-stashing step, then the hand-written RK4 step adjoint consumes the stash step
-by step in reverse with no recomputation.  Torch holds the tensors; all
-arithmetic runs in the HIP library.
+Forward: nsteps classical RK4 steps in segments of `ckpt` steps.  The last
+segments, as many as fit in a device-memory budget (at least one), run with
+the library's stashing step, which leaves every step's stage states and
+primal intermediates in device memory (~40 states per step for
+Navier-Stokes); the earlier segments run the captured step graph and keep
+only their starting state (a checkpoint every `ckpt` steps).  Backward:
+segments from last to first; a segment without a stash is first replayed
+from its checkpoint with the stashing step (into a reused buffer), then the
+hand-written RK4 step adjoint consumes the stash step by step in reverse with
+no recomputation.  The budget defaults to the free device memory less a
+reserve, so on a 288 GB device most segments are never replayed; budget 0
+replays every segment but the last.  Torch holds the tensors; all arithmetic
+runs in the HIP library.
 """
 from __future__ import annotations
 
@@ -17,23 +21,29 @@ import torch
 
 class FRSteps(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, u0, solver, dt, nsteps, ckpt):
+    def forward(ctx, u0, solver, dt, nsteps, ckpt, budget):
         work = u0.detach().clone()
-        ckpts = []
         L = solver.stash_len()
-        # one segment's stash: stage states and primal intermediates of every
-        # step, written by the stashing steps and read by the step adjoints
-        stash = torch.empty(ckpt * L, dtype=torch.float64, device=work.device)
-        last0 = ((nsteps - 1) // ckpt) * ckpt if nsteps > 0 else 0
+        nseg = -(-nsteps // ckpt) if nsteps > 0 else 0
+        resident = min(nseg, max(1, int(stash_segments(L, ckpt, budget, work.device))))
+        first = nseg - resident            # segments first.. keep their stash
+        ckpts, stashes = {}, {}
         for n in range(nsteps):
-            if n % ckpt == 0:
-                ckpts.append(work.clone())
-            if n >= last0:
-                solver.step_stash(work, dt, stash[(n - last0) * L:(n - last0 + 1) * L])
+            seg, i = divmod(n, ckpt)
+            if i == 0:
+                if seg < first:
+                    ckpts[seg] = work.clone()
+                else:
+                    # a stash of stage states and primal intermediates per step,
+                    # written here and read by the step adjoints
+                    steps = min(ckpt, nsteps - n)
+                    stashes[seg] = torch.empty(steps * L, dtype=torch.float64, device=work.device)
+            if seg >= first:
+                solver.step_stash(work, dt, stashes[seg][i * L:(i + 1) * L])
             else:
                 solver.step(work, dt, 1)
-        ctx.solver, ctx.dt, ctx.nsteps, ctx.ckpt, ctx.ckpts = solver, dt, nsteps, ckpt, ckpts
-        ctx.stash = stash
+        ctx.solver, ctx.dt, ctx.nsteps, ctx.ckpt = solver, dt, nsteps, ckpt
+        ctx.ckpts, ctx.stashes, ctx.nseg = ckpts, stashes, nseg
         return work
 
     @staticmethod
@@ -42,23 +52,48 @@ class FRSteps(torch.autograd.Function):
         lam = lam_out.detach().contiguous().clone()
         work = torch.empty_like(lam)
         L = s.stash_len()
-        stash = ctx.stash
-        for seg in reversed(range(len(ctx.ckpts))):
+        spare = None                         # replay buffer: a consumed full-length stash
+        for seg in reversed(range(ctx.nseg)):
             n0 = seg * ckpt
             n1 = min(ctx.nsteps, n0 + ckpt)
-            if seg < len(ctx.ckpts) - 1:       # the last segment was stashed by forward
-                work.copy_(ctx.ckpts[seg])
+            if seg in ctx.stashes:
+                stash = ctx.stashes.pop(seg)
+            else:
+                if spare is None:
+                    spare = torch.empty(ckpt * L, dtype=torch.float64, device=lam.device)
+                stash = spare
+                work.copy_(ctx.ckpts.pop(seg))
                 for i in range(n1 - n0):
                     s.step_stash(work, dt, stash[i * L:(i + 1) * L])
             for i in reversed(range(n1 - n0)):
                 s.rk_step_adjoint_stash(stash[i * L:(i + 1) * L], dt, lam, out=lam)
-        ctx.stash = None
-        return lam, None, None, None, None
+            if spare is None and stash.numel() == ckpt * L:
+                spare = stash
+        ctx.stashes, ctx.ckpts = None, None
+        return lam, None, None, None, None, None
 
 
-def integrate_steps(solver, u0, dt, nsteps, ckpt=20):
-    """u(nsteps) as a differentiable function of u0."""
-    return FRSteps.apply(u0, solver, dt, nsteps, ckpt)
+# Device memory left free when the stash budget is taken from what is free.
+RESERVE_FRACTION, RESERVE_MIN = 0.1, 8 << 30
+
+
+def stash_segments(L, ckpt, budget, device):
+    """Segments of `ckpt` steps whose stash (L float64 per step) fits in
+    `budget` bytes; budget None: the free device memory, counting what
+    torch's allocator holds unused, less a reserve (the larger of 10% of
+    the device and 8 GiB)."""
+    if budget is None:
+        free, total = torch.cuda.mem_get_info(device)
+        cached = torch.cuda.memory_reserved(device) - torch.cuda.memory_allocated(device)
+        budget = max(0, free + cached - max(RESERVE_FRACTION * total, RESERVE_MIN))
+    return budget // (ckpt * L * 8)
+
+
+def integrate_steps(solver, u0, dt, nsteps, ckpt=20, stash_budget=None):
+    """u(nsteps) as a differentiable function of u0.  stash_budget: bytes of
+    device memory the forward pass may keep for stashed segments (None: the
+    free memory less a reserve; 0: only the last segment)."""
+    return FRSteps.apply(u0, solver, dt, nsteps, ckpt, stash_budget)
 
 
 class KineticEnergy(torch.autograd.Function):

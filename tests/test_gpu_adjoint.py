@@ -162,6 +162,30 @@ def test_gradient_through_steps_matches_oracle_complex_step():
         assert abs(got - ref) <= 1e-10 * abs(ref)
 
 
+def test_stash_budget_leaves_the_gradient_unchanged():
+    """Segments kept resident or replayed from checkpoints (budget 0, room
+    for two segments with a short last one, everything resident) give the
+    same gradient: the replay repeats the forward's arithmetic."""
+    import torch
+    from paper_1312_1638_amd.autograd import KineticEnergy, integrate_steps
+    w = configs.taylor_green_hexes(3, 2, dt=1e-3)
+    d = Discretisation(w)
+    u = _off_kink(d, d.initial_state(w), eps=1e-2)
+    s = C.solver_for(w)
+    nsteps, ckpt = 10, 3
+    two = 2 * ckpt * s.stash_len() * 8
+    grads = []
+    for budget in (0, two, None):
+        u0 = s.pack(u).requires_grad_(True)
+        J = KineticEnergy.apply(integrate_steps(s, u0, w.dt, nsteps, ckpt, budget), s)
+        (g,) = torch.autograd.grad(J, u0)
+        grads.append(g.detach().clone())
+    for g in grads[1:]:
+        err = float(torch.linalg.norm(g - grads[0]) / torch.linalg.norm(grads[0]))
+        print(f"gradient rel difference {err:.2e}")
+        assert err <= 1e-13
+
+
 @pytest.mark.parametrize("name", ["mixed5_p2_ns", "curved4_p4"])
 def test_stash_path_matches_recompute_path(name):
     import torch
