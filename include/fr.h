@@ -303,7 +303,9 @@ fr_status fr_debug_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, const d
  * the gradient transform of step 4 fused into its epilogue, so that step 4
  * launches nothing; bit 1 every field of an element computed by one thread;
  * bit 2 the LDS-staged kernel (64 columns and all rows per workgroup, B
- * streamed through LDS; nc is then unused and reported as 64). */
+ * streamed through LDS; nc is then unused and reported as 64); bit 3 (step
+ * 3, with bits 0 and 1) the transformed flux of step 6 computed in the same
+ * epilogue, so that step 6 launches nothing. */
 fr_status fr_measure_ceiling(int32_t kind, double *value, void *hip_stream);
 fr_status fr_bench_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, int64_t N,
                         int32_t mbw, int32_t nc, int32_t wm, int32_t batch, int32_t nrep,
@@ -311,9 +313,11 @@ fr_status fr_bench_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, int64_t
 fr_status fr_get_gemm_plan(const fr_ctx *ctx, int32_t block, int32_t step, int32_t *mbw,
                            int32_t *nc, int32_t *wm);
 /* fr_debug_set_plan forces the plan of right-hand-side step 1, 3, 5 or 8 of
- * `block`, or (step 13, FP64 contexts) of the adjoint's M0^T product, which
- * with a sparse-row plan also applies the reverse gradient transform (test
- * support: drives every kernel variant through the full chain): mbw > 0 a
+ * `block`, or (FP64 contexts) of the adjoint's M0^T product (step 13), which
+ * with a sparse-row plan also applies the reverse gradient transform, or of
+ * its (M1 - M3 M2)^T product (step 14), where flags 2 | 16 apply the reverse
+ * of the transformed flux in the epilogue (test support: drives every
+ * kernel variant through the full chain): mbw > 0 a
  * matrix-core plan (mbw, nc, wm) as for fr_debug_gemm;
  * mbw = 0 the sparse-row kernel with nc rows per workgroup and the flags
  * wm of fr_get_gemm_plan (fusion with bit 1 needs an operator of at most 16

@@ -42,6 +42,9 @@ const double kSparseDrop = 1e-13;
 // rows of 64 columns per workgroup and ignores NC, bit 3: with bits 0 and 1,
 // the transformed flux of step 6 fused into step 3 as well).
 const int kPlanFusedGradT = 1, kPlanFields = 2, kPlanStaged = 4, kPlanFusedFlux = 8;
+// Adjoint (M1 - M3 M2)^T product: bit 4, with bit 1, applies the reverse of
+// the transformed flux in its epilogue (the point-wise flux VJP pass goes).
+const int kPlanFusedFluxVjp = 16;
 const int kPlanFusedAll = kPlanFusedGradT | kPlanFields | kPlanFusedFlux;
 
 void apply_sparse_plan(GemmOp &op, const fr::GemmPlan &p, int nvars) {
@@ -660,6 +663,27 @@ void adj_gemm(fr_ctx *c, const GemmOp &op, const double *B1, const double *B2, d
 }
 
 // Autotune one transposed operator of the adjoint with its real operands.
+bool tfvjp_fused(const BlockRT &b) {
+  return b.t_m1.MBW == 0 && (b.t_m1.WM & (kPlanFields | kPlanFusedFluxVjp)) ==
+                               (kPlanFields | kPlanFusedFluxVjp);
+}
+
+// (M1 - M3 M2)^T lt with the reverse of the transformed flux in the
+// epilogue: the state cotangent into ulam, Qb (Navier-Stokes) over F~b.
+void adj_m1t_fused(fr_ctx *c, const BlockRT &b, const GemmOp &op, const double *u,
+                   const double *qprim, double *ulam, hipStream_t s) {
+  const int64_t N = (int64_t)c->NV * b.ld;
+  fr::GemmArgs g = gemm_args(op);
+  g.B1 = c->d_lt + b.uoff; g.ldb1 = N; g.B2 = nullptr; g.ldb2 = N;
+  g.C = c->d_ftb + b.ftoff; g.ldc = N; g.N = N;
+  g.ld = b.ld; g.nelem = b.nelem; g.rcpdjac = b.d_rcpdjac;
+  g.smat = b.d_smat; g.D = c->D; g.Nu = b.Nu;
+  g.uprim = u + b.uoff; g.qprim = c->ns && qprim ? qprim + b.ftoff : nullptr;
+  g.out = ulam + b.uoff;
+  g.gamma = c->cfg.gamma; g.mu = c->cfg.mu; g.prandtl = c->cfg.prandtl;
+  hip_check(launch_op(op, fr::PREC_F64, fr::EPI_TFVJP, g, 1, s), "adjoint gemm + flux VJP");
+}
+
 void tune_adj(fr_ctx *c, GemmOp &op, const double *B1, const double *B2, double *C, int64_t N,
               int epi, int batch, int64_t sB1, int64_t sC, hipStream_t s) {
   TuneKey key{c->prec, op.M, op.K1, op.K2, batch, 10 + epi, 0, N};
@@ -783,12 +807,74 @@ void tune_adj_m0t(fr_ctx *c, BlockRT &b, hipStream_t s) {
   }
 }
 
+// The (M1 - M3 M2)^T product followed by the flux VJP kernel, against the
+// fused plans (every field per thread, the flux VJP in the epilogue), on
+// the scratch arrays; the fastest is kept (memoised per shape).
+void tune_adj_tfvjp(fr_ctx *c, BlockRT &b, hipStream_t s) {
+  GemmOp &op = b.t_m1;
+  if (!op.sp.colidx || op.sp.width > FR_SPOP_GRADT_FIELDS_WMAX) return;
+  const int64_t N = (int64_t)c->NV * b.ld;
+  TuneKey key{c->prec, op.M, op.K1, op.K2, 1, 10 + fr::EPI_TFVJP, c->ns ? 1 : 0, N};
+  fr::GemmPlan best{op.MBW, op.NC, op.WM};
+  auto it = g_tuned.find(key);
+  if (it != g_tuned.end()) {
+    best = it->second;
+  } else {
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "event");
+    hip_check(hipEventCreate(&e1), "event");
+    fr::AdjPointArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.ndims = c->D; a.nvars = c->NV; a.nupts = b.Nu; a.ld = b.ld; a.nelem = b.nelem;
+    a.smat = b.d_smat; a.rcpdjac = b.d_rcpdjac; a.u = c->d_stage + b.uoff;
+    a.q = c->ns ? (const double *)c->d_ft + b.ftoff : nullptr;
+    a.fb = c->d_ftb + b.ftoff; a.ulam = c->d_w + b.uoff;
+    a.gamma = c->cfg.gamma; a.mu = c->cfg.mu; a.prandtl = c->cfg.prandtl;
+    std::vector<fr::GemmPlan> cands{best};
+    for (int rpg : {1, 2, 4, 8, 16})
+      cands.push_back(fr::GemmPlan{0, rpg, kPlanFields | kPlanFusedFluxVjp});
+    float best_ms = 1e30f;
+    for (const fr::GemmPlan &p : cands) {
+      GemmOp trial = op;
+      trial.MBW = p.MBW; trial.NC = p.NC; trial.WM = p.WM;
+      if (p.MBW == 0) apply_sparse_plan(trial, p, c->NV);
+      const bool fused = p.MBW == 0 && (p.WM & kPlanFusedFluxVjp);
+      auto run = [&]() {
+        if (fused) {
+          adj_m1t_fused(c, b, trial, c->d_stage, (const double *)c->d_ft, c->d_w, s);
+        } else {
+          adj_gemm(c, trial, c->d_lt + b.uoff, nullptr, c->d_ftb + b.ftoff, N, fr::EPI_STORE, 1,
+                   0, 0, s);
+          hip_check(fr::launch_tflux_vjp(a, c->ns, s), "tflux_vjp");
+        }
+      };
+      float ms = 0;
+      for (int w = 0; w < 2; ++w) run();
+      hip_check(hipEventRecord(e0, s), "record");
+      for (int w = 0; w < 5; ++w) run();
+      hip_check(hipEventRecord(e1, s), "record");
+      hip_check(hipEventSynchronize(e1), "sync");
+      hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+      if (ms < best_ms) { best_ms = ms; best = p; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    g_tuned[key] = best;
+  }
+  if (best.MBW != op.MBW || best.NC != op.NC || best.WM != op.WM) {
+    op.d_A = best.MBW ? pack_upload(c, op, best, s, true) : nullptr;
+    op.MBW = best.MBW; op.NC = best.NC; op.WM = best.WM;
+    if (best.MBW == 0) apply_sparse_plan(op, best, c->NV);
+  }
+}
+
 void tune_adjoint_ops(fr_ctx *c, hipStream_t s) {
   const int D = c->D, NV = c->NV;
   for (auto &b : c->blocks) {
     const int64_t N = (int64_t)NV * b.ld;
     tune_adj(c, b.t_m3, c->d_lt + b.uoff, nullptr, c->d_ufb + b.ufoff, N, fr::EPI_STORE, 1, 0, 0, s);
     tune_adj(c, b.t_m1, c->d_lt + b.uoff, nullptr, c->d_ftb + b.ftoff, N, fr::EPI_STORE, 1, 0, 0, s);
+    tune_adj_tfvjp(c, b, s);
     if (c->ns) {
       tune_adj_m0t(c, b, s);
       tune_adj(c, b.t_m6, c->d_ftb + b.ftoff, nullptr, c->d_qfb + b.qfoff, N, fr::EPI_STORE, 1, 0,
@@ -819,9 +905,12 @@ void rhs_adjoint_chain(fr_ctx *c, const double *u, const double *lam, double *ul
     const int64_t N = (int64_t)NV * b.ld;
     hip_check(fr::launch_negscale(NV, b.Nu, b.ld, b.nelem, b.d_rcpdjac, lam + b.uoff,
                                   c->d_lt + b.uoff, s), "negscale");
-    // D~b = M3^T lt ; F~b = (M1 - M3 M2)^T lt
+    // D~b = M3^T lt ; F~b = (M1 - M3 M2)^T lt (or, fused, the flux VJP of F~b)
     adj_gemm(c, b.t_m3, c->d_lt + b.uoff, nullptr, c->d_ufb + b.ufoff, N, fr::EPI_STORE, 1, 0, 0, s);
-    adj_gemm(c, b.t_m1, c->d_lt + b.uoff, nullptr, c->d_ftb + b.ftoff, N, fr::EPI_STORE, 1, 0, 0, s);
+    if (tfvjp_fused(b))
+      adj_m1t_fused(c, b, b.t_m1, u, ft, ulam, s);
+    else
+      adj_gemm(c, b.t_m1, c->d_lt + b.uoff, nullptr, c->d_ftb + b.ftoff, N, fr::EPI_STORE, 1, 0, 0, s);
   }
   {
     fr::AdjPairArgs pa = adj_pair_args(c);
@@ -835,7 +924,7 @@ void rhs_adjoint_chain(fr_ctx *c, const double *u, const double *lam, double *ul
     a.smat = b.d_smat; a.rcpdjac = b.d_rcpdjac; a.u = u + b.uoff; a.q = ft ? ft + b.ftoff : nullptr;
     a.fb = c->d_ftb + b.ftoff; a.ulam = ulam + b.uoff;
     a.gamma = c->cfg.gamma; a.mu = c->cfg.mu; a.prandtl = c->cfg.prandtl;
-    hip_check(fr::launch_tflux_vjp(a, c->ns, s), "tflux_vjp");
+    if (!tfvjp_fused(b)) hip_check(fr::launch_tflux_vjp(a, c->ns, s), "tflux_vjp");
     const int64_t N = (int64_t)NV * b.ld;
     if (c->ns) {
       adj_m0t_transform(c, b, b.t_m0, s);
@@ -1764,8 +1853,9 @@ fr_status fr_debug_set_plan(fr_ctx *c, int32_t block, int32_t step, int32_t mbw,
   if (!c || block < 0 || block >= (int)c->blocks.size()) return FR_EINVAL;
   BlockRT &b = c->blocks[block];
   hipStream_t s = (hipStream_t)hip_stream;
-  if (step == 13) {
-    // M0^T of the adjoint (set up and tuned first, so the plan sticks)
+  if (step == 13 || step == 14) {
+    // M0^T, or (M1 - M3 M2)^T, of the adjoint (set up and tuned first, so
+    // the plan sticks)
     if (c->prec != FR_FP64) return fail(c, FR_EUNSUPPORTED, "the adjoint is FP64 only");
     try {
       ensure_adjoint(c, s);
@@ -1778,7 +1868,7 @@ fr_status fr_debug_set_plan(fr_ctx *c, int32_t block, int32_t step, int32_t mbw,
     }
   }
   GemmOp *op = step == 1 ? &b.m0 : step == 3 ? &b.s3 : step == 5 ? &b.m5 : step == 8 ? &b.s8
-               : step == 13 ? &b.t_m0 : nullptr;
+               : step == 13 ? &b.t_m0 : step == 14 ? &b.t_m1 : nullptr;
   if (!op || (!c->ns && (step == 3 || step == 5))) return fail(c, FR_EINVAL, "no such step");
   try {
     fr::GemmPlan p{mbw, nc, wm};
@@ -1789,8 +1879,10 @@ fr_status fr_debug_set_plan(fr_ctx *c, int32_t block, int32_t step, int32_t mbw,
     } else {
       if (!op->sp.colidx) throw Fail{FR_EINVAL, "operator has no sparse-row form"};
       const bool staged = wm & kPlanStaged, fused = wm & kPlanFusedGradT;
-      const bool fflux = wm & kPlanFusedFlux;
-      if (nc < 1 || wm < 0 || wm > 15 || (fused && step != 3) ||
+      const bool fflux = wm & kPlanFusedFlux, fvjp = wm & kPlanFusedFluxVjp;
+      if (nc < 1 || wm < 0 || wm > 31 || (fused && step != 3) ||
+          (fvjp && (step != 14 || wm != (kPlanFields | kPlanFusedFluxVjp) ||
+                    op->sp.width > FR_SPOP_GRADT_FIELDS_WMAX)) ||
           (fflux && (wm & ~kPlanStaged) != kPlanFusedAll) || (fflux && staged) ||
           (fflux && op->sp.width > FR_SPOP_GRADT_FIELDS_WMAX) ||
           (staged && ((wm & kPlanFields) || !staged_ok(*op, fused, c->D))) ||

@@ -23,10 +23,16 @@ enum GemmEpi {
                    // batch slices is added to C, then the D sums of one point
                    // are transformed by J^-1 = S / det J (the reverse of the
                    // gradient transform); padding columns are only added
-  EPI_GRADTF = 6   // sparse-row kernel, every field of an element per thread
+  EPI_GRADTF = 6,  // sparse-row kernel, every field of an element per thread
                    // (Navier-Stokes): EPI_GRADT, then the transformed flux
                    // F~ = S f(u, Q) of the point from the stored Q and the
                    // state (panel 2) into fout; padding columns get 0
+  EPI_TFVJP = 7    // sparse-row kernel, every field of an element per thread
+                   // (adjoint, FP64): the D rows d Nu + rho of one point are
+                   // F~b; then fb = S^T F~b and the reverse of the flux,
+                   // ub = (df/du)^T fb into `out` (the state cotangent) and,
+                   // with a primal Q (qprim), qb = (df/dq)^T fb into C;
+                   // padding columns get 0
 };
 
 enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };
@@ -59,6 +65,7 @@ struct GemmArgs {
   RkCoef rk;
   const double *smat; int D; int Nu;          // EPI_GRADT: S = adj J [D][D][Nu][ld]
   void *fout; double gamma, mu, prandtl;      // EPI_GRADTF: F~ (type TC, layout of C)
+  const double *uprim, *qprim;                // EPI_TFVJP: primal u and Q (Q null: Euler)
 };
 
 // Pack A (M x (K1 + K2), row-major, panel 2 columns follow panel 1) into the

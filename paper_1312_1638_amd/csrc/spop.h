@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
   const int64_t t = tile * 256 + threadIdx.x;
   if (t >= (F == 1 ? g.N : g.ld)) return;
   const int r0 = rgrp * rpg;
-  constexpr bool GT = EPI == EPI_GRADT || EPI == EPI_GRADTF;
+  constexpr bool GT = EPI == EPI_GRADT || EPI == EPI_GRADTF || EPI == EPI_TFVJP;
   const int rmax = GT ? g.Nu : g.M;  // EPI_ADDT: M = Nu
   const int r1 = r0 + rpg < rmax ? r0 + rpg : rmax;
   const TB1 *__restrict__ B1b = (const TB1 *)g.B1 + (int64_t)blockIdx.y * g.sB1;
@@ -134,7 +134,66 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
     }
     return;
   }
-  if constexpr (GT) {
+  if constexpr (EPI == EPI_TFVJP) {
+    // rows d Nu + rho, d < DG, of the points rho in [r0, r1): F~b of the point
+    static_assert(F == DG + 2, "the flux needs every field of a point");
+    const int64_t plane = (int64_t)g.Nu * g.ld;
+    double *C = (double *)g.C;
+    for (int rho = r0; rho < r1; ++rho) {
+      T Fb[DG][F];
+#pragma unroll
+      for (int d = 0; d < DG; ++d) row_product(d * g.Nu + rho, Fb[d]);
+      const int64_t pt = (int64_t)rho * g.ld + n;
+      const int64_t up = (int64_t)rho * g.ldc + t;
+      if (live) {
+        double S[DG][DG];
+#pragma unroll
+        for (int i = 0; i < DG; ++i)
+#pragma unroll
+          for (int jj = 0; jj < DG; ++jj) S[i][jj] = g.smat[(i * DG + jj) * plane + pt];
+        double u[F], fb[DG][F], ub[F];
+#pragma unroll
+        for (int a = 0; a < F; ++a) { u[a] = g.uprim[up + a * fs]; ub[a] = 0; }
+#pragma unroll
+        for (int jj = 0; jj < DG; ++jj)
+#pragma unroll
+          for (int a = 0; a < F; ++a) {
+            double sj = 0;
+#pragma unroll
+            for (int i = 0; i < DG; ++i) sj += S[i][jj] * (double)Fb[i][a];
+            fb[jj][a] = sj;
+          }
+        inviscid_flux_vjp<DG>(u, g.gamma, fb, 0.0, nullptr, ub);
+        if (g.qprim) {
+          double q[DG][F], qb[DG][F], nfb[DG][F];
+#pragma unroll
+          for (int jj = 0; jj < DG; ++jj)
+#pragma unroll
+            for (int a = 0; a < F; ++a) {
+              q[jj][a] = g.qprim[(int64_t)(jj * g.Nu + rho) * g.ldc + t + a * fs];
+              qb[jj][a] = 0;
+              nfb[jj][a] = -fb[jj][a];
+            }
+          viscous_flux_vjp<DG>(u, q, g.gamma, g.mu, g.prandtl, nfb, ub, qb);
+#pragma unroll
+          for (int jj = 0; jj < DG; ++jj)
+#pragma unroll
+            for (int a = 0; a < F; ++a) C[(int64_t)(jj * g.Nu + rho) * g.ldc + t + a * fs] = qb[jj][a];
+        }
+#pragma unroll
+        for (int a = 0; a < F; ++a) g.out[up + a * fs] = ub[a];
+      } else {
+#pragma unroll
+        for (int a = 0; a < F; ++a) {
+          g.out[up + a * fs] = 0.0;
+          if (g.qprim)
+#pragma unroll
+            for (int jj = 0; jj < DG; ++jj) C[(int64_t)(jj * g.Nu + rho) * g.ldc + t + a * fs] = 0.0;
+        }
+      }
+    }
+    return;
+  } else if constexpr (GT) {
     // rows d Nu + rho, d < DG, of the points rho in [r0, r1) (r1 <= Nu)
     static_assert(EPI != EPI_GRADTF || F == DG + 2, "the flux needs every field of a point");
     const int64_t plane = (int64_t)g.Nu * g.ld;
@@ -308,6 +367,10 @@ hipError_t spop_gradt_t(const GemmArgs &g, const SparseOp &sp, hipStream_t s) {
   if constexpr (EPI == EPI_GRADTF) {
     if (F == 1 || !g.fout || g.fout == g.C) return hipErrorInvalidValue;
   }
+  if constexpr (EPI == EPI_TFVJP) {
+    if (F == 1 || sizeof(T) != 8 || !g.uprim || !g.out || g.K2 != 0 || g.K1 != g.Nu)
+      return hipErrorInvalidValue;
+  }
   switch (sp.width) {
 #define FR_W(W_)                                                               \
   case W_:                                                                     \
@@ -362,6 +425,14 @@ hipError_t launch_spop_f(int prec, int epi, const GemmArgs &g, const SparseOp &s
       if (prec == PREC_F64) return spop_gradt_t<double, F, EPI_GRADTF>(g, sp, s);
       if (prec == PREC_F32) return spop_gradt_t<float, F, EPI_GRADTF>(g, sp, s);
       return hipErrorInvalidValue;
+    }
+  }
+  if (epi == EPI_TFVJP) {
+    if constexpr (F == 1) {
+      return hipErrorInvalidValue;
+    } else {
+      if (batch != 1 || prec != PREC_F64) return hipErrorInvalidValue;
+      return spop_gradt_t<double, F, EPI_TFVJP>(g, sp, s);
     }
   }
   if (prec == PREC_F64) {

@@ -162,6 +162,40 @@ def test_gradient_through_steps_matches_oracle_complex_step():
         assert abs(got - ref) <= 1e-10 * abs(ref)
 
 
+@pytest.mark.parametrize("name", ["tgv3_p4", "mixed5_p2_ns", "curved4_p4", "vortex7_p3"])
+def test_fused_flux_vjp_matches_separate_kernel(name):
+    """The adjoint's (M1 - M3 M2)^T product with the flux VJP in its
+    epilogue, against the product followed by the flux VJP kernel (and the
+    dot-product identity for the fused form); blocks without a sparse form
+    (dense triangles) keep their plan."""
+    import paper_1312_1638_amd as P
+    w = C.SMALL[name]()
+    d = Discretisation(w)
+    u = _off_kink(d, d.initial_state(w))
+    lam = _rand_like(u, 2)
+    s = C.solver_for(w)
+    out = []
+    for wm in (2, 18):
+        forced = 0
+        for bi in range(len(w.mesh.blocks)):
+            try:
+                s.set_plan(bi, 14, (0, 2, wm))
+                forced += 1
+            except P.FRError:
+                assert w.mesh.blocks[bi].etype == "tri"
+        assert forced > 0
+        out.append(s.unpack(s.rhs_adjoint(s.pack(u), s.pack(lam))))
+    diff = C.rel_l2(out[1], out[0])
+    v = _rand_like(u, 1)
+    Jv = jvp(d, u, v)
+    lhs, rhs = _dot(Jv, lam), _dot(v, out[1])
+    scale = _norm(Jv) * _norm(lam)
+    print(f"{name}: fused vs separate flux VJP rel L2 {diff:.2e}; dot product rel "
+          f"{abs(lhs - rhs) / scale:.2e}")
+    assert diff < 1e-13
+    assert abs(lhs - rhs) <= 1e-13 * scale
+
+
 def test_stash_budget_leaves_the_gradient_unchanged():
     """Segments kept resident or replayed from checkpoints (budget 0, room
     for two segments with a short last one, everything resident) give the
