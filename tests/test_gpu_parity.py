@@ -161,6 +161,28 @@ def test_fused_gradient_transform_fp32(variant):
     assert err < tol
 
 
+@pytest.mark.parametrize("name", ["vortex1_p3", "tgv1_p3", "tgv1_p4_ns_fp32"])
+def test_single_element_periodic_mesh(name):
+    """The degenerate mesh: one element whose faces pair with its own
+    opposite faces (15 padding columns of the 16-wide layout)."""
+    if name == "vortex1_p3":
+        w, prec = configs.vortex_quads(1, 3), "fp64"
+    elif name == "tgv1_p3":
+        w, prec = configs.taylor_green_hexes(1, 3), "fp64"
+    else:
+        w, prec = configs.taylor_green_hexes(1, 4), "fp32"
+    d, s, u = _both(w, prec)
+    stated = 1e-12 if prec == "fp64" else 1e-5
+    tol, ext, floor = C.floor_tolerance(d, u, stated, 1.0 if prec == "fp64" else C.FP32_OVER_FP64)
+    err = C.rel_l2(s.unpack(s.rhs(s.pack(u))), ext)
+    t = s.pack(u)
+    dt = 1e-4
+    s.step(t, dt, 3)
+    eu = C.rel_l2(s.unpack(t), d.rk4(u, dt, 3))
+    print(f"{name}: rhs rel L2 {err:.2e} (tol {tol:.2e}), u(3) {eu:.2e}")
+    assert err < tol and eu < (1e-12 if prec == "fp64" else 1e-5)
+
+
 def test_rhs_alias_in_place():
     w = C.SMALL["mixed5_p2_ns"]()
     d, s, u = _both(w)

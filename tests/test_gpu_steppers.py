@@ -174,6 +174,28 @@ def test_dopri5_batched_problems():
     assert len(set(cnt[:, 0])) > 1
 
 
+def test_dopri5_problems_that_stand_still():
+    """A batch where one problem starts with dt = 0 and one is already past
+    its end time: both keep their state bitwise and count no attempt, while
+    the third integrates as the oracle does."""
+    wb = configs.batched_vortices(nproblems=3, seed=21, nmin=9, nmax=30, nsteps=1)
+    h0 = np.array([0.01, 0.0, 0.01])
+    tend = np.array([0.05, 0.05, -1.0])
+    d, s, dp, dev = _dopri_pair(wb, h0, tend, 1e-8, 1e-8)
+    before = [x.copy() for x in s.unpack(dev["u"])]
+    for _ in range(10):
+        _attempt_both(s, dp, dev, 1e-8, 1e-8)
+        _check_same(s, dp, dev)
+    after = s.unpack(dev["u"])
+    cnt = dev["counts"].cpu().numpy()
+    assert cnt[1].sum() == 0 and cnt[2].sum() == 0 and cnt[0, 0] > 0
+    prob = S.element_problems(d)
+    for b, (x0, x1, pb) in enumerate(zip(before, after, prob)):
+        still = np.isin(pb, [1, 2])
+        assert np.array_equal(x0[:, :, still], x1[:, :, still])
+    assert dev["t"].cpu().numpy()[1] == 0.0 and dev["t"].cpu().numpy()[2] == 0.0
+
+
 def test_dopri5_without_end_time():
     w = C.SMALL["vortex7_p3"]()
     d, s, dp, dev = _dopri_pair(w, 1e-3, None, 1e-9, 1e-9)
