@@ -316,7 +316,7 @@ def main():
                     help="diagnostic: run only the adjoint cost measurement and print it")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(halo exchange across GPUs is designed, not built).", file=sys.stderr)
         sys.exit(2)
 

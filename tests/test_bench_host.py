@@ -1,0 +1,46 @@
+"""Host-side checks of bench.py's contract that need no device: more than
+one GPU is refused with a message, and the algorithmic byte model charges
+each step's arrays once (against a hand count for the default workload)."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_byte_model_of_the_fused_gradient_step():
+    """Step 3 with steps 4 and 6 fused, TGV 16^3 p=3 FP64: C^f (96 flux points)
+    and U (64 points) read per state column, S (9) and 1/J per point, Q and
+    F~ (3 x 64 each) written per column."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    class Blk:
+        etype, order = "hex", 3
+
+    class Mesh:
+        blocks = [Blk()]
+
+    class S:
+        ndims, nvars, system = 3, 5, "ns"
+        blocks = [dict(nelem=4096, nupts=64)]
+        mesh = Mesh()
+        nfpts = {("hex", 3): 96}
+        nnz = {("hex", 3): dict(M0=384, M3=384, M4p=768, M6=384, M1p=1152)}
+        fused_gradt = [True]
+        fused_flux = [True]
+        npairs = 0
+
+    byts, _ = bench.step_model(S, 3, 8)
+    cols, ne, nu = 5 * 4096, 4096, 64
+    expect = cols * (96 + 64 + 3 * 64) * 8 + 10 * nu * ne * 8 + 3 * nu * cols * 8
+    assert byts == expect
+    assert abs(byts - 110100480) < 1          # the figure bench.py reports
+    assert bench.step_model(S, 6, 8)[0] == 0   # step 6 costs nothing when fused
