@@ -85,7 +85,7 @@ typedef struct {          /* one element block: one type, order, geometry order 
   int32_t geom_order;     /* 1 (straight) or 2 (quadratic)                     */
   int32_t correction;     /* fr_correction; SD and HU on triangles give
                              FR_EUNSUPPORTED, other values FR_EINVAL           */
-  int64_t nelem;          /* >= 1                                              */
+  int64_t nelem;          /* >= 1, and N_V nelem < 2^29 (split larger meshes) */
   const double *nodes;    /* HOST [nelem][nnodes][ndims]; nodes tensor-
                              lexicographic (xi fastest) on {-1,1} or {-1,0,1}
                              for quads/hexes; triangles v0, v1, v2 then the

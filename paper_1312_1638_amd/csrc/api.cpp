@@ -1226,6 +1226,10 @@ fr_status fr_setup_mesh_bc(const fr_config *cfg, int32_t nblocks, const fr_block
     for (int bi = 0; bi < nblocks; ++bi) {
       const fr_block &B = blocks[bi];
       if (B.nelem < 1 || !B.nodes) throw Fail{FR_EINVAL, "block without elements or nodes"};
+      // one row of a block's arrays (N_V ld values) is addressed with 32-bit
+      // byte offsets by the operator kernels
+      if ((int64_t)NV * round_up(B.nelem, 16) >= ((int64_t)1 << 29))
+        throw Fail{FR_EINVAL, "block too large: N_V * nelem must stay below 2^29; split it"};
       if ((B.etype == FR_HEX) != (D == 3) || B.etype < 0 || B.etype > 2)
         throw Fail{FR_EINVAL, "element type does not match ndims"};
       auto key = std::make_tuple(B.etype, B.order, B.correction);

@@ -28,6 +28,23 @@
 
 namespace fr {
 
+// Word 3 of a buffer resource for untyped (raw) loads on CDNA: only a
+// non-zero data format (32-bit) is required; no swizzle, no stride.
+constexpr int kRawBufferWord3 = 0x00020000;
+
+// One value at byte offset `off` of the row whose address the resource `rs`
+// holds.  The row address is wave-uniform (scalar registers) and the offset
+// is the lane's, so a gather costs one instruction and no vector address
+// arithmetic.
+template <typename TB>
+__device__ inline TB load_row(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  if constexpr (sizeof(TB) == 8) {
+    return __builtin_bit_cast(TB, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0));
+  } else {
+    return __builtin_bit_cast(TB, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
+  }
+}
+
 template <typename T, int EPI, int W, typename TB1, typename TB2, typename TC, int DG, int F>
 __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
                                                    const int32_t *__restrict__ colidx,
@@ -56,10 +73,20 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
   double dtv = 0;
   if (EPI == EPI_RK && live) dtv = g.dt[g.prob ? g.prob[n] : 0];
   const int K1 = g.K1;
-  const int64_t ldb1 = g.ldb1, ldb2 = g.ldb2, fs = F == 1 ? 0 : g.ld;
-  // B2 addressed from B1 by an element offset (same element type), so that
-  // picking the panel of an entry is a uniform select, not a branch
-  const int64_t d2 = ((intptr_t)g.B2 - (intptr_t)B1b) / (int64_t)sizeof(TB1);
+  // both panels have the row stride ldb, and N <= ldb < 2^29 (checked by
+  // the launcher): a row of B spans under 4 GiB
+  const int32_t ldb = (int32_t)g.ldb1;
+  const int64_t fs = F == 1 ? 0 : g.ld;
+  // B2 addressed from B1 by an element offset (same element type): row k of
+  // the stacked operand [B1; B2] starts at B1 + k ldb in panel 1 and at
+  // B1 + d2k + k ldb in panel 2, so the panel of an entry costs one uniform
+  // select, not a branch and a second 64-bit product
+  const int64_t d2k = ((intptr_t)g.B2 - (intptr_t)B1b) / (int64_t)sizeof(TB1) - (int64_t)K1 * ldb;
+  const uint32_t rsb = (uint32_t)ldb * (uint32_t)sizeof(TB1);  // row stride, bytes
+  // byte offset of field a's column within a row of B
+  uint32_t toff[F];
+#pragma unroll
+  for (int a = 0; a < F; ++a) toff[a] = (uint32_t)((t + a * fs) * (int64_t)sizeof(TB1));
 
   // acc[a] = row `row` of A times field a's column (of panel 1 shifted by
   // boff elements: a batch slice)
@@ -69,19 +96,24 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
     int32_t kc[W];
 #pragma unroll
     for (int e = 0; e < W; ++e) kc[e] = ci[e];
+    // row 0 of [B1; B2] as seen from each panel (panel 1 shifted by boff)
+    const char *base1 = (const char *)B1b + boff * (int64_t)sizeof(TB1);
+    const char *base2 = (const char *)B1b + d2k * (int64_t)sizeof(TB1);
     T b[F][W];
 #pragma unroll
     for (int e = 0; e < W; ++e) {
       const int k = kc[e];
       if constexpr (sizeof(TB1) == sizeof(TB2)) {
-        const int64_t off = k < K1 ? (int64_t)k * ldb1 + boff : d2 + (int64_t)(k - K1) * ldb2;
+        const char *rowp = (k < K1 ? base1 : base2) + (uint64_t)(uint32_t)k * rsb;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void *)rowp, 0, -1, kRawBufferWord3);
 #pragma unroll
-        for (int a = 0; a < F; ++a) b[a][e] = (T)B1[off + a * fs];
+        for (int a = 0; a < F; ++a) b[a][e] = (T)load_row<TB1>(rs, toff[a]);
       } else {
 #pragma unroll
         for (int a = 0; a < F; ++a)
-          b[a][e] = k < K1 ? (T)B1[(int64_t)k * ldb1 + a * fs]
-                           : (T)B2[(int64_t)(k - K1) * ldb2 + a * fs];
+          b[a][e] = k < K1 ? (T)B1[(int64_t)k * ldb + a * fs]
+                           : (T)B2[(int64_t)(k - K1) * ldb + a * fs];
       }
     }
 #pragma unroll
@@ -225,7 +257,7 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
           }
         if constexpr (EPI == EPI_GRADTF) {
           // the state of the point is panel 2 (u, rows rho of every field)
-          const double *__restrict__ up = (const double *)g.B2 + (int64_t)rho * ldb2 + t;
+          const double *__restrict__ up = (const double *)g.B2 + (int64_t)rho * ldb + t;
           double u[F], f[DG][F], fv[DG][F], p, v[DG];
 #pragma unroll
           for (int a = 0; a < F; ++a) u[a] = up[a * fs];

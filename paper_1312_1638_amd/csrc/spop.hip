@@ -9,6 +9,11 @@ hipError_t launch_spop(int prec, int epi, const GemmArgs &g, const SparseOp &sp,
                        hipStream_t s) {
   if (g.N <= 0) return hipSuccess;
   if (sp.rpg < 1) return hipErrorInvalidValue;
+  // one row stride for both panels, and the N columns within one row of B
+  // (ldb FP64 values, under 4 GiB): a column's byte offset fits 32 bits
+  if (g.ldb1 <= 0 || g.ldb1 >= ((int64_t)1 << 29) || g.N > g.ldb1 ||
+      (g.K2 > 0 && g.ldb2 != g.ldb1))
+    return hipErrorInvalidValue;
   if (sp.fields == 1) return launch_spop_f<1>(prec, epi, g, sp, batch, s);
   if (sp.fields == 4) return launch_spop_fields4(prec, epi, g, sp, batch, s);
   if (sp.fields == 5) return launch_spop_fields5(prec, epi, g, sp, batch, s);
