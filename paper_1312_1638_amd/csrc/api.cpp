@@ -206,6 +206,13 @@ T *dev_upload(fr_ctx *c, const T *h, size_t n, hipStream_t s) {
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// One row of a block's arrays (N_V ld values) is addressed with 32-bit byte
+// offsets by the operator kernels, so it must span under 4 GiB.
+bool block_too_large(const fr_block &B, int nvars) {
+  return (int64_t)nvars * round_up(B.nelem, 16) >= ((int64_t)1 << 29);
+}
+const char *const kBlockTooLarge = "block too large: N_V * nelem must stay below 2^29; split it";
+
 void *pack_upload(fr_ctx *c, const GemmOp &op, fr::GemmPlan p, hipStream_t s, bool track) {
   const bool bf = c->prec == FR_BF16X3;
   const int64_t n = bf ? fr::gemm_pack_size_bf16(op.M, op.K1, op.K2, p.MBW, p.WM)
@@ -1226,10 +1233,7 @@ fr_status fr_setup_mesh_bc(const fr_config *cfg, int32_t nblocks, const fr_block
     for (int bi = 0; bi < nblocks; ++bi) {
       const fr_block &B = blocks[bi];
       if (B.nelem < 1 || !B.nodes) throw Fail{FR_EINVAL, "block without elements or nodes"};
-      // one row of a block's arrays (N_V ld values) is addressed with 32-bit
-      // byte offsets by the operator kernels
-      if ((int64_t)NV * round_up(B.nelem, 16) >= ((int64_t)1 << 29))
-        throw Fail{FR_EINVAL, "block too large: N_V * nelem must stay below 2^29; split it"};
+      if (block_too_large(B, NV)) throw Fail{FR_EINVAL, kBlockTooLarge};
       if ((B.etype == FR_HEX) != (D == 3) || B.etype < 0 || B.etype > 2)
         throw Fail{FR_EINVAL, "element type does not match ndims"};
       auto key = std::make_tuple(B.etype, B.order, B.correction);
@@ -1669,6 +1673,7 @@ fr_status fr_check_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *b
     for (int bi = 0; bi < nblocks; ++bi) {
       const fr_block &B = blocks[bi];
       if (B.nelem < 1 || !B.nodes) return fail(nullptr, FR_EINVAL, "block without elements");
+      if (block_too_large(B, D + 2)) return fail(nullptr, FR_EINVAL, kBlockTooLarge);
       if ((B.etype == FR_HEX) != (D == 3) || B.etype < 0 || B.etype > 2)
         return fail(nullptr, FR_EINVAL, "element type does not match ndims");
       auto key = std::make_tuple(B.etype, B.order, B.correction);

@@ -163,3 +163,21 @@ def test_solver_refuses_without_device():
         pytest.skip("a device is present")
     with pytest.raises(RuntimeError):
         P.Solver(configs.vortex_quads(3, 1).mesh)
+
+
+@pytest.mark.parametrize("ndims,etype,nelem", [(3, "hex", 1 << 27), (2, "quad", 1 << 27),
+                                               (3, "hex", 1 << 40)])
+def test_block_too_large_is_rejected(ndims, etype, nelem):
+    """The operator kernels address one row of a block (N_V ld values) with
+    32-bit byte offsets: a block with N_V nelem >= 2^29 is refused up front,
+    before its nodes are read (here they hold a single element)."""
+    import ctypes
+    L = _lib()
+    nodes = np.zeros((1, 2 ** ndims, ndims))
+    blk = P.binding.FrBlock(etype=P.binding.ETYPE[etype], order=1, geom_order=1, correction=0,
+                            nelem=nelem, nodes=nodes.ctypes.data, problem=None)
+    cfg = P.binding._config(ndims, "euler", "fp64", 1.4, 0.0, 0.72, 0.5, 0.1, 0, 1)
+    n = ctypes.c_int64()
+    st = L.fr_check_mesh(ctypes.byref(cfg), 1, ctypes.byref(blk), 0, None, ctypes.byref(n))
+    assert st == P.binding.FR_EINVAL
+    assert "too large" in L.fr_last_error(None).decode()
