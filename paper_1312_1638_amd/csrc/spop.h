@@ -77,12 +77,13 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
   // the launcher): a row of B spans under 4 GiB
   const int32_t ldb = (int32_t)g.ldb1;
   const int64_t fs = F == 1 ? 0 : g.ld;
-  // B2 addressed from B1 by an element offset (same element type): row k of
-  // the stacked operand [B1; B2] starts at B1 + k ldb in panel 1 and at
-  // B1 + d2k + k ldb in panel 2, so the panel of an entry costs one uniform
-  // select, not a branch and a second 64-bit product
-  const int64_t d2k = ((intptr_t)g.B2 - (intptr_t)B1b) / (int64_t)sizeof(TB1) - (int64_t)K1 * ldb;
+  // row k of the stacked operand [B1; B2] starts k ldb values after the
+  // base of its panel, so the panel of an entry costs one uniform select,
+  // not a branch and a second product
   const uint32_t rsb = (uint32_t)ldb * (uint32_t)sizeof(TB1);  // row stride, bytes
+  // where row 0 of [B1; B2] would start if B2 were panel 1 (row K1 is B2's row 0)
+  // (integer arithmetic: B2 is null for single-panel operators, never read)
+  const char *const b2row0 = (const char *)((uintptr_t)g.B2 - (uint64_t)K1 * rsb);
   // byte offset of field a's column within a row of B
   uint32_t toff[F];
 #pragma unroll
@@ -96,9 +97,11 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
     int32_t kc[W];
 #pragma unroll
     for (int e = 0; e < W; ++e) kc[e] = ci[e];
-    // row 0 of [B1; B2] as seen from each panel (panel 1 shifted by boff)
+    // row 0 of [B1; B2] as seen from each panel (panel 1 shifted by boff);
+    // base2 is formed from B2's own pointer so that the compiler keeps the two
+    // bases apart and picks one with a single 64-bit select
     const char *base1 = (const char *)B1b + boff * (int64_t)sizeof(TB1);
-    const char *base2 = (const char *)B1b + d2k * (int64_t)sizeof(TB1);
+    const char *base2 = b2row0;
     T b[F][W];
 #pragma unroll
     for (int e = 0; e < W; ++e) {
