@@ -268,7 +268,7 @@ fr_status fr_check_mesh(const fr_config *cfg, int32_t nblocks, const fr_block *b
  * concatenated) into the DEVICE buffer `out` of fr_debug_scratch_len
  * doubles.  fr_debug_gemm computes C = A [B1; B2] with the library's matrix
  * core kernel: A HOST row-major M x (K1 + K2); B1 (K1 rows), B2 (K2 rows)
- * DEVICE float64 with row stride ldb; C DEVICE (float64 for FP64, float32
+ * DEVICE float64 with row stride ldb >= N; C DEVICE (float64 for FP64, float32
  * for FP32) M x N, row stride N; N a multiple of 16.  (mbw, nc, wm) forces a
  * matrix-core tile plan; mbw = 0 with nc > 0 and wm = 0 forces the
  * sparse-row kernel, one column per thread, with nc operator rows per

@@ -1754,7 +1754,8 @@ fr_status fr_debug_scratch_len(const fr_ctx *c, int32_t stage, int64_t *len) {
 fr_status fr_debug_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, const double *A,
                         const void *B1, const void *B2, int64_t ldb, void *C, int64_t N,
                         int32_t mbw, int32_t nc, int32_t wm, void *hip_stream) {
-  if (!A || !B1 || !C || M < 1 || K1 < 1 || K2 < 0 || N < 16 || N % 16 || (K2 && !B2))
+  if (!A || !B1 || !C || M < 1 || K1 < 1 || K2 < 0 || N < 16 || N % 16 || (K2 && !B2) ||
+      ldb < N)
     return fail(nullptr, FR_EINVAL, "bad gemm arguments");
   if (prec != FR_FP64 && prec != FR_FP32 && prec != FR_BF16X3)
     return fail(nullptr, FR_EUNSUPPORTED, "precision");

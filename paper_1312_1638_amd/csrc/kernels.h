@@ -93,7 +93,8 @@ struct SparseOp {
   int rpg;                 // operator rows per workgroup row
   int fields;              // fields per thread: 1, or the field count (N = fields * ld)
 };
-#define FR_SPOP_WIDTHS(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32)
+#define FR_SPOP_WIDTHS(X) \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(10) X(12) X(14) X(15) X(16) X(18) X(20) X(21) X(24) X(32)
 // the fused gradient transform with every field in one thread holds D x N_V
 // accumulators besides the row's loads: instantiated up to this width only
 #define FR_SPOP_GRADT_FIELDS_WMAX 16

@@ -90,6 +90,43 @@ def test_sparse_row_kernel(prec):
             assert err < TOL[prec], (A.shape, rpg, err)
 
 
+@pytest.mark.parametrize("plan", [(0, 0, 0), (0, 1, 0), (0, 5, 0), (2, 2, 2)])
+def test_operands_with_a_row_stride_beyond_n(plan):
+    """B1 and B2 as column slices of wider arrays (row stride ldb > N): the
+    sparse-row kernel's byte offsets and the matrix-core loads follow ldb."""
+    import torch
+    import paper_1312_1638_amd as P
+    rng = np.random.default_rng(17)
+    m1p = P.binding.reference_operator("hex", 3, 4)
+    m3 = P.binding.reference_operator("hex", 3, 1)
+    A = np.concatenate([m3, m1p], 1)
+    K1 = m3.shape[1]
+    K2 = m1p.shape[1]
+    N, ldb = 16 * 9, 16 * 9 + 40
+    W1 = rng.standard_normal((K1, ldb))
+    W2 = rng.standard_normal((K2, ldb))
+    dB1 = torch.from_numpy(W1).cuda()[:, :N]
+    dB2 = torch.from_numpy(W2).cuda()[:, :N]
+    assert dB1.stride(0) == ldb and dB2.stride(0) == ldb
+    ref = A @ np.concatenate([W1[:, :N], W2[:, :N]])
+    got = P.binding.debug_gemm(A, dB1, dB2, "fp64", plan).cpu().numpy()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"strided operands, plan {plan}: max rel {err:.2e}")
+    assert err < TOL["fp64"]
+
+
+def test_row_stride_below_n_is_rejected():
+    """Overlapping rows (ldb < N) are refused before any launch."""
+    import torch
+    import paper_1312_1638_amd as P
+    A = np.eye(16)
+    base = torch.zeros(16 * 64, dtype=torch.float64, device="cuda")
+    B = base.as_strided((16, 32), (16, 1))
+    with pytest.raises(P.binding.FRError) as e:
+        P.binding.debug_gemm(A, B, None, "fp64", (0, 1, 0))
+    assert e.value.status == P.binding.FR_EINVAL
+
+
 def test_sparse_plan_rejected_for_dense_operator():
     import torch
     import paper_1312_1638_amd as P
