@@ -113,12 +113,13 @@ def _force_plans(s, w, variant):
 
 
 @pytest.mark.parametrize("name", ["tgv3_p4", "mixed5_p2_ns", "curved3_p2_ns", "vortex7_p3",
-                                  "mixed6_p3_euler"])
+                                  "mixed6_p3_euler", "tgv5_p3", "vortex4_p6", "mixed5_p4_euler"])
 @pytest.mark.parametrize("variant", ["mfma", "sparse", "fused", "fields", "fused_fields",
                                      "fused_flux", "staged", "staged_fused"])
 def test_every_kernel_variant(name, variant):
     """du/dt and u after 3 RK4 steps (captured graph) with every operator
-    product forced onto one kernel family."""
+    product forced onto one kernel family.  The cases cover every ELL width
+    the quad and hex operators use (2 to 21 entries per row)."""
     w = C.SMALL[name]()
     d, s, u = _both(w)
     _force_plans(s, w, variant)
