@@ -446,8 +446,9 @@ class Solver:
                                         self._stream()), self.ctx)
 
     def integrate(self, u):
-        """[nproblems, nvars + 1]: integral of every field, then kinetic energy."""
-        out = self.torch.zeros((self.nproblems, self.nvars + 1), dtype=self.torch.float64,
+        """[nproblems, nvars + 1]: integral of every field, then kinetic energy.
+        Every entry is written by the library (no zero fill needed)."""
+        out = self.torch.empty((self.nproblems, self.nvars + 1), dtype=self.torch.float64,
                                device="cuda")
         _check(self.L.fr_integrate(self.ctx, self._ptr(u), 0, out.data_ptr(), self._stream()),
                self.ctx)
