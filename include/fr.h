@@ -176,15 +176,17 @@ fr_status fr_rhs(fr_ctx *ctx, const double *u, double *dudt, void *hip_stream);
 
 /* nsteps classical RK4 steps in place on u.  dt_dev: DEVICE float64
  * [nproblems], one step size per problem (read on the device, so replays of
- * the captured step graph pick up new values). */
+ * the captured step graphs pick up new values).  Steps go out in captured
+ * graphs of 8 steps while 8 or more remain, then one step per graph; both
+ * give the same result bit for bit. */
 fr_status fr_rk_step(fr_ctx *ctx, double *u, const double *dt_dev, int32_t nsteps,
                      void *hip_stream);
 
 /* The other time steppers of the paper's functionality table (Table 1 of
  * the implementation section): forward Euler and adaptive DOPRI5.
  *
- * fr_euler_step: nsteps steps u <- u + dt R(u) in place, dt_dev as for
- * fr_rk_step (one captured graph per step).
+ * fr_euler_step: nsteps steps u <- u + dt R(u) in place, dt_dev and the
+ * captured graphs (8 steps, then one) as for fr_rk_step.
  *
  * fr_dopri5_step: `nattempts` attempts of the Dormand-Prince 5(4) pair in
  * place on u, each problem on its own.  All step-size state is DEVICE

@@ -129,10 +129,10 @@ struct fr_ctx {
   int64_t slice_len = 64;
   int32_t *d_flag = nullptr;
   int nproblems = 1;
-  // graph of one RK4 step
+  // graphs of one and of kStepsPerGraph RK4 steps (same state and dt)
   hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr, graph_k = nullptr;
+  hipGraphExec_t graph_exec = nullptr, graph_k_exec = nullptr;
   const double *graph_u = nullptr, *graph_dt = nullptr;
   // adjoint scratch (allocated on first use, FP64 contexts only)
   // arrays the right-hand-side chain uses (default: the scratch above, with
@@ -150,8 +150,8 @@ struct fr_ctx {
   // other steppers: forward Euler (one graph per step), DOPRI5 (slopes
   // k1..k7, the stage/new state y, per-problem error sums, DOF counts,
   // accept and rejection flags, one graph per attempt)
-  hipGraph_t eu_graph = nullptr;
-  hipGraphExec_t eu_exec = nullptr;
+  hipGraph_t eu_graph = nullptr, eu_graph_k = nullptr;
+  hipGraphExec_t eu_exec = nullptr, eu_exec_k = nullptr;
   const double *eu_u = nullptr, *eu_dt = nullptr;
   std::vector<double> ndof_host;
   bool dp_ready = false;
@@ -1067,20 +1067,33 @@ void rk4_step(fr_ctx *c, double *u, const double *dt, hipStream_t s) {
   }
 }
 
+void release_graph_pair(hipGraph_t &g, hipGraphExec_t &e) {
+  if (e) hipGraphExecDestroy(e);
+  if (g) hipGraphDestroy(g);
+  e = nullptr; g = nullptr;
+}
+
 void release_graph(fr_ctx *c) {
-  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
-  if (c->graph) hipGraphDestroy(c->graph);
-  c->graph_exec = nullptr; c->graph = nullptr; c->graph_u = nullptr; c->graph_dt = nullptr;
+  release_graph_pair(c->graph, c->graph_exec);
+  release_graph_pair(c->graph_k, c->graph_k_exec);
+  c->graph_u = nullptr; c->graph_dt = nullptr;
+}
+
+void release_euler_graphs(fr_ctx *c) {
+  release_graph_pair(c->eu_graph, c->eu_exec);
+  release_graph_pair(c->eu_graph_k, c->eu_exec_k);
+  c->eu_u = nullptr; c->eu_dt = nullptr;
 }
 
 void release_stepper_graphs(fr_ctx *c) {
-  if (c->eu_exec) hipGraphExecDestroy(c->eu_exec);
-  if (c->eu_graph) hipGraphDestroy(c->eu_graph);
-  c->eu_exec = nullptr; c->eu_graph = nullptr; c->eu_u = nullptr; c->eu_dt = nullptr;
+  release_euler_graphs(c);
   if (c->dp_exec) hipGraphExecDestroy(c->dp_exec);
   if (c->dp_graph) hipGraphDestroy(c->dp_graph);
   c->dp_exec = nullptr; c->dp_graph = nullptr; c->dp_key = fr_ctx::DpKey{};
 }
+
+// Steps captured into one graph when a call asks for that many or more.
+constexpr int kStepsPerGraph = 8;
 
 // Capture `body` on the context's capture stream into (graph, exec).
 template <typename F>
@@ -1457,22 +1470,24 @@ fr_status fr_rk_step(fr_ctx *c, double *u, const double *dt_dev, int32_t nsteps,
   if (!u || !dt_dev || nsteps < 0) return fail(c, FR_EINVAL, "bad rk_step arguments");
   hipStream_t s = (hipStream_t)hip_stream;
   try {
-    if (nsteps > 0 && (c->graph_u != u || c->graph_dt != dt_dev || !c->graph_exec)) {
+    if (nsteps > 0 && (c->graph_u != u || c->graph_dt != dt_dev)) {
       release_graph(c);
-      hip_check(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "capture");
-      try {
-        rk4_step(c, u, dt_dev, c->cap_stream);
-      } catch (...) {
-        hipGraph_t g;
-        hipStreamEndCapture(c->cap_stream, &g);
-        if (g) hipGraphDestroy(g);
-        throw;
-      }
-      hip_check(hipStreamEndCapture(c->cap_stream, &c->graph), "end capture");
-      hip_check(hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0), "instantiate");
       c->graph_u = u; c->graph_dt = dt_dev;
     }
-    for (int i = 0; i < nsteps; ++i) hip_check(hipGraphLaunch(c->graph_exec, s), "graph launch");
+    // groups of kStepsPerGraph steps in one graph (one launch gap per group),
+    // the rest one step per launch: the same kernels in the same order
+    int done = 0;
+    if (nsteps >= kStepsPerGraph) {
+      if (!c->graph_k_exec)
+        capture(c, c->graph_k, c->graph_k_exec, [&](hipStream_t cs) {
+          for (int k = 0; k < kStepsPerGraph; ++k) rk4_step(c, u, dt_dev, cs);
+        });
+      for (; done + kStepsPerGraph <= nsteps; done += kStepsPerGraph)
+        hip_check(hipGraphLaunch(c->graph_k_exec, s), "graph launch");
+    }
+    if (done < nsteps && !c->graph_exec)
+      capture(c, c->graph, c->graph_exec, [&](hipStream_t cs) { rk4_step(c, u, dt_dev, cs); });
+    for (; done < nsteps; ++done) hip_check(hipGraphLaunch(c->graph_exec, s), "graph launch");
     if (c->cfg.check_finite) {
       int32_t h = 0;
       hip_check(hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), s), "memset");
@@ -1493,15 +1508,22 @@ fr_status fr_euler_step(fr_ctx *c, double *u, const double *dt_dev, int32_t nste
   if (!u || !dt_dev || nsteps < 0) return fail(c, FR_EINVAL, "bad euler_step arguments");
   hipStream_t s = (hipStream_t)hip_stream;
   try {
-    if (nsteps > 0 && (c->eu_u != u || c->eu_dt != dt_dev || !c->eu_exec)) {
-      if (c->eu_exec) hipGraphExecDestroy(c->eu_exec);
-      if (c->eu_graph) hipGraphDestroy(c->eu_graph);
-      c->eu_exec = nullptr; c->eu_graph = nullptr;
-      capture(c, c->eu_graph, c->eu_exec,
-              [&](hipStream_t cs) { euler_step(c, u, dt_dev, cs); });
+    if (nsteps > 0 && (c->eu_u != u || c->eu_dt != dt_dev)) {
+      release_euler_graphs(c);
       c->eu_u = u; c->eu_dt = dt_dev;
     }
-    for (int i = 0; i < nsteps; ++i) hip_check(hipGraphLaunch(c->eu_exec, s), "graph launch");
+    int done = 0;
+    if (nsteps >= kStepsPerGraph) {
+      if (!c->eu_exec_k)
+        capture(c, c->eu_graph_k, c->eu_exec_k, [&](hipStream_t cs) {
+          for (int k = 0; k < kStepsPerGraph; ++k) euler_step(c, u, dt_dev, cs);
+        });
+      for (; done + kStepsPerGraph <= nsteps; done += kStepsPerGraph)
+        hip_check(hipGraphLaunch(c->eu_exec_k, s), "graph launch");
+    }
+    if (done < nsteps && !c->eu_exec)
+      capture(c, c->eu_graph, c->eu_exec, [&](hipStream_t cs) { euler_step(c, u, dt_dev, cs); });
+    for (; done < nsteps; ++done) hip_check(hipGraphLaunch(c->eu_exec, s), "graph launch");
   } catch (const Fail &f) {
     return fail(c, f.st, f.msg);
   }

@@ -229,3 +229,34 @@ def test_dopri5_argument_errors():
     before = dev["u"].clone()
     s.dopri5(dev["u"], dev["t"], dev["dt"], 0, 1e-9, 1e-9)
     assert bool((dev["u"] == before).all())
+
+
+@pytest.mark.parametrize("stepper", ["rk4", "euler"])
+def test_grouped_step_graphs_equal_single_steps(stepper):
+    """A call of 19 steps (two 8-step graphs, then three 1-step graphs) equals
+    19 calls of one step bit for bit, also after the device step size
+    changes between calls."""
+    w = C.SMALL["mixed5_p2_ns"]()
+    d = Discretisation(w)
+    u = C.perturbed(d, d.initial_state(w))
+    outs = []
+    for grouped in (True, False):
+        s = C.solver_for(w)
+        t = s.pack(u)
+        dt = _dev([0.05 * w.dt])
+        go = s.step if stepper == "rk4" else s.euler_step
+        for dtv in (0.05 * w.dt, 0.08 * w.dt):
+            dt.fill_(dtv)
+            if grouped:
+                go(t, dt, 19)
+            else:
+                for _ in range(19):
+                    go(t, dt, 1)
+        outs.append(t.clone())
+    assert bool((outs[0] == outs[1]).all())
+    ref = u
+    for dtv in (0.05 * w.dt, 0.08 * w.dt):
+        ref = d.rk4(ref, dtv, 19) if stepper == "rk4" else S.euler(d, ref, dtv, 19)
+    err = C.rel_l2(s.unpack(outs[0]), ref)
+    print(f"{stepper}: 2 x 19 steps, grouped == single bitwise; rel L2 vs oracle {err:.2e}")
+    assert err < 1e-12
