@@ -79,17 +79,26 @@ def flux(u, q, params):
     return f
 
 
-def rusanov(uL, uR, n, gamma):
-    """Rusanov / local Lax-Friedrichs flux (Appendix B):
-    F = n.(fL + fR)/2 + s (uL - uR)/2, s = sqrt(g (pL+pR)/(rhoL+rhoR))
-    + |n.(vL+vR)|/2.  n has shape (D, ...) and is the normal of the L side."""
-    fL = inviscid_flux(uL, gamma)
-    fR = inviscid_flux(uR, gamma)
+def rusanov_wave_speed(uL, uR, n, gamma):
+    """The wave-speed estimate s of the Rusanov flux (Appendix B): the
+    sound speed of the summed pressures over the summed densities plus half
+    the magnitude of the normal component of the summed velocities,
+    s = sqrt(g (pL+pR)/(rhoL+rhoR)) + |n.(vL+vR)|/2."""
     rL, vL, _, pL = primitives(uL, gamma)
     rR, vR, _, pR = primitives(uR, gamma)
     D = n.shape[0]
     vn = sum(n[j] * (vL[j] + vR[j]) for j in range(D))
-    s = np.sqrt(gamma * (pL + pR) / (rL + rR)) + 0.5 * cabs(vn)
+    return np.sqrt(gamma * (pL + pR) / (rL + rR)) + 0.5 * cabs(vn)
+
+
+def rusanov(uL, uR, n, gamma):
+    """Rusanov / local Lax-Friedrichs flux (Appendix B):
+    F = n.(fL + fR)/2 + s (uL - uR)/2 with s from rusanov_wave_speed.
+    n has shape (D, ...) and is the normal of the L side."""
+    fL = inviscid_flux(uL, gamma)
+    fR = inviscid_flux(uR, gamma)
+    D = n.shape[0]
+    s = rusanov_wave_speed(uL, uR, n, gamma)
     nf = sum(n[j] * (fL[j] + fR[j]) for j in range(D))
     return 0.5 * nf + 0.5 * s * (uL - uR)
 
