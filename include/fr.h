@@ -174,7 +174,10 @@ fr_status fr_get_quadrature(const fr_ctx *ctx, int32_t block, double *wj);
  * alias u. */
 fr_status fr_rhs(fr_ctx *ctx, const double *u, double *dudt, void *hip_stream);
 
-/* nsteps classical RK4 steps in place on u.  dt_dev: DEVICE float64
+/* nsteps classical RK4 steps in place on u: the classical four-stage
+ * Runge-Kutta scheme, one of the time steppers in the functionality table
+ * (Table 1) of the paper's implementation section, advancing the
+ * semi-discrete system du/dt = R(u) of eq. negdivconf.  dt_dev: DEVICE float64
  * [nproblems], one step size per problem (read on the device, so replays of
  * the captured step graphs pick up new values).  Steps go out in captured
  * graphs of 8 steps while 8 or more remain, then one step per graph; both

@@ -92,7 +92,11 @@ def lagrange_1d(nodes, x):
 
 
 # ---------------------------------------------------------------------------
-# Triangle solution points: Warburton's warp-and-blend construction (alpha=0)
+# Triangle solution points: Warburton's warp-and-blend construction (alpha=0),
+# Warburton, J. Eng. Math. 56 (2006); the steps follow the Warpfactor and
+# Nodes2D routines of Hesthaven & Warburton, "Nodal Discontinuous Galerkin
+# Methods" (2008), including its treatment of the edge points (warp kept
+# unscaled where |r| = 1).
 # ---------------------------------------------------------------------------
 def _warp_factor(n, r):
     gll = gauss_lobatto_nodes(n)

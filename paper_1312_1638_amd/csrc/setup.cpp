@@ -77,7 +77,9 @@ static std::vector<double> gauss_lobatto(int n) {
 }
 
 // Normalised Jacobi polynomial P_n^(a,b)(x), orthonormal on [-1,1] with
-// weight (1-x)^a (1+x)^b, by its three-term recurrence.
+// weight (1-x)^a (1+x)^b, by its three-term recurrence (the normalised
+// recurrence as Hesthaven & Warburton, "Nodal Discontinuous Galerkin
+// Methods", 2008, give it in their JacobiP routine).
 static ld_t jacobi(int n, int a, int b, ld_t x) {
   ld_t g0 = std::pow(2.0L, a + b + 1) / (a + b + 1) * std::tgamma((ld_t)a + 1) *
             std::tgamma((ld_t)b + 1) / std::tgamma((ld_t)a + b + 1);
@@ -198,7 +200,9 @@ static std::vector<ld_t> invert(std::vector<ld_t> A, int n) {
 // ---------------------------------------------------------------------------
 // Triangle solution points: Warburton's warp-and-blend construction with
 // blend exponent 0 (equispaced lattice warped so its edges carry
-// Gauss-Lobatto points).
+// Gauss-Lobatto points): Warburton, J. Eng. Math. 56 (2006), and the
+// Warpfactor / Nodes2D routines of Hesthaven & Warburton (2008), whose steps
+// this follows.
 // ---------------------------------------------------------------------------
 static double warp_factor(int n, double r, const std::vector<double> &gll) {
   // interpolant through equispaced nodes of (gll - equispaced), at r
