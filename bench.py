@@ -9,12 +9,18 @@ conservation / kinetic-energy integrals.  Metric: right-hand-side
 DOF-updates per second, DOF = fields x solution points x elements (the
 paper's unit), four evaluations per step.
 
-Default workload: compressible Navier-Stokes Taylor-Green vortex, Re=1600,
-Ma=0.1, 16^3 periodic hexahedra, p=3 (64 solution points each), FP64.
-Synthetic, seeded inputs; the state is resident in HBM when timing starts.
+Default workload: Euler on 48^3 curved quadratic (Q2) hexahedra over the
+unit cube, p=4 (125 solution points each, 6.9e7 DOF), a uniform stream plus
+seeded smooth perturbations, FP64 -- the largest single-GPU configuration,
+far larger than the 256 MB Infinity Cache.  Synthetic, seeded inputs; the
+state is resident in HBM when timing starts.
 
-Prints one JSON line.  Extra keys: per-step kernel times, the FP32 operator
-path, the roofline of the dominant kernel and the CPU oracle baseline.
+Prints one JSON line.  Extra keys: per-step kernel times, the FP32 and
+BF16x3 operator paths, the relative L2 error of each precision against the
+FP64 oracle on sampled elements, the roofline of the dominant kernel, the
+CPU oracle baseline (all cores and one core), the cache-resident
+Taylor-Green 16^3 workload, the other time steppers and the adjoint cost.
+Progress lines go to stderr.
 """
 import argparse
 import json
@@ -46,6 +52,11 @@ WORKLOADS = {
 
 STEP_NAMES = {1: "interp_M0", 2: "common_solution", 3: "grad_M6_M4p", 4: "grad_transform",
               5: "grad_interp_M5", 6: "transformed_flux", 7: "common_flux", 8: "div_M3_M1p"}
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
 
 PEAK_HBM = 8.0e12                                           # B/s
 PEAK_MFMA = {"fp64": 78.6e12, "fp32": 157.3e12}             # dense FLOP/s
@@ -279,25 +290,154 @@ def adjoint_ratio(P, configs, torch, n=24, nsteps=200, ckpt=20):
                 objective="kinetic energy at t_N")
 
 
-def cpu_baseline(w, nsteps):
-    """The FP64 oracle on the host: nsteps RK4 steps of the same workload."""
+def sample_elements(nelem, nsample, seed):
+    """Seeded random elements plus element 0, the last element, one inside
+    the last tile of 256 columns and the two elements either side of the
+    first boundary between XCD tile groups (2047, 2048)."""
     import numpy as np
-    from oracle import Discretisation
+    fixed = [0, nelem - 1, (nelem - 1) // 256 * 256 + min(97, (nelem - 1) % 256)]
+    if nelem > 2048:
+        fixed += [2047, 2048]
+    rnd = np.random.default_rng(seed).choice(nelem, min(nsample, nelem), replace=False)
+    return np.unique(np.concatenate([fixed, rnd]))
+
+
+def patch_workload(w, sample, rings):
+    """The sampled elements of a single-block workload plus `rings` layers
+    of face neighbours, as a workload of its own (faces on its outer
+    boundary unpaired).  Returns (workload, index of each sample in it)."""
+    import dataclasses
+    import numpy as np
+    from workloads import meshes
+    pr = w.mesh.pairs
+    le, re = pr["lelem"].astype(np.int64), pr["relem"].astype(np.int64)
+    b = w.mesh.blocks[0]
+    inside = np.zeros(b.nelem, bool)
+    inside[sample] = True
+    for _ in range(rings):
+        touch = inside[le] | inside[re]
+        inside[le[touch]] = True
+        inside[re[touch]] = True
+    elems = np.nonzero(inside)[0]
+    local = -np.ones(b.nelem, np.int64)
+    local[elems] = np.arange(len(elems))
+    sel = inside[le] & inside[re]
+    sub = pr[sel].copy()
+    sub["lelem"] = local[le[sel]]
+    sub["relem"] = local[re[sel]]
+    blk = meshes.Block(b.etype, b.order, b.geom_order, b.nodes[elems])
+    blk.correction = getattr(b, "correction", "dg")
+    mesh = meshes.Mesh(w.mesh.ndims, [blk], sub, info=dict(w.mesh.info))
+    return dataclasses.replace(w, mesh=mesh), local[sample]
+
+
+def host_info():
+    """nproc (CPUs this process may run on), the CPU model and the BLAS
+    thread pool that numpy's contractions use."""
+    info = dict(nproc=len(os.sched_getaffinity(0)), cpu_model=None, blas_threads=None)
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     try:
         from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        info["blas_threads"] = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
-        cores = 1
-    d = Discretisation(w)
-    u = d.initial_state(w)
-    t0 = time.perf_counter()
-    d.rk4(u, w.dt, nsteps)
-    el = time.perf_counter() - t0
-    dof = sum(r.nupts * g.nelem for r, g in zip(d.refs, d.geoms)) * d.nvars
-    return dict(value=4.0 * nsteps * dof / el, unit="RHS DOF-updates/s", cores=int(cores),
-                kind="oracle",
-                sample=f"{nsteps} RK4 steps ({4 * nsteps} right-hand sides) of the same "
-                       f"workload, numpy FP64 oracle, {el:.1f} s")
+        pass
+    return info
+
+
+def cpu_baseline(w, nsample, seed=33, reps=5):
+    """The FP64 oracle on the host, on a bounded sample of the workload.
+
+    Single-block meshes (the curved and Taylor-Green hexes): a patch of the
+    mesh -- `nsample` seeded elements (plus the fixed edge elements) and
+    their face neighbours (two rings for Navier-Stokes) -- and the median of
+    `reps` right-hand sides over the whole patch, with numpy's BLAS pool at
+    its default size and again limited to one thread.  The oracle's du/dt
+    on the sampled elements, which the patch computes completely, is
+    returned as well: it is the reference of every precision's error.
+    Other meshes: one RK4 step of the whole workload, timed."""
+    import numpy as np
+    from oracle import Discretisation
+    hi = host_info()
+    single_block = len(w.mesh.blocks) == 1 and getattr(w.mesh, "bcfaces", None) is None
+    out = dict(unit="RHS DOF-updates/s", kind="oracle", nproc=hi["nproc"],
+               cpu_model=hi["cpu_model"], cores=hi["blas_threads"] or 1,
+               threads_note="plain numpy FP64 reference (not a tuned CPU solver): its "
+                            "contractions run on numpy's BLAS pool (cores), the rest on one "
+                            "thread")
+    ref = None
+    if single_block:
+        sample = sample_elements(w.mesh.blocks[0].nelem, nsample, seed)
+        pw, loc = patch_workload(w, sample, 2 if w.system == "ns" else 1)
+        d = Discretisation(pw, allow_unpaired=True)
+        u = d.initial_state(pw)
+        dof = sum(r.nupts * g.nelem for r, g in zip(d.refs, d.geoms)) * d.nvars
+
+        def timed(n):
+            ts = []
+            for _ in range(n):
+                t0 = time.perf_counter()
+                r = d.rhs(u)
+                ts.append(time.perf_counter() - t0)
+            return float(np.median(ts)), r
+
+        t_all, r = timed(reps)
+        ref = dict(sample=sample, rhs=r[0][:, :, loc])
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(1):
+                t_one, _ = timed(max(3, reps // 2))
+        except Exception:
+            t_one = None
+        out.update(value=dof / t_all, value_one_core=(dof / t_one) if t_one else None,
+                   sample=f"median of {reps} right-hand sides on a patch of {d.geoms[0].nelem} "
+                          f"elements of the same mesh ({len(sample)} seeded elements and their "
+                          f"face neighbours; {dof} DOF per right-hand side), numpy FP64 oracle: "
+                          f"{t_all:.2f} s per right-hand side on the BLAS pool, "
+                          + (f"{t_one:.2f} s on one thread" if t_one else "one-thread run "
+                             "unavailable"))
+    else:
+        d = Discretisation(w)
+        u = d.initial_state(w)
+        dof = sum(r.nupts * g.nelem for r, g in zip(d.refs, d.geoms)) * d.nvars
+        t0 = time.perf_counter()
+        d.rk4(u, w.dt, 1)
+        el = time.perf_counter() - t0
+        out.update(value=4.0 * dof / el, value_one_core=None,
+                   sample=f"1 RK4 step (4 right-hand sides) of the whole workload, numpy FP64 "
+                          f"oracle, {el:.1f} s")
+    return out, ref
+
+
+def sampled_error(s, u, ref):
+    """Relative L2 error of the library's du/dt on the sampled elements
+    against the FP64 oracle's, over the whole sample and per field."""
+    import numpy as np
+    r = s.unpack(s.rhs(s.pack(u)))[0][:, :, ref["sample"]]
+    e = r - ref["rhs"]
+    whole = float(np.sqrt(np.sum(e ** 2) / np.sum(ref["rhs"] ** 2)))
+    per = np.sqrt(np.sum(e ** 2, axis=(0, 2)) / np.sum(ref["rhs"] ** 2, axis=(0, 2)))
+    return dict(rel_l2=whole, rel_l2_per_field=[float(x) for x in per],
+                sampled_elements=int(len(ref["sample"])),
+                reference="FP64 oracle on a patch around the sampled elements")
+
+
+def measure_workload(name, prec, args, P, configs, torch, with_kernels=True):
+    """Solver set-up (with the plan tuner), timed RK4 steps and per-kernel
+    launch times of one workload in one precision."""
+    progress(f"{name} {prec}: set-up and plan tuning")
+    w, s, u0 = make_solver(name, prec, P, configs)
+    dof = sum(b["nupts"] * b["nelem"] for b in s.blocks) * s.nvars
+    progress(f"{name} {prec}: {args.warmup} + {args.steps} RK4 steps")
+    el = time_steps(s, s.pack(u0), s.bench_dt, args.steps, args.warmup, torch)
+    kt = time_kernels(s, s.pack(u0), torch) if with_kernels else {}
+    return w, s, u0, dof, el, kt
 
 
 def main():
@@ -305,13 +445,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="tgv16", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-steps", type=int, default=8,
-                    help="RK4 steps of the oracle for the CPU baseline (0: skip)")
+    ap.add_argument("--workload", default="curved48", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-sample", type=int, default=256,
+                    help="seeded elements of the oracle's patch for the CPU baseline and the "
+                         "error of each precision (0: skip both)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-steppers", action="store_true",
                     help="skip the forward Euler and DOPRI5 timings")
+    ap.add_argument("--no-extra-workload", action="store_true",
+                    help="skip the cache-resident Taylor-Green 16^3 line")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="diagnostic: run only the adjoint cost measurement and print it")
     args = ap.parse_args()
@@ -329,17 +472,12 @@ def main():
         print(json.dumps(adjoint_ratio(P, configs, torch)))
         return
 
-    w, s, u0 = make_solver(args.workload, "fp64", P, configs)
-    dof = sum(b["nupts"] * b["nelem"] for b in s.blocks) * s.nvars
+    w, s, u0, dof, el, kt = measure_workload(args.workload, "fp64", args, P, configs, torch)
     npts = dof // s.nvars
-    u = s.pack(u0)
-    el = time_steps(s, u, s.bench_dt, args.steps, args.warmup, torch)
     ms = el / args.steps * 1e3
     value = 4.0 * dof * args.steps / el
 
-    # per-kernel timing and the dominant kernel's roofline
-    u = s.pack(u0)
-    kt = time_kernels(s, u, torch)
+    # the dominant kernel's roofline
     dom = max(kt, key=kt.get)
     byts, flops = step_model(s, dom, 8)
     ai = flops / byts if byts else 0.0
@@ -359,6 +497,8 @@ def main():
     from paper_1312_1638_amd.profile_report import read_traffic_table
     roof["traffic"] = read_traffic_table(ROCPROF_TRAFFIC, args.workload, STEP_NAMES[dom])
     roof["measured_hbm_triad_GBps"] = round(P.binding.measure_ceiling(0), 1)
+    roof["frac_of_measured_triad"] = (roof["achieved"] / roof["measured_hbm_triad_GBps"]
+                                      if roof["unit"] == "GB/s" else None)
     kernels = {}
     for st, t in sorted(kt.items()):
         b_, f_ = step_model(s, st, 8)
@@ -367,29 +507,51 @@ def main():
         if st in (1, 3, 5, 8):
             kernels[STEP_NAMES[st]]["plan"] = plan_name(s.gemm_plan(0, st), st)
 
+    # the oracle on a bounded sample of the same mesh: CPU baseline, and the
+    # reference of each precision's error on the sampled elements
+    cpu, ref = None, None
+    if args.cpu_sample > 0:
+        progress(f"CPU oracle on a patch of {args.cpu_sample} sampled elements")
+        cpu, ref = cpu_baseline(w, args.cpu_sample)
+    errors = {}
+    if ref is not None:
+        errors["fp64"] = sampled_error(s, u0, ref)
+
     extra = {}
+    if not args.no_steppers:
+        progress("forward Euler and DOPRI5")
+        extra["steppers"] = stepper_costs(s, u0, w.dt, args.steps, torch)
+        extra["steppers"]["rk4_ms_per_step"] = ms
+    s.close()
+    torch.cuda.empty_cache()
+
     if not args.no_fp32:
         for prec in ("fp32", "bf16x3"):
-            wr, sr, _ = make_solver(args.workload, prec, P, configs)
-            ur = sr.pack(u0)
-            elr = time_steps(sr, ur, sr.bench_dt, args.steps, args.warmup, torch)
-            ktr = time_kernels(sr, sr.pack(u0), torch)
+            wr, sr, _, _, elr, ktr = measure_workload(args.workload, prec, args, P, configs, torch)
             extra[prec] = dict(value=4.0 * dof * args.steps / elr, ms_per_step=elr / args.steps * 1e3,
                                kernels_us={STEP_NAMES[k]: round(v * 1e6, 2) for k, v in ktr.items()},
                                plans={STEP_NAMES[k]: plan_name(sr.gemm_plan(0, k), k) for k in ktr
                                       if k in (1, 3, 5, 8)})
+            if ref is not None:
+                errors[prec] = sampled_error(sr, u0, ref)
+                extra[prec]["error_vs_fp64_oracle"] = errors[prec]
             sr.close()
+            torch.cuda.empty_cache()
 
-    if not args.no_steppers:
-        extra["steppers"] = stepper_costs(s, u0, w.dt, args.steps, torch)
-        extra["steppers"]["rk4_ms_per_step"] = ms
+    if not args.no_extra_workload and args.workload != "tgv16":
+        wt, st_, _, doft, elt, ktt = measure_workload("tgv16", "fp64", args, P, configs, torch)
+        extra["tgv16"] = dict(
+            value=4.0 * doft * args.steps / elt, unit="DOF-updates/s", dtype="f64",
+            ms_per_step=elt / args.steps * 1e3, workload=wt.name,
+            note="every array fits in the 256 MB Infinity Cache: GB/s here are cache "
+                 "bandwidth, not HBM",
+            kernels_us={STEP_NAMES[k]: round(v * 1e6, 2) for k, v in ktt.items()})
+        st_.close()
+        torch.cuda.empty_cache()
 
     if not args.no_adjoint:
+        progress("adjoint cost (Taylor-Green 24^3, 200 steps)")
         extra["adjoint"] = adjoint_ratio(P, configs, torch)
-
-    cpu = None
-    if args.cpu_steps > 0:
-        cpu = cpu_baseline(w, args.cpu_steps)
 
     line = {
         "metric": "RHS DOF-updates/s",
@@ -404,17 +566,18 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "system": w.system, "elements": int(sum(b.nelem for b in w.mesh.blocks)),
+        "config": {"workload": w.name, "system": w.system,
+                   "elements": int(sum(b.nelem for b in w.mesh.blocks)),
                    "blocks": [f"{b.etype} p={b.order} x{b.nelem}" for b in w.mesh.blocks],
                    "problems": int(w.mesh.nproblems), "dof": int(dof), "solution_points": int(npts),
                    "rhs_per_step": 4, "dt": w.dt, "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "error_vs_fp64_oracle": errors.get("fp64"),
         "kernels": kernels,
         "points_per_s": value / s.nvars,
     }
     line.update(extra)
-    s.close()
     print(json.dumps(line))
 
 

@@ -21,6 +21,38 @@ def rel_l2(a, b):
     return np.sqrt(num / den)
 
 
+def field_rel_l2(a, b):
+    """Relative L2 error of each field alpha on its own, over every block:
+    ||a_alpha - b_alpha|| / ||b_alpha|| (arrays u[rho, alpha, n]).  A field
+    much smaller than the others (momentum beside the energy of a low-Mach
+    flow) is then held to the bar by itself rather than hidden in the
+    whole-vector norm."""
+    nv = b[0].shape[1]
+    num, den = np.zeros(nv), np.zeros(nv)
+    for x, y in zip(a, b):
+        num += np.sum((np.asarray(x, np.float64) - y) ** 2, axis=(0, 2))
+        den += np.sum(np.asarray(y, np.float64) ** 2, axis=(0, 2))
+    return np.sqrt(num / den)
+
+
+def field_tolerance(ref64, ext, stated, unit_ratio=1.0, factor=4.0):
+    """Per-field bar of du/dt: the stated bar, or `factor` times that field's
+    FP64 rounding floor (the oracle's per-field distance from the long-double
+    evaluation) times the unit-roundoff ratio.  Returns (tolerances, floors)."""
+    floor = field_rel_l2(ref64, ext)
+    return np.maximum(stated, factor * floor * unit_ratio), floor
+
+
+def check_fields(label, got, ref, tol):
+    """Assert every field's relative L2 error below its bar (a scalar bar
+    applies to every field); prints the errors.  Returns them."""
+    err = field_rel_l2(got, ref)
+    tol = np.broadcast_to(np.asarray(tol, np.float64), err.shape)
+    print(f"{label}: per-field rel L2 " + " ".join(f"{e:.1e}/{t:.0e}" for e, t in zip(err, tol)))
+    assert np.all(err < tol), (label, err, tol)
+    return err
+
+
 def floor_tolerance(d, u, stated, unit_ratio=1.0, factor=4.0):
     """Tolerance for du/dt of one case: the stated bar, or `factor` times
     the FP64 rounding floor of the oracle (its relative L2 distance from a
@@ -29,9 +61,17 @@ def floor_tolerance(d, u, stated, unit_ratio=1.0, factor=4.0):
     reference, floor)."""
     ref64 = d.rhs(u)
     ext = d.extended().rhs([x.astype(np.longdouble) for x in u])
-    ext = [x.astype(np.float64) for x in ext]
+    ext = Reference(x.astype(np.float64) for x in ext)
     floor = rel_l2(ref64, ext)
+    ext.field_tol, ext.field_floor = field_tolerance(ref64, ext, stated, unit_ratio, factor)
     return max(stated, factor * floor * unit_ratio), ext, floor
+
+
+class Reference(list):
+    """Per-block long-double du/dt (rounded to FP64) with the per-field bars
+    and floors that floor_tolerance derived beside the whole-vector one."""
+    field_tol = None
+    field_floor = None
 
 
 def patch(w, sample, rings):
@@ -64,10 +104,12 @@ def patch(w, sample, rings):
 def sampled_floor_tolerance(d, u, loc, stated, unit_ratio=1.0, factor=4.0):
     """floor_tolerance restricted to the elements `loc` of a patch (the only
     ones whose du/dt is complete).  Returns (tolerance, exact reference on
-    loc, floor)."""
+    loc, floor); the reference is a Reference of one block."""
     ref64 = d.rhs(u)[0][:, :, loc]
     ext = d.extended().rhs([x.astype(np.longdouble) for x in u])[0][:, :, loc].astype(np.float64)
     floor = rel_l2([ref64], [ext])
+    ext = Reference([ext])
+    ext.field_tol, ext.field_floor = field_tolerance([ref64], ext, stated, unit_ratio, factor)
     return max(stated, factor * floor * unit_ratio), ext, floor
 
 

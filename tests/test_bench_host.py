@@ -44,3 +44,36 @@ def test_byte_model_of_the_fused_gradient_step():
     assert byts == expect
     assert abs(byts - 110100480) < 1          # the figure bench.py reports
     assert bench.step_model(S, 6, 8)[0] == 0   # step 6 costs nothing when fused
+
+
+def test_sample_holds_the_edge_elements():
+    """The sampled elements always include element 0, the last element, one
+    in the last 256-column tile and both sides of the first XCD tile-group
+    boundary (2047, 2048), and are unique and in range."""
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import bench
+    for nelem in (110592, 4096, 300, 1):
+        smp = bench.sample_elements(nelem, 12, 33)
+        assert np.all(np.diff(smp) > 0) and smp[0] == 0 and smp[-1] == nelem - 1
+        assert np.any(smp >= (nelem - 1) // 256 * 256)
+        if nelem > 2048:
+            assert 2047 in smp and 2048 in smp
+
+
+def test_cpu_baseline_reference_is_the_oracle_on_the_sample():
+    """On a small curved mesh the oracle's du/dt over the patch equals the
+    full-mesh oracle's on the sampled elements, and the baseline reports the
+    host it ran on."""
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import bench
+    from oracle import Discretisation
+    from workloads import configs
+    w = configs.curved_freestream_hexes(5, 2)
+    cpu, ref = bench.cpu_baseline(w, 6, reps=1)
+    d = Discretisation(w)
+    full = d.rhs(d.initial_state(w))[0][:, :, ref["sample"]]
+    assert np.abs(ref["rhs"] - full).max() <= 1e-13 * np.abs(full).max()
+    assert cpu["value"] > 0 and cpu["nproc"] >= 1 and cpu["kind"] == "oracle"
+    assert "patch" in cpu["sample"]

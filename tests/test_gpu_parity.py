@@ -1,13 +1,16 @@
 """Parity of the HIP library (through the C ABI) with the FP64 oracle.
 
-Tolerances: relative L2 over the whole SoA vector (every block and field).
+Tolerances: relative L2 over the whole SoA vector (every block and field),
+and over each field on its own (so that a small field, such as momentum
+beside the energy of a low-Mach flow, is held to the bar by itself).
 u after RK4 steps: 1e-12 (FP64) and 1e-5 (FP32 operator path), the stated
 bars.  du/dt: the stated bar, unless the case is ill-conditioned -- du/dt is
 a small difference of flux derivatives much larger than itself (low-Mach
 energy equation, a perturbed free stream) -- in which case the bar is four
 times the case's measured FP64 rounding floor (the oracle's own distance
-from a long-double evaluation of the same formula), times 2^29 for FP32
-operands.  Errors are then measured against the long-double evaluation.
+from a long-double evaluation of the same formula, whole-vector or per
+field), times 2^29 for FP32 operands.  Errors are then measured against the
+long-double evaluation.
 """
 import numpy as np
 import pytest
@@ -37,6 +40,8 @@ def test_rhs_small(name):
     err = C.rel_l2(got, ref)
     print(f"{name}: rel L2 {err:.3e}")
     assert err < 1e-12
+    _tol, ext, _floor = C.floor_tolerance(d, u, 1e-12)
+    C.check_fields(name, got, ext, ext.field_tol)
 
 
 @pytest.mark.parametrize("name", ["vortex7_p3", "mixed6_p3_euler", "tgv5_p3", "curved4_p4"])
@@ -48,6 +53,7 @@ def test_rhs_small_fp32(name):
     err = C.rel_l2(got, ext)
     print(f"{name} fp32: rel L2 {err:.3e} (fp64 floor {floor:.2e}, tol {tol:.2e})")
     assert err < tol
+    C.check_fields(f"{name} fp32", got, ext, ext.field_tol)
 
 
 @pytest.mark.parametrize("name", ["vortex7_p3", "mixed6_p3_euler", "tgv5_p3", "curved4_p4"])
@@ -59,12 +65,16 @@ def test_rhs_small_bf16x3(name):
     d, s, u = _both(w, "bf16x3")
     tol, ext, floor = C.floor_tolerance(d, u, 1e-4, C.BF16X3_OVER_FP64)
     t = s.pack(u)
-    err = C.rel_l2(s.unpack(s.rhs(t)), ext)
+    got = s.unpack(s.rhs(t))
+    err = C.rel_l2(got, ext)
     dt = 1e-4
     s.step(t, dt, 5)
-    eu = C.rel_l2(s.unpack(t), d.rk4(u, dt, 5))
+    ref_u = d.rk4(u, dt, 5)
+    eu = C.rel_l2(s.unpack(t), ref_u)
     print(f"{name} bf16x3: rhs rel L2 {err:.3e} (tol {tol:.2e}), u(5) {eu:.3e}")
     assert err < tol and eu < 1e-5
+    C.check_fields(f"{name} bf16x3 rhs", got, ext, ext.field_tol)
+    C.check_fields(f"{name} bf16x3 u(5)", s.unpack(t), ref_u, 1e-5)
 
 
 def _force_plans(s, w, variant):
@@ -123,13 +133,29 @@ def test_every_kernel_variant(name, variant):
     w = C.SMALL[name]()
     d, s, u = _both(w)
     _force_plans(s, w, variant)
-    err = C.rel_l2(s.unpack(s.rhs(s.pack(u))), d.rhs(u))
+    ref, ext, ref_u = _variant_refs(name, d, u)
+    got = s.unpack(s.rhs(s.pack(u)))
+    err = C.rel_l2(got, ref)
     t = s.pack(u)
     dt = 1e-4
     s.step(t, dt, 3)
-    eu = C.rel_l2(s.unpack(t), d.rk4(u, dt, 3))
+    eu = C.rel_l2(s.unpack(t), ref_u)
     print(f"{name} {variant}: rhs rel L2 {err:.3e}, u(3) {eu:.3e}")
     assert err < 1e-12 and eu < 1e-12
+    C.check_fields(f"{name} {variant} rhs", got, ext, ext.field_tol)
+    C.check_fields(f"{name} {variant} u(3)", s.unpack(t), ref_u, 1e-12)
+
+
+_VARIANT_REFS = {}
+
+
+def _variant_refs(name, d, u):
+    """The oracle's du/dt, its long-double evaluation (with per-field bars at
+    the stated 1e-12) and u after 3 RK4 steps of 1e-4, once per case."""
+    if name not in _VARIANT_REFS:
+        _tol, ext, _floor = C.floor_tolerance(d, u, 1e-12)
+        _VARIANT_REFS[name] = (d.rhs(u), ext, d.rk4(u, 1e-4, 3))
+    return _VARIANT_REFS[name]
 
 
 @pytest.mark.parametrize("name", ["tgv3_p4", "mixed5_p2_ns", "curved3_p2_ns"])
@@ -157,9 +183,11 @@ def test_fused_gradient_transform_fp32(variant):
     d, s, u = _both(w, "fp32")
     _force_plans(s, w, variant)
     tol, ext, floor = C.floor_tolerance(d, u, 1e-5, C.FP32_OVER_FP64)
-    err = C.rel_l2(s.unpack(s.rhs(s.pack(u))), ext)
+    got = s.unpack(s.rhs(s.pack(u)))
+    err = C.rel_l2(got, ext)
     print(f"tgv5_p3 fp32 {variant}: rel L2 {err:.3e} (tol {tol:.2e})")
     assert err < tol
+    C.check_fields(f"tgv5_p3 fp32 {variant}", got, ext, ext.field_tol)
 
 
 @pytest.mark.parametrize("name", ["vortex1_p3", "tgv1_p3", "tgv1_p4_ns_fp32"])
@@ -212,36 +240,52 @@ def test_cfg1_rhs_and_100_steps():
     d, s, u = _both(w, perturb=False)
     ref = d.rhs(u)
     t = s.pack(u)
-    e_rhs = C.rel_l2(s.unpack(s.rhs(t)), ref)
+    got = s.unpack(s.rhs(t))
+    e_rhs = C.rel_l2(got, ref)
     s.step(t, w.dt, 40)
     s.step(t, w.dt, 60)           # two replays of the captured step graph
     ref_u = d.rk4(u, w.dt, 100)
     e_u = C.rel_l2(s.unpack(t), ref_u)
     print(f"cfg1: rhs {e_rhs:.3e}  u(100) {e_u:.3e}")
     assert e_rhs < 1e-12 and e_u < 1e-12
+    _tol, ext, _floor = C.floor_tolerance(d, u, 1e-12)
+    C.check_fields("cfg1 rhs", got, ext, ext.field_tol)
+    C.check_fields("cfg1 u(100)", s.unpack(t), ref_u, 1e-12)
 
 
-def test_cfg2_rhs_and_steps():
-    """Taylor-Green, 16^3 hexes, p=3, Navier-Stokes: du/dt and u after 2 RK4
-    steps (FP64), and the FP32 operator path."""
+def test_cfg2_rhs_and_100_steps():
+    """Taylor-Green, 16^3 hexes, p=3, Navier-Stokes: du/dt and u after the
+    workload's 100 RK4 steps (dt 3e-4), in FP64 and on the FP32 operator
+    path (FP64 state, update and reductions)."""
     w = configs.CONFIGS["cfg2"]()
+    assert w.nsteps == 100
     d, s, u = _both(w, perturb=False)
     tol64, ext, floor = C.floor_tolerance(d, u, 1e-12)
+    ftol32 = np.maximum(1e-5, ext.field_floor * 4 * C.FP32_OVER_FP64)
     tol32 = max(1e-5, 4 * floor * C.FP32_OVER_FP64)
     t = s.pack(u)
-    e_rhs = C.rel_l2(s.unpack(s.rhs(t)), ext)
-    s.step(t, w.dt, 2)
-    ref_u = d.rk4(u, w.dt, 2)
+    g64 = s.unpack(s.rhs(t))
+    e_rhs = C.rel_l2(g64, ext)
+    s.step(t, w.dt, w.nsteps)
+    ref_u = u
+    for k in range(0, w.nsteps, 20):          # the oracle, with a progress line per 20 steps
+        ref_u = d.rk4(ref_u, w.dt, min(20, w.nsteps - k))
+        print(f"cfg2: oracle at step {min(k + 20, w.nsteps)}", flush=True)
     e_u = C.rel_l2(s.unpack(t), ref_u)
     s32 = C.solver_for(w, "fp32")
     t32 = s32.pack(u)
-    e32 = C.rel_l2(s32.unpack(s32.rhs(t32)), ext)
-    s32.step(t32, w.dt, 2)
+    g32 = s32.unpack(s32.rhs(t32))
+    e32 = C.rel_l2(g32, ext)
+    s32.step(t32, w.dt, w.nsteps)
     e32u = C.rel_l2(s32.unpack(t32), ref_u)
-    print(f"cfg2: fp64 floor {floor:.2e} | rhs {e_rhs:.3e} (tol {tol64:.1e}) u(2) {e_u:.3e} | "
-          f"fp32 rhs {e32:.3e} (tol {tol32:.1e}) u(2) {e32u:.3e}")
+    print(f"cfg2: fp64 floor {floor:.2e} | rhs {e_rhs:.3e} (tol {tol64:.1e}) u(100) {e_u:.3e} | "
+          f"fp32 rhs {e32:.3e} (tol {tol32:.1e}) u(100) {e32u:.3e}")
     assert e_rhs < tol64 and e_u < 1e-12
     assert e32 < tol32 and e32u < 1e-5
+    C.check_fields("cfg2 fp64 rhs", g64, ext, ext.field_tol)
+    C.check_fields("cfg2 fp64 u(100)", s.unpack(t), ref_u, 1e-12)
+    C.check_fields("cfg2 fp32 rhs", g32, ext, ftol32)
+    C.check_fields("cfg2 fp32 u(100)", s32.unpack(t32), ref_u, 1e-5)
 
 
 def test_rk_graph_replay_matches_single_steps():
