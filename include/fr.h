@@ -248,6 +248,24 @@ fr_status fr_rk_step_adjoint_stash(fr_ctx *ctx, double *stash, const double *dt_
 fr_status fr_integrate(fr_ctx *ctx, const double *u, int32_t kind, double *out,
                        void *hip_stream);
 
+/* fr_integrate for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops or harnesses that forbid hipMalloc).
+ * Same arguments, kernels, summation order and result as fr_integrate
+ * (bitwise), but the element and slice partials live in a fixed scratch
+ * array inside the library, one copy per GPU, held until the process ends:
+ * FR_INTEGRAL_SCRATCH_DOUBLES doubles (32 MiB).  Its address on a device is
+ * resolved once, when the first context is set up there.  The call allocates
+ * nothing and needs no clearing (every partial it reads it writes first).
+ * A mesh whose partials need more than the fixed scratch holds
+ * (nchunk x elements x (nvars + 1) plus the slice partials; about 800,000
+ * elements of a 3-D mesh) gets FR_EINVAL with a message naming both sizes.
+ * Every call on one GPU shares that GPU's scratch: calls that overlap in
+ * time on one GPU (other streams, other threads) race and must be ordered
+ * by the caller. */
+#define FR_INTEGRAL_SCRATCH_DOUBLES 4194304
+fr_status fr_integrate_noalloc(fr_ctx *ctx, const double *u, int32_t kind, double *out,
+                               void *hip_stream);
+
 /* Host-only diagnostics (no device use; callable without a GPU).
  * fr_reference_operator copies one reference-element array of (etype, p,
  * fr_correction) into HOST memory `out` (capacity `cap` doubles) and stores its shape in

@@ -22,7 +22,7 @@ SYSTEM = {"euler": 0, "ns": 1}
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 EXPORTS = ("fr_setup_mesh", "fr_setup_mesh_bc", "fr_get_layout", "fr_get_solution_points", "fr_get_quadrature",
-           "fr_rhs", "fr_rk_step", "fr_euler_step", "fr_dopri5_step", "fr_rhs_adjoint", "fr_rk_step_adjoint", "fr_integrate",
+           "fr_rhs", "fr_rk_step", "fr_euler_step", "fr_dopri5_step", "fr_rhs_adjoint", "fr_rk_step_adjoint", "fr_integrate", "fr_integrate_noalloc",
            "fr_reference_operator", "fr_check_mesh", "fr_debug_stage", "fr_debug_scratch_len", "fr_bench_step",
            "fr_debug_gemm", "fr_measure_ceiling", "fr_bench_gemm", "fr_get_gemm_plan", "fr_integrate_grad", "fr_stash_len", "fr_rk_step_stash",
            "fr_rk_step_adjoint_stash", "fr_debug_set_plan",
@@ -91,6 +91,7 @@ def load_library(path: str = LIB_PATH):
         "fr_rhs_adjoint": [vp, dp, dp, dp, vp],
         "fr_rk_step_adjoint": [vp, dp, dp, dp, dp, vp],
         "fr_integrate": [vp, dp, i32, dp, vp],
+        "fr_integrate_noalloc": [vp, dp, i32, dp, vp],
         "fr_integrate_grad": [vp, dp, i32, dp, vp],
         "fr_stash_len": [vp, ctypes.POINTER(i64)],
         "fr_rk_step_stash": [vp, dp, dp, dp, vp],
@@ -452,6 +453,15 @@ class Solver:
                                device="cuda")
         _check(self.L.fr_integrate(self.ctx, self._ptr(u), 0, out.data_ptr(), self._stream()),
                self.ctx)
+        return out
+
+    def integrate_noalloc(self, u, out):
+        """As integrate, into the caller's `out` [nproblems, nvars + 1], with
+        the library's fixed scratch: the call allocates nothing."""
+        assert out.dtype == self.torch.float64 and out.is_cuda
+        assert out.numel() >= self.nproblems * (self.nvars + 1)
+        _check(self.L.fr_integrate_noalloc(self.ctx, self._ptr(u), 0, out.data_ptr(),
+                                           self._stream()), self.ctx)
         return out
 
     def close(self):

@@ -1411,6 +1411,11 @@ fr_status fr_setup_mesh_bc(const fr_config *cfg, int32_t nblocks, const fr_block
       c->d_tune_dt = dev_upload(c.get(), zeros.data(), zeros.size(), s);
     }
     if (cfg->autotune) autotune(c.get(), s);
+    {
+      // the integrals' fixed scratch of this device (fr_integrate_noalloc)
+      double *scr = nullptr;
+      hip_check(fr::integral_scratch(&scr), "integral scratch address");
+    }
     hip_check(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "stream");
     hip_check(hipDeviceSynchronize(), "setup sync");
   } catch (const fr::SetupError &e) {
@@ -1641,6 +1646,40 @@ fr_status fr_integrate(fr_ctx *c, const double *u, int32_t kind, double *out, vo
                                       c->nslice, c->slice_len, c->d_pstart, c->d_plist, c->d_part,
                                       c->d_part2,
                                       out, s),
+              "problem sums");
+  } catch (const Fail &f) {
+    return fail(c, f.st, f.msg);
+  }
+  return FR_OK;
+}
+
+fr_status fr_integrate_noalloc(fr_ctx *c, const double *u, int32_t kind, double *out,
+                               void *hip_stream) {
+  if (!c) return FR_EINVAL;
+  if (!u || !out || kind != 0) return fail(c, FR_EINVAL, "bad integrate arguments");
+  hipStream_t s = (hipStream_t)hip_stream;
+  // element partials, then (several slices per problem) the slice partials,
+  // 256-byte aligned
+  const int64_t npart = (int64_t)c->nchunk * c->nelem_total * (c->NV + 1);
+  const int64_t off2 = (npart + 31) / 32 * 32;
+  const int64_t npart2 = c->nslice > 1 ? (int64_t)c->nproblems * c->nslice * (c->NV + 1) : 0;
+  if (off2 + npart2 > fr::kIntegralScratchDoubles)
+    return fail(c, FR_EINVAL,
+                "fr_integrate_noalloc: this mesh needs " + std::to_string(off2 + npart2) +
+                    " doubles of scratch; the fixed scratch holds " +
+                    std::to_string(fr::kIntegralScratchDoubles) + " (use fr_integrate)");
+  try {
+    double *scr = nullptr;
+    hip_check(fr::integral_scratch(&scr), "integral scratch address");
+    // every partial the sums read is written first: nothing to clear
+    for (auto &b : c->blocks)
+      hip_check(fr::launch_elem_integrals(c->NV, c->D, b.Nu, b.ld, b.nelem, c->nchunk,
+                                          c->nelem_total, b.d_wdjac, u + b.uoff,
+                                          scr + b.part_off, s),
+                "elem integrals");
+    hip_check(fr::launch_problem_sums(c->NV + 1, c->nproblems, c->nchunk, c->nelem_total,
+                                      c->nslice, c->slice_len, c->d_pstart, c->d_plist, scr,
+                                      npart2 ? scr + off2 : nullptr, out, s),
               "problem sums");
   } catch (const Fail &f) {
     return fail(c, f.st, f.msg);

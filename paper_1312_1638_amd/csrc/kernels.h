@@ -206,6 +206,13 @@ hipError_t launch_elem_integrals(int nvars, int ndims, int nupts, int64_t ld, in
 hipError_t launch_problem_sums(int ncomp, int nprob, int nchunk, int64_t pstride, int nslice,
                                int64_t per, const int64_t *pstart, const int64_t *plist,
                                const double *part, double *part2, double *out, hipStream_t s);
+// The integrals' fixed scratch (element partials, then slice partials) for
+// callers that cannot allocate: kIntegralScratchDoubles doubles (32 MiB) per
+// device.  integral_scratch returns its address on the current device
+// (hipGetSymbolAddress, resolved once per device).  Every call on a device
+// shares that device's copy: calls that overlap on one device race.
+constexpr int64_t kIntegralScratchDoubles = int64_t(1) << 22;
+hipError_t integral_scratch(double **ptr);
 // measured ceilings: kind 0 HBM triad GB/s, 1 FP64 MFMA TFLOP/s, 2 FP32 MFMA TFLOP/s
 hipError_t measure_ceiling(int kind, double *value, hipStream_t s);
 // flag[0] = 1 if any u is not finite

@@ -14,6 +14,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "physics.h"
@@ -520,6 +522,32 @@ hipError_t launch_problem_sums(int ncomp, int nprob, int nchunk, int64_t pstride
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+// Fixed scratch of the integrals for callers that cannot allocate: a static
+// device array, one copy per GPU, held until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is a stand-in,
+// not a device address); it passes the address that hipGetSymbolAddress
+// returns for the current device, resolved once per device and kept here.
+static __device__ __align__(256) double scratch[kIntegralScratchDoubles];
+
+hipError_t integral_scratch(double **ptr) {
+  static std::mutex mu;
+  static std::map<int, double *> addr;  // device ordinal -> address of its copy
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr) return hipErrorInvalidSymbol;
+    it = addr.emplace(dev, static_cast<double *>(p)).first;
+  }
+  *ptr = it->second;
+  return hipSuccess;
 }
 
 __global__ __launch_bounds__(256) void check_finite_kernel(const double *u, int64_t n,
