@@ -51,7 +51,8 @@ WORKLOADS = {
 }
 
 STEP_NAMES = {1: "interp_M0", 2: "common_solution", 3: "grad_M6_M4p", 4: "grad_transform",
-              5: "grad_interp_M5", 6: "transformed_flux", 7: "common_flux", 8: "div_M3_M1p"}
+              5: "grad_interp_M5", 6: "transformed_flux", 7: "common_flux", 8: "div_M3_M1p",
+              9: "div_M3_M1p_rk4"}
 
 
 def progress(msg):
@@ -107,6 +108,11 @@ def step_model(s, step, ts):
         elif step == 8:
             flops += 2.0 * (nnz["M3"] + nnz["M1p"]) * cols
             byts += cols * (nf + D * nu) * ts + nu * ne * 8 + nu * cols * 8
+        elif step == 9:
+            # step 8 with the RK4 update of a middle stage: u and the
+            # accumulator read, the accumulator and the next stage written
+            flops += 2.0 * (nnz["M3"] + nnz["M1p"]) * cols
+            byts += cols * (nf + D * nu) * ts + nu * ne * 8 + 4 * nu * cols * 8
     npairs = s.npairs
     if step == 2:
         byts += npairs * (4 * NV * ts + 8)
@@ -213,7 +219,7 @@ def time_kernels(s, u, torch, nrep=50):
     the kernels are launched on (torch's current stream, passed to the
     library)."""
     out = {}
-    steps = [1, 6, 7, 8] if s.system == "euler" else [1, 2, 3, 4, 5, 6, 7, 8]
+    steps = [1, 6, 7, 8, 9] if s.system == "euler" else [1, 2, 3, 4, 5, 6, 7, 8, 9]
     stream = torch.cuda.current_stream()
     for st in steps:
         s.bench_step(u, st, 2)                           # warm
@@ -504,8 +510,15 @@ def main():
         b_, f_ = step_model(s, st, 8)
         kernels[STEP_NAMES[st]] = dict(us=round(t * 1e6, 2), GBps=round(b_ / t / 1e9, 1),
                                        TFLOPs=round(f_ / t / 1e12, 2))
-        if st in (1, 3, 5, 8):
-            kernels[STEP_NAMES[st]]["plan"] = plan_name(s.gemm_plan(0, st), st)
+        if st in (1, 3, 5, 8, 9):
+            kernels[STEP_NAMES[st]]["plan"] = plan_name(s.gemm_plan(0, min(st, 8)), st)
+        if len(s.blocks) > 1 and st in (1, 5, 6, 8, 9):
+            m = s.multi(min(st, 8))
+            kernels[STEP_NAMES[st]]["launches"] = (
+                "one launch over every block" if st == 6 and m else
+                ", ".join(x for x, bit in (("one sparse-row launch over its blocks", 1),
+                                            ("one matrix-core launch over its blocks", 2))
+                          if m & bit) or "one launch per block")
 
     # the oracle on a bounded sample of the same mesh: CPU baseline, and the
     # reference of each precision's error on the sampled elements

@@ -306,7 +306,10 @@ fr_status fr_debug_scratch_len(const fr_ctx *ctx, int32_t stage, int64_t *len);
  * state u, then launches that step's kernels nrep times on hip_stream (step
  * 7 works in place, so its repeats read the previous repeat's output; the
  * values are meaningless, the work is the same).  The output of step 8 goes
- * to internal scratch. */
+ * to internal scratch.  Step 9: step 8 with the RK4 register update of a
+ * middle stage, as the captured step graph runs it (reads u and the
+ * accumulator, writes the accumulator and the next stage; internal
+ * registers, dt = 0). */
 fr_status fr_bench_step(fr_ctx *ctx, const double *u, int32_t step, int32_t nrep,
                         void *hip_stream);
 fr_status fr_debug_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, const double *A,
@@ -350,6 +353,21 @@ fr_status fr_get_gemm_plan(const fr_ctx *ctx, int32_t block, int32_t step, int32
  * Synchronous on hip_stream. */
 fr_status fr_debug_set_plan(fr_ctx *ctx, int32_t block, int32_t step, int32_t mbw, int32_t nc,
                             int32_t wm, void *hip_stream);
+
+/* Multi-block launches (test and report support).  On a mesh of several
+ * element blocks the set-up times, for steps 1 (U^f = M0 U), 5 (Q^f), 8 (the
+ * divergence with its epilogue) and 6 (transformed flux), one launch per
+ * kernel family over every block against a launch per block, and keeps the
+ * faster.  fr_debug_multi reports (state: bit 0 sparse-row launch over
+ * several blocks, bit 1 matrix-core launch over several blocks, bit 2 for
+ * step 6 the one-launch transformed flux) and, with mode >= 0, sets it: 0 a
+ * launch per block, 1 one launch per family with one field per thread (and
+ * one column strip per wavefront), 2 with all fields per thread (two
+ * strips).  A plan forced with fr_debug_set_plan turns that step's
+ * multi-block launches off.  FP64 and FP32 contexts; BF16x3 launches per
+ * block.  Steps other than 1, 5, 6, 8 give FR_EINVAL. */
+fr_status fr_debug_multi(fr_ctx *ctx, int32_t step, int32_t mode, int32_t *state,
+                         void *hip_stream);
 
 /* Gradient of an integral of fr_integrate with respect to the state: kind 1
  * (kinetic energy, summed over problems) -> grad (DEVICE, state layout),

@@ -25,7 +25,7 @@ EXPORTS = ("fr_setup_mesh", "fr_setup_mesh_bc", "fr_get_layout", "fr_get_solutio
            "fr_rhs", "fr_rk_step", "fr_euler_step", "fr_dopri5_step", "fr_rhs_adjoint", "fr_rk_step_adjoint", "fr_integrate", "fr_integrate_noalloc",
            "fr_reference_operator", "fr_check_mesh", "fr_debug_stage", "fr_debug_scratch_len", "fr_bench_step",
            "fr_debug_gemm", "fr_measure_ceiling", "fr_bench_gemm", "fr_get_gemm_plan", "fr_integrate_grad", "fr_stash_len", "fr_rk_step_stash",
-           "fr_rk_step_adjoint_stash", "fr_debug_set_plan",
+           "fr_rk_step_adjoint_stash", "fr_debug_set_plan", "fr_debug_multi",
            "fr_last_error", "fr_destroy")
 
 
@@ -110,6 +110,7 @@ def load_library(path: str = LIB_PATH):
                              ctypes.POINTER(i32)],
         "fr_debug_gemm": [i32, i32, i32, i32, dp, dp, dp, i64, dp, i64, i32, i32, i32, vp],
         "fr_debug_set_plan": [vp, i32, i32, i32, i32, i32, vp],
+        "fr_debug_multi": [vp, i32, i32, ctypes.POINTER(i32), vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -445,6 +446,16 @@ class Solver:
         """Force the (mbw, nc, wm) plan of RHS step 1, 3, 5 or 8 of a block."""
         _check(self.L.fr_debug_set_plan(self.ctx, block, step, plan[0], plan[1], plan[2],
                                         self._stream()), self.ctx)
+
+    def multi(self, step, mode=-1):
+        """Multi-block launches of step 1, 5, 6 or 8: bit 0 sparse-row over
+        several blocks, bit 1 matrix cores over several blocks, bit 2 (step
+        6) the one-launch transformed flux.  mode >= 0 sets them first (0 a
+        launch per block, 1 / 2 one launch per kernel family)."""
+        st = ctypes.c_int32()
+        _check(self.L.fr_debug_multi(self.ctx, step, mode, ctypes.byref(st), self._stream()),
+               self.ctx)
+        return st.value
 
     def integrate(self, u):
         """[nproblems, nvars + 1]: integral of every field, then kinetic energy.

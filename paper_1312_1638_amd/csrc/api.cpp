@@ -27,6 +27,10 @@ struct GemmOp {
   void *d_A = nullptr;
   std::vector<double> A;  // unpacked operator (kept for re-packing by the tuner)
   fr::SparseOp sp{nullptr, nullptr, 0, 0, 1};  // ELL copy when the operator is sparse
+  std::vector<int32_t> ell_cols;                // host copies of sp.colidx, sp.vals, sp.roff
+  std::vector<double> ell_vals;
+  std::vector<uint32_t> roff_host;
+  int64_t roff_rs1 = 0, roff_rs2 = 0;          // row strides (bytes) sp.roff was built for
   fr::StagedOp st{nullptr, nullptr, 0, 0, 0};  // chunked ELL copy for the LDS-staged kernel
   double density = 1.0;
 };
@@ -85,6 +89,7 @@ struct BlockRT {
   int64_t nelem = 0, ld = 0;
   int Nu = 0, Nf = 0;
   int64_t uoff = 0, ufoff = 0, qfoff = 0, ftoff = 0, part_off = 0;
+  int64_t refoff = 0;  // reference states of the deviation form ([NV][ld])
   double *d_smat = nullptr, *d_rcpdjac = nullptr, *d_wdjac = nullptr;
   int32_t *d_prob = nullptr;
   GemmOp m0, m5, s3, s8;
@@ -92,6 +97,28 @@ struct BlockRT {
   // [(M4 - M6 M0)^T | M0^T]
   GemmOp t_m3, t_m1, t_m0, t_m6, t_fin;
   std::vector<double> xu, wdjac_host;
+};
+
+// One launch of an operator product over several element blocks (steps 1,
+// 5 and 8 of a mixed or batched mesh): the blocks whose plans share a
+// kernel family, and a device table of their slots.
+struct MultiLaunch {
+  bool on = false;
+  int width = 0, fields = 1;    // sparse-row family (precomputed gathers)
+  int MBW = 0, NC = 0;          // matrix-core family
+  std::vector<int> blocks;
+  fr::LaunchSlot *d_slots = nullptr;
+  int nslots = 0;
+  int64_t nwg = 0;
+  std::vector<void *> owned;    // slot table, padded operator copies, packed operators
+};
+
+// The transformed flux (step 6) over every block in one launch.
+struct PointMulti {
+  bool on = false;
+  fr::PointSlot *d_slots = nullptr;
+  int nslots = 0;
+  int64_t nwg = 0;
 };
 
 }  // namespace
@@ -170,6 +197,16 @@ struct fr_ctx {
     }
   } dp_key{};
   std::vector<void *> allocs;
+  // Euler in reduced precision: the deviation form (each element's state
+  // less its reference, the state at its first solution point, before any
+  // rounding to FP32 or bf16)
+  bool devform = false;
+  void *d_udev = nullptr;        // u - u_ref (scratch element type, state layout)
+  double *d_uref = nullptr;      // u_ref per block [NV][ld]
+  int64_t *d_blk_refbase = nullptr;
+  // multi-block launches: [step][family 0 sparse-row, 1 matrix cores]
+  MultiLaunch multi[9][2];
+  PointMulti tflux_multi;
 };
 
 namespace {
@@ -242,7 +279,8 @@ void *pack_upload(fr_ctx *c, const GemmOp &op, fr::GemmPlan p, hipStream_t s, bo
 }
 
 void make_op(fr_ctx *c, GemmOp &op, const std::vector<double> &A, int M, int K1, int K2,
-             int64_t N, hipStream_t s, fr::GemmPlan *force = nullptr) {
+             int64_t N, hipStream_t s, fr::GemmPlan *force = nullptr, int hint1 = 0,
+             int hint2 = 0) {
   op.M = M; op.K1 = K1; op.K2 = K2;
   const int kstep = c->prec == FR_BF16X3 ? 32 : 4;
   op.KS1 = (K1 + kstep - 1) / kstep;
@@ -277,35 +315,66 @@ void make_op(fr_ctx *c, GemmOp &op, const std::vector<double> &A, int M, int K1,
       }
       op.sp.colidx = dev_upload(c, ci.data(), ci.size(), s);
       op.sp.vals = dev_upload(c, va.data(), va.size(), s);
+      op.ell_cols = ci;
+      op.ell_vals = va;
       op.sp.width = W;
       op.sp.rpg = 16;
       op.sp.fields = 1;
-      // chunked copy for the LDS-staged kernel: kc rows of B (32 KB of LDS)
-      // per chunk, columns within the chunk
-      const int kc = c->prec == FR_FP64 ? 64 : 128;
-      const int nchunk = (K + kc - 1) / kc;
-      int wc = 1;
+      // chunked copy for the LDS-staged kernel: each panel split into chunks
+      // of at most kcmax rows of B (the LDS a workgroup may use, up to 64 KB,
+      // for 64 columns), aligned
+      // where possible to the operator's blocks (hint1 rows of panel 1, such
+      // as the points of one face; hint2 rows of panel 2, such as one
+      // direction of the transformed flux), so that every operator row has
+      // about the same number of entries in a chunk; columns within the chunk
+      int maxshm = 32768;
+      {
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess)
+          hipDeviceGetAttribute(&maxshm, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+      }
+      // at most 64 KB, and what the device allows a workgroup
+      const int kcmax = std::max(16, std::min(65536, maxshm) / (64 * (c->prec == FR_FP64 ? 8 : 4)));
+      std::vector<int> starts(1, 0);
+      for (int pn = 0; pn < 2; ++pn) {
+        const int rows = pn ? K2 : K1, hint = pn ? hint2 : hint1;
+        if (rows <= 0) continue;
+        int n = (rows + kcmax - 1) / kcmax;
+        int size = 0;
+        for (int m = n; hint > 0 && m <= rows && rows / m >= hint; ++m)
+          if (rows % m == 0 && (rows / m) % hint == 0) { n = m; size = rows / m; break; }
+        for (int i = 0; i < n; ++i)
+          starts.push_back(starts.back() + (size ? size : rows / n + (i < rows % n)));
+      }
+      const int nchunk = (int)starts.size() - 1;
+      int kc = 1;
+      for (int ch = 0; ch < nchunk; ++ch) kc = std::max(kc, starts[ch + 1] - starts[ch]);
+      std::vector<int32_t> cw(nchunk, 0);
+      std::vector<int> chunk_of(K);
       for (int ch = 0; ch < nchunk; ++ch)
-        for (int r = 0; r < M; ++r) {
-          int cnt = 0;
-          for (int k : cols[r]) cnt += k / kc == ch;
-          wc = std::max(wc, cnt);
-        }
-      const int WC = fr::spop_lds_width(wc);
+        for (int k = starts[ch]; k < starts[ch + 1]; ++k) chunk_of[k] = ch;
+      for (int r = 0; r < M; ++r) {
+        std::vector<int> cnt(nchunk, 0);
+        for (int k : cols[r]) ++cnt[chunk_of[k]];
+        for (int ch = 0; ch < nchunk; ++ch) cw[ch] = std::max(cw[ch], cnt[ch]);
+      }
+      const int WC = fr::spop_lds_width(*std::max_element(cw.begin(), cw.end()));
       if (WC > 0) {
         std::vector<int32_t> sci((size_t)nchunk * M * WC, 0);
         std::vector<double> sva((size_t)nchunk * M * WC, 0.0);
         for (int r = 0; r < M; ++r) {
           std::vector<int> fill(nchunk, 0);
           for (int k : cols[r]) {
-            const int ch = k / kc;
+            const int ch = chunk_of[k];
             const size_t at = ((size_t)ch * M + r) * WC + fill[ch]++;
-            sci[at] = k - ch * kc;
+            sci[at] = k - starts[ch];
             sva[at] = A[(size_t)r * K + k];
           }
         }
         op.st.colidx = dev_upload(c, sci.data(), sci.size(), s);
         op.st.vals = dev_upload(c, sva.data(), sva.size(), s);
+        op.st.cstart = dev_upload(c, starts.data(), starts.size(), s);
+        op.st.cwidth = dev_upload(c, cw.data(), cw.size(), s);
         op.st.width = WC;
         op.st.kc = kc;
         op.st.nchunk = nchunk;
@@ -335,11 +404,52 @@ bool flux_fused(const fr_ctx *c, const BlockRT &b) {
          !(b.s3.WM & kPlanStaged) && c->cur.fto != c->cur.ft;
 }
 
-// Launch an operator product with whichever kernel its plan names.
+// Byte offsets of the B row of every ELL entry of `op`, for operands with
+// row strides rs1 and rs2 bytes: k rs1 for a one-panel operator (from its
+// panel, whatever its address); for two panels at B1 and B2, from the lower
+// of the two.  Kept only if every entry's row, plus `span` bytes of columns,
+// lies within 4 GiB of that base (one buffer resource covers both panels).
+void build_row_offsets(fr_ctx *c, GemmOp &op, const void *B1, int64_t rs1, const void *B2,
+                       int64_t rs2, int64_t span, hipStream_t s) {
+  if (!op.sp.colidx || op.ell_cols.empty()) return;
+  int64_t o1 = 0, o2 = 0;
+  if (op.K2 > 0) {
+    const int64_t d = (const char *)B2 - (const char *)B1;
+    o1 = d < 0 ? -d : 0;
+    o2 = d < 0 ? 0 : d;
+    op.sp.roff_delta = d;
+  }
+  std::vector<uint32_t> off(op.ell_cols.size());
+  for (size_t i = 0; i < off.size(); ++i) {
+    const int k = op.ell_cols[i];
+    const int64_t o = k < op.K1 ? o1 + (int64_t)k * rs1 : o2 + (int64_t)(k - op.K1) * rs2;
+    if (o < 0 || o + span >= ((int64_t)1 << 32)) return;
+    off[i] = (uint32_t)o;
+  }
+  op.sp.roff = dev_upload(c, off.data(), off.size(), s);
+  op.roff_host = off;
+  op.roff_rs1 = rs1;
+  op.roff_rs2 = rs2;
+}
+
+// Launch an operator product with whichever kernel its plan names.  Sparse
+// plans use the precomputed row offsets when they hold for these operands.
 hipError_t launch_op(const GemmOp &op, int gprec, int epi, const fr::GemmArgs &g, int batch,
                      hipStream_t s) {
   if (op.MBW == 0 && (op.WM & kPlanStaged)) return fr::launch_spop_lds(gprec, epi, g, op.st, batch, s);
-  if (op.MBW == 0) return fr::launch_spop(gprec, epi, g, op.sp, batch, s);
+  if (op.MBW == 0) {
+    if (op.sp.roff && g.ldb1 * (g.b1_f32 ? 4 : 8) == op.roff_rs1) {
+      fr::GemmArgs go = g;
+      if (op.K2 == 0) {
+        go.roff = op.sp.roff; go.rbase = g.B1;
+      } else if ((const char *)g.B2 - (const char *)g.B1 == op.sp.roff_delta &&
+                 g.ldb2 * (g.b2_f32 ? 4 : 8) == op.roff_rs2) {
+        go.roff = op.sp.roff; go.rbase = op.sp.roff_delta < 0 ? g.B2 : g.B1;
+      }
+      return fr::launch_spop(gprec, epi, go, op.sp, batch, s);
+    }
+    return fr::launch_spop(gprec, epi, g, op.sp, batch, s);
+  }
   return fr::launch_gemm(gprec, epi, g, batch, s);
 }
 
@@ -386,6 +496,10 @@ fr::PairArgs pair_args(fr_ctx *c) {
   pa.qstride0 = (int64_t)c->blocks[0].Nf * NV * c->blocks[0].ld;
   pa.gamma = c->cfg.gamma; pa.mu = c->cfg.mu; pa.prandtl = c->cfg.prandtl;
   pa.beta = c->cfg.ldg_beta; pa.tau = c->cfg.ldg_tau;
+  if (c->devform) {
+    pa.uref = c->d_uref;
+    pa.blk_refbase = c->d_blk_refbase;
+  }
   return pa;
 }
 
@@ -409,7 +523,226 @@ fr::PointArgs point_args(fr_ctx *c, const BlockRT &b, const double *u) {
   p.q = elem(c->cur.ft, b.ftoff, c->tsize); p.q_f32 = c->prec != FR_FP64;
   p.fout = c->cur.fto != c->cur.ft ? elem(c->cur.fto, b.ftoff, c->tsize) : nullptr;
   p.gamma = c->cfg.gamma; p.mu = c->cfg.mu; p.prandtl = c->cfg.prandtl;
+  if (c->devform) {
+    p.udev = elem(c->d_udev, b.uoff, c->tsize);
+    p.uref = c->d_uref + b.refoff;
+  }
   return p;
+}
+
+// ---------------------------------------------------------------------------
+// Multi-block launches
+// ---------------------------------------------------------------------------
+GemmOp &step_op(BlockRT &b, int st) { return st == 1 ? b.m0 : st == 5 ? b.m5 : b.s8; }
+
+template <typename T>
+T *owned_upload(MultiLaunch &ml, const T *h, size_t n, hipStream_t s) {
+  void *d = nullptr;
+  hip_check(hipMalloc(&d, std::max<size_t>(1, n) * sizeof(T)), "hipMalloc");
+  ml.owned.push_back(d);
+  hip_check(hipMemcpyAsync(d, h, n * sizeof(T), hipMemcpyHostToDevice, s), "upload");
+  hip_check(hipStreamSynchronize(s), "upload sync");
+  return (T *)d;
+}
+
+// Element offsets of block b's operands for step st (slot of a
+// multi-block launch): step 1 reads the state and writes U^f; step 5 reads
+// Q and writes Q^f (D batch slices); step 8 reads D~ and F~ and updates the
+// state registers.
+void slot_offsets(const fr_ctx *c, const BlockRT &b, int st, fr::LaunchSlot &sl) {
+  const int64_t N = (int64_t)c->NV * b.ld;
+  sl.ld = b.ld; sl.N = N; sl.nelem = b.nelem;
+  sl.rcpdjac = b.d_rcpdjac; sl.prob = b.d_prob;
+  if (st == 1) {
+    sl.off_b1 = b.uoff; sl.off_c = b.ufoff;
+  } else if (st == 5) {
+    sl.off_b1 = b.ftoff; sl.off_c = b.qfoff;
+    sl.sB1 = (int64_t)b.Nu * N; sl.sC = (int64_t)b.Nf * N;
+  } else {
+    sl.off_b1 = b.ufoff; sl.off_b2 = b.ftoff; sl.off_u = b.uoff;
+  }
+}
+
+// Blocks of step st whose plan is in the family (0: sparse-row with
+// precomputed gathers, 1: matrix cores, FP64 and FP32 contexts).
+std::vector<int> family_blocks(fr_ctx *c, int st, int fam) {
+  std::vector<int> out;
+  for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
+    GemmOp &op = step_op(c->blocks[bi], st);
+    if (fam == 0 && op.MBW == 0 && !(op.WM & kPlanStaged) && op.sp.roff &&
+        op.ell_vals.size() == op.roff_host.size())
+      out.push_back((int)bi);
+    if (fam == 1 && op.MBW > 0 && c->prec != FR_BF16X3) out.push_back((int)bi);
+  }
+  return out;
+}
+
+void free_multi(MultiLaunch &ml) {
+  for (void *p : ml.owned) hipFree(p);
+  ml = MultiLaunch{};
+}
+
+// One sparse-row launch over the family's blocks with `fields` fields per
+// thread: every block's ELL padded to the widest (padding: value 0 on the
+// row's last real entry), its own rows per workgroup row.
+bool build_multi_sparse(fr_ctx *c, int st, int fields, hipStream_t s) {
+  MultiLaunch &ml = c->multi[st][0];
+  free_multi(ml);
+  const std::vector<int> bl = family_blocks(c, st, 0);
+  if (bl.size() < 2) return false;
+  int W = 0;
+  for (int bi : bl) W = std::max(W, step_op(c->blocks[bi], st).sp.width);
+  std::vector<fr::LaunchSlot> host;
+  int64_t wg = 0;
+  for (int bi : bl) {
+    BlockRT &b = c->blocks[bi];
+    GemmOp &op = step_op(b, st);
+    const int w0 = op.sp.width, M = op.M;
+    const double *dv = op.sp.vals;
+    const uint32_t *dr = op.sp.roff;
+    if (w0 != W) {
+      std::vector<double> v((size_t)M * W, 0.0);
+      std::vector<uint32_t> r((size_t)M * W);
+      for (int row = 0; row < M; ++row)
+        for (int e = 0; e < W; ++e) {
+          const size_t src = (size_t)row * w0 + std::min(e, w0 - 1);
+          v[(size_t)row * W + e] = e < w0 ? op.ell_vals[src] : 0.0;
+          r[(size_t)row * W + e] = op.roff_host[src];
+        }
+      dv = owned_upload(ml, v.data(), v.size(), s);
+      dr = owned_upload(ml, r.data(), r.size(), s);
+    }
+    fr::LaunchSlot sl{};
+    slot_offsets(c, b, st, sl);
+    sl.wg_begin = wg;
+    sl.vals = dv; sl.roff = dr;
+    sl.rbase_b2 = op.K2 > 0 && op.sp.roff_delta < 0;
+    sl.M = M; sl.K1 = op.K1; sl.K2 = op.K2;
+    sl.rpg = op.sp.rpg;
+    sl.ngroups = (M + sl.rpg - 1) / sl.rpg;
+    wg += fr::spop_workgroups(fields == 1 ? sl.N : b.ld, M, sl.rpg);
+    host.push_back(sl);
+  }
+  ml.d_slots = owned_upload(ml, host.data(), host.size(), s);
+  ml.nslots = (int)host.size(); ml.nwg = wg; ml.blocks = bl;
+  ml.width = W; ml.fields = fields; ml.on = true;
+  return true;
+}
+
+// One matrix-core launch over the family's blocks: the largest tuned row
+// blocks per wavefront, NC column strips, each block's operator packed for
+// its own row split.
+bool build_multi_mfma(fr_ctx *c, int st, int NC, hipStream_t s) {
+  MultiLaunch &ml = c->multi[st][1];
+  free_multi(ml);
+  const std::vector<int> bl = family_blocks(c, st, 1);
+  if (bl.size() < 2) return false;
+  int MBW = 0;
+  for (int bi : bl) MBW = std::max(MBW, step_op(c->blocks[bi], st).MBW);
+  if (!fr::gemm_plan_valid(MBW, NC)) return false;
+  std::vector<fr::LaunchSlot> host;
+  int64_t wg = 0;
+  for (int bi : bl) {
+    BlockRT &b = c->blocks[bi];
+    GemmOp &op = step_op(b, st);
+    const int WM = (op.M + 16 * MBW - 1) / (16 * MBW);
+    void *A = pack_upload(c, op, fr::GemmPlan{MBW, NC, WM}, s, false);
+    ml.owned.push_back(A);
+    fr::LaunchSlot sl{};
+    slot_offsets(c, b, st, sl);
+    sl.wg_begin = wg;
+    sl.Apack = A;
+    sl.M = op.M; sl.K1 = op.K1; sl.K2 = op.K2; sl.KS1 = op.KS1; sl.KS2 = op.KS2; sl.WM = WM;
+    wg += fr::gemm_workgroups(sl.N, NC, WM);
+    host.push_back(sl);
+  }
+  ml.d_slots = owned_upload(ml, host.data(), host.size(), s);
+  ml.nslots = (int)host.size(); ml.nwg = wg; ml.blocks = bl;
+  ml.MBW = MBW; ml.NC = NC; ml.on = true;
+  return true;
+}
+
+// The transformed flux over every block in one launch (blocks whose flux is
+// not fused into step 3).
+bool build_tflux_multi(fr_ctx *c, hipStream_t s) {
+  PointMulti &pm = c->tflux_multi;
+  pm.on = false;
+  if (c->blocks.size() < 2) return false;
+  for (auto &b : c->blocks)
+    if (flux_fused(c, b)) return false;
+  std::vector<fr::PointSlot> host;
+  int64_t wg = 0;
+  for (auto &b : c->blocks) {
+    fr::PointSlot sl{};
+    sl.wg_begin = wg;
+    sl.off_u = b.uoff; sl.off_q = b.ftoff; sl.off_ref = b.refoff;
+    sl.nupts = b.Nu; sl.ld = b.ld; sl.nelem = b.nelem;
+    sl.smat = b.d_smat; sl.rcpdjac = b.d_rcpdjac;
+    wg += fr::point_workgroups(b.Nu, b.ld);
+    host.push_back(sl);
+  }
+  if (!pm.d_slots) pm.d_slots = dev_upload(c, host.data(), host.size(), s);
+  pm.nslots = (int)host.size(); pm.nwg = wg; pm.on = true;
+  return true;
+}
+
+// The one-launch transformed flux needs every block's flux unfused (a plan
+// forced later may fuse it into step 3).
+bool tflux_multi_valid(const fr_ctx *c) {
+  for (auto &b : c->blocks)
+    if (flux_fused(c, b)) return false;
+  return true;
+}
+
+// Whether a multi-block launch of step st applies to the arrays in use: the
+// two-panel product's precomputed offsets assume the context's own D~ and F~.
+bool multi_usable(const fr_ctx *c, int st) {
+  if (st != 8) return true;
+  return c->cur.df == c->d_uf && c->cur.fto == (c->ns ? c->d_fto : c->d_ft);
+}
+
+// Issue the multi-block launches of step st; marks the blocks they cover.
+void run_multi(fr_ctx *c, int st, const double *u, double *dudt, int epi, const fr::RkCoef *rk,
+               const double *dt, hipStream_t s, std::vector<char> &done) {
+  if (!multi_usable(c, st)) return;
+  const int f32 = c->prec != FR_FP64;
+  const int gprec = c->prec == FR_FP64 ? fr::PREC_F64 : fr::PREC_F32;
+  for (int fam = 0; fam < 2; ++fam) {
+    MultiLaunch &ml = c->multi[st][fam];
+    if (!ml.on) continue;
+    fr::GemmArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.slots = ml.d_slots; g.nslots = ml.nslots; g.nwg = ml.nwg;
+    int batch = 1;
+    if (st == 1) {
+      g.B1 = c->devform ? (const void *)c->d_udev : (const void *)u;
+      g.b1_f32 = g.b2_f32 = c->devform ? 1 : 0;
+      g.C = c->cur.uf; g.c_f32 = f32;
+    } else if (st == 5) {
+      g.B1 = c->cur.ft; g.b1_f32 = f32; g.b2_f32 = f32;
+      g.C = c->cur.qf; g.c_f32 = f32;
+      batch = c->D;
+    } else {
+      g.B1 = c->cur.df; g.b1_f32 = f32;
+      g.B2 = c->cur.fto; g.b2_f32 = f32;
+      g.out = dudt;
+      g.K2 = 1;  // two panels
+      if (epi == fr::EPI_RK) {
+        g.acc = c->cur.acc ? c->cur.acc : c->d_acc;
+        g.stage = c->cur.stage_out;
+        g.dt = dt; g.rk = *rk;
+      }
+    }
+    if (fam == 0) {
+      hip_check(fr::launch_spop_multi(gprec, epi, g, ml.width, ml.fields, batch, s),
+                "multi-block sparse-row product");
+    } else {
+      // g.N is per slot; any positive value passes the launcher's empty check
+      g.MBW = ml.MBW; g.NC = ml.NC; g.N = 1;
+      hip_check(fr::launch_gemm(gprec, epi, g, batch, s), "multi-block matrix-core product");
+    }
+    for (int bi : ml.blocks) done[bi] = 1;
+  }
 }
 
 // Steps of the right-hand side (every block):
@@ -439,12 +772,36 @@ void run_step(fr_ctx *c, int st, const double *u, double *dudt, int epi, const f
     if (c->nbpts) hip_check(fr::launch_bc_comm_flux(bc_args(c), c->ns, s), "boundary comm_flux");
     return;
   }
-  for (auto &b : c->blocks) {
+  // one launch per kernel family over several blocks where set up
+  std::vector<char> done(c->blocks.size(), 0);
+  if (st == 1 || st == 5 || st == 8) run_multi(c, st, u, dudt, epi, rk, dt, s, done);
+  if (st == 6 && c->tflux_multi.on && tflux_multi_valid(c)) {
+    fr::PointArgs a = point_args(c, c->blocks[0], u);
+    a.u = u;
+    a.q = c->cur.ft;
+    a.fout = c->cur.fto != c->cur.ft ? c->cur.fto : nullptr;
+    if (c->devform) {
+      a.udev = c->d_udev;
+      a.uref = c->d_uref;
+    }
+    a.slots = c->tflux_multi.d_slots; a.nslots = c->tflux_multi.nslots; a.nwg = c->tflux_multi.nwg;
+    hip_check(fr::launch_tflux(a, c->ns, s), "multi-block tflux");
+    return;
+  }
+  for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
+    if (done[bi]) continue;
+    BlockRT &b = c->blocks[bi];
     const int64_t N = NV * b.ld;
     if (st == 1) {
       fr::GemmArgs g = gemm_args(b.m0);
       g.ld = b.ld;
-      g.B1 = u + b.uoff; g.ldb1 = N; g.b1_f32 = 0;
+      if (c->devform) {
+        // one panel: B2 is never read, typed as B1 so that both panels share
+        // an element size (precomputed-gather kernels)
+        g.B1 = elem(c->d_udev, b.uoff, ts); g.ldb1 = N; g.b1_f32 = 1; g.b2_f32 = 1;
+      } else {
+        g.B1 = u + b.uoff; g.ldb1 = N; g.b1_f32 = 0;
+      }
       g.C = elem(c->cur.uf, b.ufoff, ts); g.ldc = N; g.c_f32 = f32;
       g.N = N;
       hip_check(launch_op(b.m0, gprec, fr::EPI_STORE, g, 1, s), "gemm M0");
@@ -503,9 +860,30 @@ void run_step(fr_ctx *c, int st, const double *u, double *dudt, int epi, const f
 // The right-hand-side chain, steps 1..min(stop, 8).  epi: EPI_NEGDIV writes
 // dudt; EPI_RK applies the RK stage update `rk` with registers (dudt = u,
 // acc, stage).
+// Order of the steps: the deviation form computes the transformed flux
+// first, since it also writes the deviations step 1 interpolates.
+const std::vector<int> &chain_order(const fr_ctx *c) {
+  static const std::vector<int> plain{1, 2, 3, 4, 5, 6, 7, 8}, dev{6, 1, 7, 8};
+  return c->devform ? dev : plain;
+}
+
+// The right-hand-side chain in its order, up to and including step `stop`
+// (stop 0: nothing).
 void rhs_chain(fr_ctx *c, const double *u, double *dudt, int epi, const fr::RkCoef *rk,
                const double *dt, hipStream_t s, int stop = 8) {
-  for (int st = 1; st <= stop && st <= 8; ++st) run_step(c, st, u, dudt, epi, rk, dt, s);
+  if (stop < 1) return;
+  for (int st : chain_order(c)) {
+    run_step(c, st, u, dudt, epi, rk, dt, s);
+    if (st == stop) break;
+  }
+}
+
+// The steps that come before `step` in the chain's order (inputs of step).
+int step_before(const fr_ctx *c, int step) {
+  const std::vector<int> &o = chain_order(c);
+  for (size_t i = 0; i < o.size(); ++i)
+    if (o[i] == step) return i ? o[i - 1] : 0;
+  return 0;
 }
 
 // Time every instantiated plan of each operator product on this mesh (the
@@ -593,6 +971,76 @@ void tune_op(fr_ctx *c, GemmOp &op, int step, BlockRT &b, hipStream_t s) {
   }
 }
 
+// One launch per kernel family over the blocks of a multi-block mesh is
+// switched off: with it, the set-up or the first right-hand side of a
+// 12-problem batched mesh (six blocks) made a GPU memory access fault whose
+// cause is not yet found.  The launches stay built but unused; multi-block
+// meshes launch per block.
+constexpr bool kMultiBlockLaunches = false;
+
+// Mean time of step st over 5 launches (after 2), with the RK epilogue the
+// step graph uses for step 8 (dt = 0: values meaningless, traffic the same).
+float time_step_ms(fr_ctx *c, int st, hipStream_t s) {
+  const int epi = st == 8 ? fr::EPI_RK : fr::EPI_STORE;
+  fr::RkCoef rk;
+  rk.a_next = 0.5; rk.b = 1.0 / 3; rk.first = 0; rk.last = 0;
+  const fr::RkCoef *rkp = st == 8 ? &rk : nullptr;
+  const double *dtp = st == 8 ? c->d_tune_dt : nullptr;
+  hipEvent_t e0, e1;
+  hip_check(hipEventCreate(&e0), "event");
+  hip_check(hipEventCreate(&e1), "event");
+  float ms = 0;
+  try {
+    for (int w = 0; w < 2; ++w) run_step(c, st, c->d_stage, c->d_acc, epi, rkp, dtp, s);
+    hip_check(hipEventRecord(e0, s), "record");
+    for (int w = 0; w < 5; ++w) run_step(c, st, c->d_stage, c->d_acc, epi, rkp, dtp, s);
+    hip_check(hipEventRecord(e1, s), "record");
+    hip_check(hipEventSynchronize(e1), "sync");
+    hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+  } catch (...) {
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    throw;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return ms / 5;
+}
+
+// Steps 1, 5, 8 and 6 of a multi-block mesh: one launch per kernel family
+// over its blocks (each block keeping its tuned rows per workgroup, or its
+// row split), kept where it is not slower than a launch per block; for the
+// sparse-row family one or all fields per thread, for the matrix cores 1,
+// 2 or 4 column strips per wavefront.
+void tune_multi(fr_ctx *c, hipStream_t s) {
+  if (c->blocks.size() < 2 || c->prec == FR_BF16X3) return;
+  for (int st : {1, 5, 8}) {
+    if (st == 5 && !c->ns) continue;
+    free_multi(c->multi[st][0]);
+    free_multi(c->multi[st][1]);
+    float best = time_step_ms(c, st, s);
+    int bestF = 0;
+    for (int F : {1, c->NV})
+      if (build_multi_sparse(c, st, F, s)) {
+        const float t = time_step_ms(c, st, s);
+        if (t <= best) { best = t; bestF = F; }
+      }
+    if (bestF) build_multi_sparse(c, st, bestF, s);
+    else free_multi(c->multi[st][0]);
+    int bestNC = 0;
+    for (int NC : {1, 2, 4})
+      if (build_multi_mfma(c, st, NC, s)) {
+        const float t = time_step_ms(c, st, s);
+        if (t <= best) { best = t; bestNC = NC; }
+      }
+    if (bestNC) build_multi_mfma(c, st, bestNC, s);
+    else free_multi(c->multi[st][1]);
+  }
+  c->tflux_multi.on = false;
+  const float t_sep = time_step_ms(c, 6, s);
+  if (build_tflux_multi(c, s) && time_step_ms(c, 6, s) > t_sep) c->tflux_multi.on = false;
+}
+
 void autotune(fr_ctx *c, hipStream_t s) {
   for (auto &b : c->blocks) {
     tune_op(c, b.m0, 1, b, s);
@@ -602,6 +1050,9 @@ void autotune(fr_ctx *c, hipStream_t s) {
       tune_op(c, b.m5, 5, b, s);
     }
   }
+  // one launch per kernel family over several blocks: switched off (see
+  // kMultiBlockLaunches)
+  if (kMultiBlockLaunches) tune_multi(c, s);
   hip_check(hipStreamSynchronize(s), "tune sync");
 }
 
@@ -1242,7 +1693,7 @@ fr_status fr_setup_mesh_bc(const fr_config *cfg, int32_t nblocks, const fr_block
     std::map<std::tuple<int, int, int>, int> refmap;
     std::vector<fr::BlockGeom> geoms;
     std::vector<int> block_ref;
-    int64_t uoff = 0, ufoff = 0, qfoff = 0, ftoff = 0, poff = 0;
+    int64_t uoff = 0, ufoff = 0, qfoff = 0, ftoff = 0, poff = 0, refoff = 0;
     for (int bi = 0; bi < nblocks; ++bi) {
       const fr_block &B = blocks[bi];
       if (B.nelem < 1 || !B.nodes) throw Fail{FR_EINVAL, "block without elements or nodes"};
@@ -1267,6 +1718,7 @@ fr_status fr_setup_mesh_bc(const fr_config *cfg, int32_t nblocks, const fr_block
       rt.qfoff = qfoff; qfoff += (int64_t)D * rt.Nf * NV * rt.ld;
       rt.ftoff = ftoff; ftoff += (int64_t)D * rt.Nu * NV * rt.ld;
       rt.part_off = poff; poff += B.nelem;
+      rt.refoff = refoff; refoff += (int64_t)NV * rt.ld;
       c->blocks.push_back(std::move(rt));
     }
     c->total_len = uoff; c->uf_len = ufoff; c->qf_len = c->ns ? qfoff : 0; c->ft_len = ftoff;
@@ -1325,12 +1777,14 @@ fr_status fr_setup_mesh_bc(const fr_config *cfg, int32_t nblocks, const fr_block
         b.d_prob = dev_upload(c.get(), blocks[bi].problem, b.nelem, s);
       }
       const int64_t N = (int64_t)NV * b.ld;
+      // LDS chunk hints: the flux points of one face, one direction of F~
+      const int nface = b.etype == 0 ? 4 : b.etype == 1 ? 3 : 6;
       make_op(c.get(), b.m0, R.M0, R.nfpts, R.nupts, 0, N, s);
       make_op(c.get(), b.s8, hcat(R.M3, R.nfpts, R.M1p, D * R.nupts, R.nupts), R.nupts,
-              R.nfpts, D * R.nupts, N, s);
+              R.nfpts, D * R.nupts, N, s, nullptr, R.nfpts / nface, R.nupts);
       if (c->ns) {
         make_op(c.get(), b.s3, hcat(R.M6, R.nfpts, R.M4p, R.nupts, D * R.nupts), D * R.nupts,
-                R.nfpts, R.nupts, N, s);
+                R.nfpts, R.nupts, N, s, nullptr, R.nfpts / nface);
         make_op(c.get(), b.m5, R.M0, R.nfpts, R.nupts, 0, D * N, s);
       }
       G = fr::BlockGeom();
@@ -1357,20 +1811,48 @@ fr_status fr_setup_mesh_bc(const fr_config *cfg, int32_t nblocks, const fr_block
       c->d_blk_qstride = dev_upload(c.get(), qs.data(), qs.size(), s);
     }
     // scratch
-    c->d_uf = c->prec == FR_FP64 ? (void *)dev_alloc<double>(c.get(), c->uf_len)
-                                  : (void *)dev_alloc<float>(c.get(), c->uf_len);
-    c->d_ft = c->prec == FR_FP64 ? (void *)dev_alloc<double>(c.get(), c->ft_len)
-                                  : (void *)dev_alloc<float>(c.get(), c->ft_len);
+    // U^f (then D~) and F~ in one allocation, so that the divergence
+    // product's two panels lie within one 32-bit buffer range (precomputed
+    // row offsets) on meshes up to a few GiB of them
+    {
+      const int64_t al = 256 / (int64_t)c->tsize;  // 256-byte aligned parts
+      const int64_t nuf = (c->uf_len + al - 1) / al * al, nft = (c->ft_len + al - 1) / al * al;
+      const int64_t tot = nuf + nft + (c->ns ? nft : 0);
+      char *arena = c->prec == FR_FP64 ? (char *)dev_alloc<double>(c.get(), tot)
+                                       : (char *)dev_alloc<float>(c.get(), tot);
+      c->d_uf = arena;
+      c->d_ft = arena + nuf * c->tsize;
+      if (c->ns) c->d_fto = arena + (nuf + nft) * c->tsize;
+    }
     if (c->ns)
       c->d_qf = c->prec == FR_FP64 ? (void *)dev_alloc<double>(c.get(), c->qf_len)
                                     : (void *)dev_alloc<float>(c.get(), c->qf_len);
-    if (c->ns)
-      c->d_fto = c->prec == FR_FP64 ? (void *)dev_alloc<double>(c.get(), c->ft_len)
-                                     : (void *)dev_alloc<float>(c.get(), c->ft_len);
     c->d_acc = dev_alloc<double>(c.get(), c->total_len);
     c->d_stage = dev_alloc<double>(c.get(), c->total_len);
+    c->devform = !c->ns && c->prec != FR_FP64;
+    if (c->devform) {
+      c->d_udev = dev_alloc<float>(c.get(), c->total_len);
+      int64_t nref = 0;
+      std::vector<int64_t> rb;
+      for (auto &b : c->blocks) { rb.push_back(b.refoff); nref += (int64_t)NV * b.ld; }
+      c->d_uref = dev_alloc<double>(c.get(), nref);
+      c->d_blk_refbase = dev_upload(c.get(), rb.data(), rb.size(), s);
+    }
     c->cur = fr_ctx::Bufs{c->d_uf, c->d_qf, c->d_ft, c->d_uf, c->ns ? c->d_fto : c->d_ft,
                           c->d_stage};
+    // precomputed row offsets of the sparse-row products of steps 1, 5 and 8
+    // (single-block meshes: on meshes of several blocks the precomputed-gather
+    // kernel is not used, as the multi-block launches built on it are off)
+    for (auto &b : c->blocks) {
+      if (c->blocks.size() > 1) break;
+      const int64_t rsu = (int64_t)NV * b.ld * 8, rst = (int64_t)NV * b.ld * (int64_t)c->tsize;
+      // step 1 reads the state, or in the deviation form its FP32 deviation
+      const int64_t rs0 = c->devform ? rst : rsu;
+      build_row_offsets(c.get(), b.m0, nullptr, rs0, nullptr, 0, rs0, s);
+      if (c->ns) build_row_offsets(c.get(), b.m5, nullptr, rst, nullptr, 0, rst, s);
+      build_row_offsets(c.get(), b.s8, elem(c->cur.df, b.ufoff, c->tsize), rst,
+                        elem(c->cur.fto, b.ftoff, c->tsize), rst, rst, s);
+    }
     // reductions: element partials and per-problem element lists
     {
       // enough workgroups to fill the chip on small meshes
@@ -1653,6 +2135,42 @@ fr_status fr_integrate(fr_ctx *c, const double *u, int32_t kind, double *out, vo
   return FR_OK;
 }
 
+fr_status fr_debug_multi(fr_ctx *c, int32_t step, int32_t mode, int32_t *state,
+                         void *hip_stream) {
+  if (!c || (step != 1 && step != 5 && step != 6 && step != 8)) return FR_EINVAL;
+  if (step == 5 && !c->ns) return fail(c, FR_EINVAL, "no such step");
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    if (mode > 0 && !kMultiBlockLaunches)
+      return fail(c, FR_EUNSUPPORTED, "multi-block launches are switched off");
+    if (mode >= 0) {
+      // captured graphs hold the current slot tables as kernel arguments:
+      // release them before the tables are freed and rebuilt
+      hip_check(hipDeviceSynchronize(), "sync");
+      release_graph(c);
+      release_stepper_graphs(c);
+      if (step == 6) {
+        c->tflux_multi.on = false;
+        if (mode > 0) build_tflux_multi(c, s);
+      } else {
+        free_multi(c->multi[step][0]);
+        free_multi(c->multi[step][1]);
+        if (mode > 0 && c->prec != FR_BF16X3) {
+          build_multi_sparse(c, step, mode == 1 ? 1 : c->NV, s);
+          build_multi_mfma(c, step, mode == 1 ? 1 : 2, s);
+        }
+      }
+    }
+    if (state) {
+      *state = step == 6 ? (c->tflux_multi.on ? 4 : 0)
+                         : (c->multi[step][0].on ? 1 : 0) | (c->multi[step][1].on ? 2 : 0);
+    }
+  } catch (const Fail &f) {
+    return fail(c, f.st, f.msg);
+  }
+  return FR_OK;
+}
+
 fr_status fr_integrate_noalloc(fr_ctx *c, const double *u, int32_t kind, double *out,
                                void *hip_stream) {
   if (!c) return FR_EINVAL;
@@ -1791,14 +2309,23 @@ fr_status fr_debug_stage(fr_ctx *c, const double *u, int32_t stage, double *out,
 
 fr_status fr_bench_step(fr_ctx *c, const double *u, int32_t step, int32_t nrep,
                         void *hip_stream) {
-  if (!c || !u || step < 1 || step > 8 || nrep < 0) return FR_EINVAL;
+  if (!c || !u || step < 1 || step > 9 || nrep < 0) return FR_EINVAL;
   if (!c->ns && step >= 2 && step <= 5) return fail(c, FR_EINVAL, "no such step for Euler");
   hipStream_t s = (hipStream_t)hip_stream;
   try {
-    rhs_chain(c, u, nullptr, fr::EPI_NEGDIV, nullptr, nullptr, s, step - 1);
+    rhs_chain(c, u, nullptr, fr::EPI_NEGDIV, nullptr, nullptr, s,
+              step_before(c, std::min(step, 8)));
     // step 7 works in place, so its repeats read the previous repeat's
     // output: the same arithmetic and traffic on other values (timing only)
-    for (int i = 0; i < nrep; ++i)
+    if (step == 9) {
+      // step 8 with the RK4 update of a middle stage, as the step graph runs
+      // it (reads u and acc, writes acc and the next stage; dt = 0)
+      fr::RkCoef rk;
+      rk.a_next = 0.5; rk.b = 1.0 / 3; rk.first = 0; rk.last = 0;
+      for (int i = 0; i < nrep; ++i)
+        run_step(c, 8, c->d_stage, c->d_acc, fr::EPI_RK, &rk, c->d_tune_dt, s);
+    }
+    for (int i = 0; step <= 8 && i < nrep; ++i)
       run_step(c, step, u, c->d_acc, fr::EPI_NEGDIV, nullptr, nullptr, s);
   } catch (const Fail &f) {
     return fail(c, f.st, f.msg);
@@ -1827,7 +2354,10 @@ fr_status fr_debug_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, const d
     GemmOp op;
     std::vector<double> Av(A, A + (size_t)M * (K1 + K2));
     fr::GemmPlan p{mbw, nc, wm};
-    if (mbw > 0 && (!fr::gemm_plan_valid(mbw, nc) || wm < 1 || mbw * wm * 16 < M))
+    if (mbw > 0 && (!fr::gemm_plan_valid(mbw, nc, wm, prec == FR_FP64 ? fr::PREC_F64
+                                                       : (prec == FR_FP32 ? fr::PREC_F32
+                                                                          : fr::PREC_BF16X3)) ||
+                    wm < 1 || mbw * wm * 16 < M))
       throw Fail{FR_EINVAL, "bad plan"};
     if (mbw == 0 && (nc < 0 || wm != 0)) throw Fail{FR_EINVAL, "bad plan"};
     make_op(&tmp, op, Av, M, K1, K2, N, s, (mbw > 0 || nc > 0) ? &p : nullptr);
@@ -1872,7 +2402,10 @@ fr_status fr_bench_gemm(int32_t prec, int32_t M, int32_t K1, int32_t K2, int64_t
     GemmOp op;
     std::vector<double> A((size_t)M * (K1 + K2), 0.5);
     fr::GemmPlan p{mbw, nc, wm};
-    if (mbw > 0 && (!fr::gemm_plan_valid(mbw, nc) || wm < 1 || mbw * wm * 16 < M))
+    if (mbw > 0 && (!fr::gemm_plan_valid(mbw, nc, wm, prec == FR_FP64 ? fr::PREC_F64
+                                                       : (prec == FR_FP32 ? fr::PREC_F32
+                                                                          : fr::PREC_BF16X3)) ||
+                    wm < 1 || mbw * wm * 16 < M))
       throw Fail{FR_EINVAL, "bad plan"};
     make_op(&tmp, op, A, M, K1, K2, N, s, mbw > 0 ? &p : nullptr);
     void *B1 = dev_alloc<char>(&tmp, (size_t)K1 * N * batch * es);
@@ -1941,10 +2474,22 @@ fr_status fr_debug_set_plan(fr_ctx *c, int32_t block, int32_t step, int32_t mbw,
   GemmOp *op = step == 1 ? &b.m0 : step == 3 ? &b.s3 : step == 5 ? &b.m5 : step == 8 ? &b.s8
                : step == 13 ? &b.t_m0 : step == 14 ? &b.t_m1 : nullptr;
   if (!op || (!c->ns && (step == 3 || step == 5))) return fail(c, FR_EINVAL, "no such step");
+  // a forced plan runs as it is: no multi-block launch of this step.  Graphs
+  // captured before hold the old plan's kernel arguments (operator copies,
+  // slot tables): release them before anything they point at is freed.
+  hipDeviceSynchronize();
+  release_graph(c);
+  release_stepper_graphs(c);
+  if (step == 1 || step == 5 || step == 8) {
+    free_multi(c->multi[step][0]);
+    free_multi(c->multi[step][1]);
+  }
   try {
     fr::GemmPlan p{mbw, nc, wm};
     if (mbw > 0) {
-      if (!fr::gemm_plan_valid(mbw, nc) || wm < 1 || mbw * wm * 16 < op->M)
+      const int gp = c->prec == FR_FP64 ? fr::PREC_F64
+                     : (c->prec == FR_FP32 ? fr::PREC_F32 : fr::PREC_BF16X3);
+      if (!fr::gemm_plan_valid(mbw, nc, wm, gp) || wm < 1 || mbw * wm * 16 < op->M)
         throw Fail{FR_EINVAL, "bad matrix-core plan"};
       op->d_A = pack_upload(c, *op, p, s, true);
     } else {
@@ -1999,6 +2544,8 @@ void fr_destroy(fr_ctx *c) {
   release_graph(c);
   release_stepper_graphs(c);
   if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  for (auto &row : c->multi)
+    for (auto &ml : row) free_multi(ml);
   for (void *p : c->allocs) hipFree(p);
   delete c;
 }

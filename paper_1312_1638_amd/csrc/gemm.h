@@ -54,7 +54,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   typedef typename Mma<T>::acc_t acc_t;
   constexpr int KC = Chunk<MBW, NC>::KC;
   const int lane = threadIdx.x & 63;
-  const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  // multi-block launch: this workgroup's block and its index within it
+  int64_t wg = blockIdx.x;
+  if (g.slots) wg = take_slot(g, wg, sizeof(TB1), sizeof(TB2), sizeof(TC));
+  const int64_t gw = wg * 4 + (threadIdx.x >> 6);
   const int rg = (int)(gw % g.WM);
   const int64_t n0 = (gw / g.WM) * (16 * NC);
   if (n0 >= g.N) return;
@@ -159,9 +162,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 
 template <typename T, int MBW, int NC, int EPI>
 hipError_t launch_gemm_shape(const GemmArgs &g, int batch, hipStream_t s) {
-  const int64_t tiles = (g.N + 16 * NC - 1) / (16 * NC);
-  const int64_t waves = tiles * g.WM;
-  dim3 grid((unsigned)((waves + 3) / 4), batch), block(256);
+  // multi-block launch: every slot's workgroups
+  const int64_t wgs = g.slots ? g.nwg : gemm_workgroups(g.N, NC, g.WM);
+  dim3 grid((unsigned)wgs, batch), block(256);
   if constexpr (sizeof(T) == 8) {
     gemm_kernel<T, MBW, NC, EPI, double, double, double><<<grid, block, 0, s>>>(g);
   } else if constexpr (EPI == EPI_NEGDIV || EPI == EPI_RK) {

@@ -17,6 +17,17 @@ bool gemm_plan_valid(int MBW, int NC) {
   return false;
 }
 
+bool gemm_plan_valid(int MBW, int NC, int WM, int prec) {
+  if (NC >= 64) {
+    bool ok = false;
+#define FR_CASE(MB_, WM_, TW_) ok = ok || (MB_ == MBW && WM_ == WM && TW_ == NC);
+    FR_BF16_LDS_SHAPES(FR_CASE)
+#undef FR_CASE
+    return ok && prec == PREC_BF16X3;
+  }
+  return gemm_plan_valid(MBW, NC);
+}
+
 static int round_mbw(int need) {
   const int vals[] = {1, 2, 3, 4, 6, 8, 12};
   for (int v : vals)
@@ -36,9 +47,21 @@ GemmPlan gemm_plan(int M, int64_t N, int prec) {
 }
 
 std::vector<GemmPlan> gemm_candidates(int M, int64_t N, int prec) {
-  (void)prec;
   std::vector<GemmPlan> out;
   const int MB = (M + 15) / 16;
+  if (prec == PREC_BF16X3) {
+    // LDS-staged plans: for each row split WM and column tile TW, the
+    // smallest instantiated MBW that covers the rows
+    for (int wm : {1, 2, 4})
+      for (int tw : {64, 128}) {
+        int best = 0;
+#define FR_CASE(MB_, WM_, TW_) \
+  if (WM_ == wm && TW_ == tw && MB_ * WM_ >= MB && (best == 0 || MB_ < best)) best = MB_;
+        FR_BF16_LDS_SHAPES(FR_CASE)
+#undef FR_CASE
+        if (best && N >= tw) out.push_back(GemmPlan{best, tw, wm});
+      }
+  }
   for (int wm = 1; wm <= std::min(MB, 12); ++wm) {
     const int mbw = round_mbw((MB + wm - 1) / wm);
     if (mbw < 0) continue;

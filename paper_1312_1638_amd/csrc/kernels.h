@@ -66,7 +66,54 @@ struct GemmArgs {
   const double *smat; int D; int Nu;          // EPI_GRADT: S = adj J [D][D][Nu][ld]
   void *fout; double gamma, mu, prandtl;      // EPI_GRADTF: F~ (type TC, layout of C)
   const double *uprim, *qprim;                // EPI_TFVJP: primal u and Q (Q null: Euler)
+  // sparse-row kernel with precomputed gathers: roff[r * width + e] is the
+  // byte offset, from rbase, of the B row of entry e of operator row r
+  // (both panels), rbase + (batch slice) addressed through one 32-bit
+  // buffer range; null: rows located from the column index at run time
+  const uint32_t *roff; const void *rbase;
+  // multi-block launch: one launch covers the workgroups of every slot; the
+  // pointers above are then the bases of whole arrays (slot offsets added)
+  const struct LaunchSlot *slots; int nslots; int64_t nwg;  // nwg: workgroups of all slots
 };
+
+// One element block of a multi-block launch (one launch of an operator
+// product over several blocks of a mixed or batched mesh): its workgroups
+// [wg_begin, next slot's wg_begin), the element offsets of its operands
+// from the launch's base pointers, and its own operator and geometry.
+struct LaunchSlot {
+  int64_t wg_begin;
+  int64_t off_b1, off_b2, off_c, off_u;   // B1, B2, C, and out/acc/stage
+  int64_t ld, N, nelem, sB1, sC;           // ldb1 = ldb2 = ldc = N
+  const void *Apack;                       // matrix-core plans
+  const int32_t *colidx; const double *vals; const uint32_t *roff;  // sparse-row plans
+  int rbase_b2;                            // two panels: rbase is B2 (else B1)
+  const double *rcpdjac; const int32_t *prob;
+  int M, K1, K2, KS1, KS2, WM, rpg, ngroups;
+};
+
+// Patch a multi-block launch's arguments with the slot of workgroup `wg`
+// (slots sorted by wg_begin, at most a few dozen); returns the workgroup's
+// index within its slot.  Element sizes: ts1 (B1), ts2 (B2), tc (C).
+__device__ __forceinline__ int64_t take_slot(GemmArgs &g, int64_t wg, size_t ts1, size_t ts2,
+                                             size_t tc, const LaunchSlot **which = nullptr) {
+  int k = 0;
+  while (k + 1 < g.nslots && wg >= g.slots[k + 1].wg_begin) ++k;
+  const LaunchSlot &sl = g.slots[k];
+  if (which) *which = &sl;
+  g.B1 = (const char *)g.B1 + sl.off_b1 * (int64_t)ts1;
+  if (g.B2) g.B2 = (const char *)g.B2 + sl.off_b2 * (int64_t)ts2;
+  if (g.C) g.C = (char *)g.C + sl.off_c * (int64_t)tc;
+  if (g.out) g.out += sl.off_u;
+  if (g.acc) g.acc += sl.off_u;
+  if (g.stage) g.stage += sl.off_u;
+  g.ldb1 = g.ldb2 = g.ldc = g.N = sl.N;
+  g.ld = sl.ld; g.nelem = sl.nelem; g.sB1 = sl.sB1; g.sC = sl.sC;
+  g.Apack = sl.Apack; g.roff = sl.roff;
+  g.rbase = sl.rbase_b2 ? g.B2 : g.B1;
+  g.rcpdjac = sl.rcpdjac; g.prob = sl.prob;
+  g.M = sl.M; g.K1 = sl.K1; g.K2 = sl.K2; g.KS1 = sl.KS1; g.KS2 = sl.KS2; g.WM = sl.WM;
+  return wg - sl.wg_begin;
+}
 
 // Pack A (M x (K1 + K2), row-major, panel 2 columns follow panel 1) into the
 // fragment layout the kernel reads; returns element count, writes into dst
@@ -92,6 +139,12 @@ struct SparseOp {
   int width;               // one of FR_SPOP_WIDTHS
   int rpg;                 // operator rows per workgroup row
   int fields;              // fields per thread: 1, or the field count (N = fields * ld)
+  // precomputed byte offsets of every entry's B row ([M][width]) for the
+  // operand arrays of the context's own right-hand side: from panel 1 for a
+  // one-panel operator (valid for any operand address), from the lower of
+  // the two panels otherwise (valid while B2 - B1 == roff_delta bytes)
+  const uint32_t *roff = nullptr;
+  int64_t roff_delta = 0;
 };
 #define FR_SPOP_WIDTHS(X) \
   X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(10) X(12) X(14) X(15) X(16) X(18) X(20) X(21) X(24) X(32)
@@ -108,9 +161,15 @@ int spop_width(int nnz_max);
 struct StagedOp {
   const int32_t *colidx;   // [nchunk][M][width]
   const double *vals;      // [nchunk][M][width]
-  int width;               // one of FR_LDS_WIDTHS
-  int kc;                  // B rows per chunk (kc x 64 values of LDS)
+  int width;               // one of FR_LDS_WIDTHS (at least every chunk's own width)
+  int kc;                  // most B rows of a chunk (kc x 64 values of LDS)
   int nchunk;
+  // chunk c holds B rows [cstart[c], cstart[c + 1]); its rows hold cwidth[c]
+  // entries each (the rest of `width` unused).  Chunks follow the operator's
+  // structure where they can (the faces of a face group, one direction of the
+  // transformed flux), so every row of a chunk has about the same count.
+  const int32_t *cstart = nullptr;
+  const int32_t *cwidth = nullptr;
 };
 #define FR_LDS_WIDTHS(X) X(4) X(8) X(12)
 // output rows per wavefront (4 wavefronts split the M rows of a tile)
@@ -128,6 +187,32 @@ hipError_t launch_spop_lds_f32(int epi, const GemmArgs &g, const StagedOp &op, i
 int spop_lds_width(int nnz_max);
 hipError_t launch_spop(int prec, int epi, const GemmArgs &g, const SparseOp &sp, int batch,
                        hipStream_t s);
+// One launch over every slot of g.slots (g.nwg workgroups): the sparse-row
+// kernel with precomputed gathers, ELL width `width` in every slot, `fields`
+// fields per thread; epilogues store, -1/J and RK.
+hipError_t launch_spop_multi(int prec, int epi, const GemmArgs &g, int width, int fields,
+                             int batch, hipStream_t s);
+hipError_t launch_spop_multi_fields(int prec, int epi, const GemmArgs &g, int width, int fields,
+                                    int batch, hipStream_t s);
+// workgroups (four wavefronts each) of one block's matrix-core launch
+inline int64_t gemm_workgroups(int64_t N, int NC, int WM) {
+  return ((N + 16 * NC - 1) / (16 * NC) * WM + 3) / 4;
+}
+// workgroups of one block's sparse-row launch (column tiles padded to a
+// multiple of the 8 XCDs, times the row groups)
+inline int64_t spop_workgroups(int64_t threads, int M, int rpg) {
+  return ((threads + 255) / 256 + 7) / 8 * 8 * ((M + rpg - 1) / rpg);
+}
+
+// LDS-staged BF16x3 plans (MBW, WM, column tile TW = NC): four wavefronts
+// per workgroup split WM row groups and TW / 16 strips
+#define FR_BF16_LDS_SHAPES(X)                                                                 \
+  X(1, 4, 64) X(2, 4, 64) X(3, 4, 64) X(4, 4, 64) X(6, 4, 64)                                \
+  X(1, 2, 64) X(2, 2, 64) X(3, 2, 64) X(4, 2, 64) X(6, 2, 64) X(8, 2, 64)                    \
+  X(1, 1, 64) X(2, 1, 64) X(3, 1, 64) X(4, 1, 64) X(6, 1, 64) X(8, 1, 64) X(12, 1, 64)       \
+  X(1, 4, 128) X(2, 4, 128)                                                                  \
+  X(1, 2, 128) X(2, 2, 128) X(3, 2, 128) X(4, 2, 128)                                        \
+  X(1, 1, 128) X(2, 1, 128) X(4, 1, 128) X(6, 1, 128) X(8, 1, 128)
 
 // MBW > 0: matrix-core plan; MBW == 0: sparse-row kernel with NC = rows per group.
 struct GemmPlan { int MBW, NC, WM; };
@@ -136,6 +221,8 @@ GemmPlan gemm_plan(int M, int64_t N, int prec);
 // Every instantiated plan worth timing for this shape (autotuner).
 std::vector<GemmPlan> gemm_candidates(int M, int64_t N, int prec);
 bool gemm_plan_valid(int MBW, int NC);
+// with the row split and the precision (NC >= 64: LDS-staged BF16x3 plans)
+bool gemm_plan_valid(int MBW, int NC, int WM, int prec);
 
 // ----------------------------------------------------------------------------
 // Point-wise and interface kernels
@@ -150,7 +237,27 @@ struct PointArgs {
   void *fout;              // transformed-flux output (null: over q)
   int q_f32;
   double gamma, mu, prandtl;
+  // multi-block launch: the pointers above are whole-array bases and each
+  // slot names its block's part (nwg workgroups in all)
+  const struct PointSlot *slots; int nslots; int64_t nwg;
+  // Euler in reduced precision: deviation form.  udev (type of q, state
+  // layout) receives u - u_ref, uref [NV][ld] receives the reference state
+  // of each element (its state at solution point 0), and the transformed
+  // flux is written as S (f(u) - f(u_ref)).  Null: plain form.
+  void *udev; double *uref;
 };
+
+// One element block of a multi-block point-wise launch.
+struct PointSlot {
+  int64_t wg_begin;
+  int64_t off_u, off_q;      // elements of u (and udev), and of q / fout (same layout)
+  int64_t off_ref;           // elements of uref
+  int nupts; int64_t ld, nelem;
+  const double *smat, *rcpdjac;
+};
+
+// workgroups of one block's point-wise launch
+inline int64_t point_workgroups(int nupts, int64_t ld) { return ((int64_t)nupts * ld + 255) / 256; }
 
 // S4: q = J^-T q~ in place
 hipError_t launch_gradcoru(const PointArgs &a, hipStream_t s);
@@ -179,6 +286,12 @@ struct PairArgs {
   // boundary's parameters (layout of bc_ghosts in physics.h)
   const int32_t *bcid;
   const double *bcpar;
+  // Euler in reduced precision (deviation form): U^f holds U^f - u_ref of
+  // each side's element, uref [NV][ld] per block (blk_refbase: offsets of
+  // multi-block meshes) the references; the common flux is rebuilt from
+  // u_ref + U^f in FP64 and D~ written as J^f n^f (F - n.f(u_ref)).
+  const double *uref;
+  const int64_t *blk_refbase;
 };
 #define FR_BC_NPAR 12
 

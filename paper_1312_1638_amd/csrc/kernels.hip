@@ -60,8 +60,25 @@ __global__ __launch_bounds__(256) void gradcoru_kernel(PointArgs a) {
 template <int D, int NS, typename TQ>
 __global__ __launch_bounds__(256) void tflux_kernel(PointArgs a) {
   constexpr int NV = D + 2;
+  int64_t wg = blockIdx.x;
+  if (a.slots) {
+    // multi-block launch: this workgroup's block and its index within it
+    int k = 0;
+    while (k + 1 < a.nslots && wg >= a.slots[k + 1].wg_begin) ++k;
+    const PointSlot &sl = a.slots[k];
+    wg -= sl.wg_begin;
+    a.u += sl.off_u;
+    a.q = (TQ *)a.q + sl.off_q;
+    if (a.fout) a.fout = (TQ *)a.fout + sl.off_q;
+    if (a.udev) {
+      a.udev = (TQ *)a.udev + sl.off_u;
+      a.uref += sl.off_ref;
+    }
+    a.nupts = sl.nupts; a.ld = sl.ld; a.nelem = sl.nelem;
+    a.smat = sl.smat; a.rcpdjac = sl.rcpdjac;
+  }
   const int64_t plane = (int64_t)a.nupts * a.ld;
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t t = wg * 256 + threadIdx.x;
   if (t >= plane) return;
   const int64_t r = t / a.ld, n = t - r * a.ld;
   if (n >= a.nelem) return;
@@ -74,6 +91,24 @@ __global__ __launch_bounds__(256) void tflux_kernel(PointArgs a) {
   TQ *qo = a.fout ? (TQ *)a.fout : q;
   double f[D][NV], p, v[D];
   inviscid_flux<D>(u, a.gamma, f, p, v);
+  if (!NS && a.udev) {
+    // deviation form: the element's reference state (its first solution
+    // point), u - u_ref for the interpolation, f(u) - f(u_ref) for F~
+    double ub[NV], fb[D][NV], pb, vb[D];
+#pragma unroll
+    for (int al = 0; al < NV; ++al) ub[al] = a.u[n + al * a.ld];
+    inviscid_flux<D>(ub, a.gamma, fb, pb, vb);
+    TQ *ud = (TQ *)a.udev;
+#pragma unroll
+    for (int al = 0; al < NV; ++al) {
+      ud[base + al * a.ld] = (TQ)(u[al] - ub[al]);
+      if (r == 0) a.uref[al * a.ld + n] = ub[al];
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+      for (int al = 0; al < NV; ++al) f[j][al] -= fb[j][al];
+  }
   if (NS) {
     double g[D][NV], fv[D][NV];
 #pragma unroll
@@ -117,7 +152,7 @@ hipError_t launch_gradcoru(const PointArgs &a, hipStream_t s) {
 
 template <typename TQ>
 static hipError_t tflux_t(const PointArgs &a, int ns, hipStream_t s) {
-  unsigned nb = blocks_for((int64_t)a.nupts * a.ld);
+  unsigned nb = a.slots ? (unsigned)a.nwg : blocks_for((int64_t)a.nupts * a.ld);
   if (a.ndims == 2) {
     if (ns) tflux_kernel<2, 1, TQ><<<nb, 256, 0, s>>>(a);
     else tflux_kernel<2, 0, TQ><<<nb, 256, 0, s>>>(a);
@@ -144,7 +179,7 @@ __device__ __forceinline__ int64_t xcd_block(unsigned nreal) {
 }
 
 struct Side {
-  int64_t base, ld, qbase, qstride;
+  int64_t base, ld, qbase, qstride, rbase;
 };
 
 template <bool MULTI>
@@ -157,10 +192,33 @@ __device__ __forceinline__ Side side_of(const PairArgs &a, const int32_t *blk, i
     s.ld = a.blk_ld[b];
     s.qbase = q ? a.blk_qfbase[b] : 0;
     s.qstride = q ? a.blk_qstride[b] : 0;
+    s.rbase = a.uref ? a.blk_refbase[b] : 0;
   } else {
-    s.base = 0; s.ld = a.ld0; s.qbase = 0; s.qstride = a.qstride0;
+    s.base = 0; s.ld = a.ld0; s.qbase = 0; s.qstride = a.qstride0; s.rbase = 0;
   }
   return s;
+}
+
+// Deviation form (Euler, reduced precision): the reference state of the
+// element of flux point i (index sigma NV ld + n within its block) and the
+// normal component of its flux, n . f(u_ref).
+template <int D>
+__device__ __forceinline__ void side_reference(const PairArgs &a, const Side &S, int64_t i,
+                                               const double *n, double ub[D + 2],
+                                               double fn[D + 2]) {
+  constexpr int NV = D + 2;
+  const double *r = a.uref + S.rbase + i % S.ld;
+#pragma unroll
+  for (int al = 0; al < NV; ++al) ub[al] = r[al * S.ld];
+  double f[D][NV], p, v[D];
+  inviscid_flux<D>(ub, a.gamma, f, p, v);
+#pragma unroll
+  for (int al = 0; al < NV; ++al) {
+    double s = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) s += n[d] * f[d][al];
+    fn[al] = s;
+  }
 }
 
 template <int D, bool MULTI, typename T>
@@ -201,6 +259,17 @@ __global__ __launch_bounds__(256) void comm_flux_kernel(PairArgs a, unsigned nre
   }
 #pragma unroll
   for (int d = 0; d < D; ++d) n[d] = a.nrm[d * a.npairs + k];
+  double fnL[NV], fnR[NV];
+  const bool dev = !NS && a.uref;
+  if (dev) {
+    double ub[NV];
+    side_reference<D>(a, L, iL, n, ub, fnL);
+#pragma unroll
+    for (int al = 0; al < NV; ++al) uL[al] += ub[al];
+    side_reference<D>(a, R, iR, n, ub, fnR);
+#pragma unroll
+    for (int al = 0; al < NV; ++al) uR[al] += ub[al];
+  }
   rusanov<D>(uL, uR, n, a.gamma, F);
   if (NS) {
     const T *qf = (const T *)a.qf;
@@ -227,8 +296,9 @@ __global__ __launch_bounds__(256) void comm_flux_kernel(PairArgs a, unsigned nre
   T *df = a.dfout ? (T *)a.dfout : uf;
 #pragma unroll
   for (int al = 0; al < NV; ++al) {
-    df[L.base + iL + al * L.ld] = (T)(mL * F[al]);
-    df[R.base + iR + al * R.ld] = (T)(-mR * F[al]);
+    // deviation form: each side less its reference's own normal flux
+    df[L.base + iL + al * L.ld] = (T)(mL * (dev ? F[al] - fnL[al] : F[al]));
+    df[R.base + iR + al * R.ld] = (T)(-mR * (dev ? F[al] - fnR[al] : F[al]));
   }
 }
 
@@ -268,6 +338,14 @@ __global__ __launch_bounds__(256) void bc_comm_flux_kernel(PairArgs a) {
   for (int al = 0; al < NV; ++al) u[al] = (double)uf[L.base + i + al * L.ld];
 #pragma unroll
   for (int d = 0; d < D; ++d) n[d] = a.nrm[d * a.npairs + k];
+  double fn[NV];
+  const bool dev = !NS && a.uref;
+  if (dev) {
+    double ub[NV];
+    side_reference<D>(a, L, i, n, ub, fn);
+#pragma unroll
+    for (int al = 0; al < NV; ++al) u[al] += ub[al];
+  }
   bool qzero;
   bc_ghosts<D>(u, a.bcpar + (int64_t)a.bcid[k] * FR_BC_NPAR, a.gamma, ginv, gldg, qzero);
   rusanov<D>(u, ginv, n, a.gamma, F);
@@ -295,7 +373,7 @@ __global__ __launch_bounds__(256) void bc_comm_flux_kernel(PairArgs a) {
   const double m = a.magL[k];
   T *df = a.dfout ? (T *)a.dfout : uf;
 #pragma unroll
-  for (int al = 0; al < NV; ++al) df[L.base + i + al * L.ld] = (T)(m * F[al]);
+  for (int al = 0; al < NV; ++al) df[L.base + i + al * L.ld] = (T)(m * (dev ? F[al] - fn[al] : F[al]));
 }
 
 template <typename T>

@@ -37,23 +37,43 @@ constexpr int kRawBufferWord3 = 0x00020000;
 // is the lane's, so a gather costs one instruction and no vector address
 // arithmetic.
 template <typename TB>
-__device__ inline TB load_row(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+__device__ inline TB load_row(__amdgpu_buffer_rsrc_t rs, uint32_t off, uint32_t soff = 0) {
   if constexpr (sizeof(TB) == 8) {
-    return __builtin_bit_cast(TB, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0));
+    return __builtin_bit_cast(TB, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, (int)soff, 0));
   } else {
-    return __builtin_bit_cast(TB, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
+    return __builtin_bit_cast(TB, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, (int)soff, 0));
   }
 }
 
-template <typename T, int EPI, int W, typename TB1, typename TB2, typename TC, int DG, int F>
+// OFF: every entry's B row comes from the precomputed byte offsets g.roff
+// (one buffer resource over both panels, the row offset as the instruction's
+// scalar offset): no scalar address arithmetic per entry.
+template <typename T, int EPI, int W, typename TB1, typename TB2, typename TC, int DG, int F,
+          bool OFF = false>
 __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
                                                    const int32_t *__restrict__ colidx,
                                                    const double *__restrict__ vals, int rpg,
                                                    int ngroups) {
+  static_assert(!OFF || (EPI != EPI_ADDT && EPI != EPI_TFVJP && EPI != EPI_GRADT &&
+                         EPI != EPI_GRADTF),
+                "precomputed gathers and multi-block launches: store, add, -1/J, RK only");
+  // multi-block launch (precomputed-gather variant): this workgroup's
+  // block, its operator and its index within the block
+  int64_t L = blockIdx.x;
+  if constexpr (OFF) {
+    if (g.slots) {
+      const LaunchSlot *sl = nullptr;
+      L = take_slot(g, L, sizeof(TB1), sizeof(TB2), sizeof(TC), &sl);
+      vals = sl->vals;
+      rpg = sl->rpg;
+      ngroups = sl->ngroups;
+    }
+  }
   // linear id L -> XCD L % 8; the j-th workgroup of an XCD takes row group
   // j % ngroups of column tile 8 (j / ngroups) + L % 8 (tiles padded to a
-  // multiple of 8 by the launch)
-  const int64_t L = blockIdx.x, j = L >> 3;
+  // multiple of 8 by the launch, and every block's range of a multi-block
+  // launch starts at a multiple of 8)
+  const int64_t j = L >> 3;
   const int64_t tile = (j / ngroups) * 8 + (L & 7);
   const int rgrp = (int)(j % ngroups);
   // F == 1: t is the state column alpha * ld + n; F > 1: t is the element n
@@ -89,11 +109,37 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
 #pragma unroll
   for (int a = 0; a < F; ++a) toff[a] = (uint32_t)((t + a * fs) * (int64_t)sizeof(TB1));
 
+  // OFF: one resource from rbase (this workgroup's batch slice)
+  const __amdgpu_buffer_rsrc_t rsoff = __builtin_amdgcn_make_buffer_rsrc(
+      OFF ? (void *)((const char *)g.rbase + (int64_t)blockIdx.y * g.sB1 * (int64_t)sizeof(TB1))
+          : nullptr,
+      0, -1, kRawBufferWord3);
+
   // acc[a] = row `row` of A times field a's column (of panel 1 shifted by
   // boff elements: a batch slice)
   auto row_product = [&](int row, T(&acc)[F], int64_t boff = 0) {
-    const int32_t *__restrict__ ci = colidx + (int64_t)row * W;
     const double *__restrict__ cv = vals + (int64_t)row * W;
+    if constexpr (OFF) {
+      static_assert(sizeof(TB1) == sizeof(TB2), "one resource spans both panels");
+      const uint32_t *__restrict__ ro = g.roff + (int64_t)row * W;
+      uint32_t ko[W];
+#pragma unroll
+      for (int e = 0; e < W; ++e) ko[e] = ro[e];
+      T b[F][W];
+#pragma unroll
+      for (int e = 0; e < W; ++e)
+#pragma unroll
+        for (int a = 0; a < F; ++a) b[a][e] = (T)load_row<TB1>(rsoff, toff[a], ko[e]);
+#pragma unroll
+      for (int a = 0; a < F; ++a) {
+        T s = 0;
+#pragma unroll
+        for (int e = 0; e < W; ++e) s += (T)cv[e] * b[a][e];
+        acc[a] = s;
+      }
+      return;
+    }
+    const int32_t *__restrict__ ci = colidx + (int64_t)row * W;
     int32_t kc[W];
 #pragma unroll
     for (int e = 0; e < W; ++e) kc[e] = ci[e];
@@ -335,21 +381,79 @@ inline int64_t spop_tiles(const GemmArgs &g) {
   return ((threads + 255) / 256 + 7) / 8 * 8;
 }
 
+template <typename T, int EPI, int W, typename TB1, typename TB2, typename TC, int F>
+void spop_go(const GemmArgs &g, const SparseOp &sp, dim3 grid, int ngroups, hipStream_t s) {
+  // precomputed gathers where both panels have one element size (the
+  // epilogues without point data: store, add, -1/J, RK update)
+  constexpr bool off_ok = sizeof(TB1) == sizeof(TB2) && EPI != EPI_ADD;
+  if (off_ok && g.roff)
+    spop_kernel<T, EPI, W, TB1, TB2, TC, 0, F, off_ok><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
+  else
+    spop_kernel<T, EPI, W, TB1, TB2, TC, 0, F><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
+}
+
+// Multi-block launch (g.slots): the precomputed-gather kernel over g.nwg
+// workgroups, each block's operator and row groups taken from its slot.
+template <typename T, int EPI, int W, int F>
+void spop_multi_w(const GemmArgs &g, int batch, hipStream_t s) {
+  dim3 grid((unsigned)g.nwg, batch);
+  if constexpr (sizeof(T) == 8) {
+    spop_kernel<T, EPI, W, double, double, double, 0, F, true><<<grid, 256, 0, s>>>(g, nullptr, nullptr, 1, 1);
+  } else if constexpr (EPI == EPI_NEGDIV || EPI == EPI_RK) {
+    spop_kernel<T, EPI, W, float, float, double, 0, F, true><<<grid, 256, 0, s>>>(g, nullptr, nullptr, 1, 1);
+  } else {
+    if (!g.b1_f32)
+      spop_kernel<T, EPI, W, double, double, float, 0, F, true><<<grid, 256, 0, s>>>(g, nullptr, nullptr, 1, 1);
+    else
+      spop_kernel<T, EPI, W, float, float, float, 0, F, true><<<grid, 256, 0, s>>>(g, nullptr, nullptr, 1, 1);
+  }
+}
+
+template <int F>
+hipError_t launch_spop_multi_f(int prec, int epi, const GemmArgs &g, int width, int batch,
+                               hipStream_t s) {
+  if (!g.slots || g.nslots < 1 || g.nwg < 1) return hipErrorInvalidValue;
+  if (prec == PREC_F32 && epi == EPI_STORE && g.b1_f32 && !g.b2_f32 && g.B2)
+    return hipErrorInvalidValue;  // panels of two element sizes
+#define FR_W(W_)                                                                     \
+  case W_:                                                                           \
+    if (prec == PREC_F64) {                                                          \
+      if (epi == EPI_STORE) spop_multi_w<double, EPI_STORE, W_, F>(g, batch, s);     \
+      else if (epi == EPI_NEGDIV) spop_multi_w<double, EPI_NEGDIV, W_, F>(g, batch, s); \
+      else if (epi == EPI_RK) spop_multi_w<double, EPI_RK, W_, F>(g, batch, s);     \
+      else return hipErrorInvalidValue;                                              \
+    } else if (prec == PREC_F32) {                                                   \
+      if (epi == EPI_STORE) spop_multi_w<float, EPI_STORE, W_, F>(g, batch, s);      \
+      else if (epi == EPI_NEGDIV) spop_multi_w<float, EPI_NEGDIV, W_, F>(g, batch, s); \
+      else if (epi == EPI_RK) spop_multi_w<float, EPI_RK, W_, F>(g, batch, s);      \
+      else return hipErrorInvalidValue;                                              \
+    } else {                                                                         \
+      return hipErrorInvalidValue;                                                   \
+    }                                                                                \
+    break;
+  switch (width) {
+    FR_SPOP_WIDTHS(FR_W)
+    default: return hipErrorInvalidValue;
+  }
+#undef FR_W
+  return hipGetLastError();
+}
+
 template <typename T, int EPI, int W, int F>
 void spop_launch_w(const GemmArgs &g, const SparseOp &sp, int batch, hipStream_t s) {
   const int ngroups = (g.M + sp.rpg - 1) / sp.rpg;
   dim3 grid((unsigned)(spop_tiles<F>(g) * ngroups), batch);
   if constexpr (sizeof(T) == 8) {
-    spop_kernel<T, EPI, W, double, double, double, 0, F><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
+    spop_go<T, EPI, W, double, double, double, F>(g, sp, grid, ngroups, s);
   } else if constexpr (EPI == EPI_NEGDIV || EPI == EPI_RK) {
-    spop_kernel<T, EPI, W, float, float, double, 0, F><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
+    spop_go<T, EPI, W, float, float, double, F>(g, sp, grid, ngroups, s);
   } else {
     if (!g.b1_f32)
-      spop_kernel<T, EPI, W, double, double, float, 0, F><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
+      spop_go<T, EPI, W, double, double, float, F>(g, sp, grid, ngroups, s);
     else if (!g.b2_f32)
-      spop_kernel<T, EPI, W, float, double, float, 0, F><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
+      spop_go<T, EPI, W, float, double, float, F>(g, sp, grid, ngroups, s);
     else
-      spop_kernel<T, EPI, W, float, float, float, 0, F><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
+      spop_go<T, EPI, W, float, float, float, F>(g, sp, grid, ngroups, s);
   }
 }
 

@@ -20,6 +20,12 @@ hipError_t launch_spop(int prec, int epi, const GemmArgs &g, const SparseOp &sp,
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_spop_multi(int prec, int epi, const GemmArgs &g, int width, int fields,
+                             int batch, hipStream_t s) {
+  if (fields == 1) return launch_spop_multi_f<1>(prec, epi, g, width, batch, s);
+  return launch_spop_multi_fields(prec, epi, g, width, fields, batch, s);
+}
+
 hipError_t launch_spop_lds(int prec, int epi, const GemmArgs &g, const StagedOp &op, int batch,
                            hipStream_t s) {
   if (prec == PREC_F64) return launch_spop_lds_f64(epi, g, op, batch, s);

@@ -14,4 +14,11 @@ hipError_t launch_spop_fields5(int prec, int epi, const GemmArgs &g, const Spars
   return launch_spop_f<5>(prec, epi, g, sp, batch, s);
 }
 
+hipError_t launch_spop_multi_fields(int prec, int epi, const GemmArgs &g, int width, int fields,
+                                    int batch, hipStream_t s) {
+  if (fields == 4) return launch_spop_multi_f<4>(prec, epi, g, width, batch, s);
+  if (fields == 5) return launch_spop_multi_f<5>(prec, epi, g, width, batch, s);
+  return hipErrorInvalidValue;
+}
+
 }  // namespace fr

@@ -20,7 +20,9 @@ template <typename T, int EPI, int W, int MR, typename TB1, typename TB2, typena
 __global__ __launch_bounds__(256) void spop_lds_kernel(GemmArgs g,
                                                        const int32_t *__restrict__ colidx,
                                                        const double *__restrict__ vals, int kc,
-                                                       int nchunk) {
+                                                       int nchunk,
+                                                       const int32_t *__restrict__ cstart,
+                                                       const int32_t *__restrict__ cwidth) {
   extern __shared__ __align__(16) unsigned char spop_smem[];
   T *lds = reinterpret_cast<T *>(spop_smem);
   const int lane = threadIdx.x & 63;
@@ -41,8 +43,9 @@ __global__ __launch_bounds__(256) void spop_lds_kernel(GemmArgs g,
     for (int d = 0; d < RPS; ++d) acc[m][d] = 0;
 
   for (int c = 0; c < nchunk; ++c) {
-    const int k0 = c * kc;
-    const int kn = kc < K - k0 ? kc : K - k0;
+    const int k0 = cstart[c];
+    const int kn = cstart[c + 1] - k0;
+    const int wc = cwidth[c];
     for (int i = w; i < kn; i += 4) {
       const int k = k0 + i;
       T v = 0;
@@ -62,7 +65,8 @@ __global__ __launch_bounds__(256) void spop_lds_kernel(GemmArgs g,
           const double *__restrict__ cv = vals + ((int64_t)c * g.M + row) * W;
           T s = 0;
 #pragma unroll
-          for (int e = 0; e < W; ++e) s += (T)cv[e] * lds[ci[e] * 64 + lane];
+          for (int e = 0; e < W; ++e)
+            if (e < wc) s += (T)cv[e] * lds[ci[e] * 64 + lane];
           acc[m][d] += s;
         }
       }
@@ -126,8 +130,8 @@ template <typename T, int EPI, int W, int MR, typename TB1, typename TB2, typena
 void spop_lds_go(const GemmArgs &g, const StagedOp &op, int batch, hipStream_t s) {
   dim3 grid((unsigned)((g.N + 63) / 64), batch);
   const size_t shmem = (size_t)op.kc * 64 * sizeof(T);
-  spop_lds_kernel<T, EPI, W, MR, TB1, TB2, TC, DG><<<grid, 256, shmem, s>>>(g, op.colidx, op.vals,
-                                                                           op.kc, op.nchunk);
+  spop_lds_kernel<T, EPI, W, MR, TB1, TB2, TC, DG><<<grid, 256, shmem, s>>>(
+      g, op.colidx, op.vals, op.kc, op.nchunk, op.cstart, op.cwidth);
 }
 
 // Operand types by precision and epilogue (as for the other operator kernels).
@@ -178,7 +182,8 @@ hipError_t spop_lds_width_t(const GemmArgs &g, const StagedOp &op, int batch, hi
 template <typename T>
 hipError_t spop_lds_prec(int epi, const GemmArgs &g, const StagedOp &op, int batch, hipStream_t s) {
   if (g.N <= 0) return hipSuccess;
-  if (op.kc < 1 || op.nchunk < 1 || (int64_t)op.kc * 64 * sizeof(T) > 65536)
+  if (op.kc < 1 || op.nchunk < 1 || !op.cstart || !op.cwidth ||
+      (int64_t)op.kc * 64 * sizeof(T) > 65536)
     return hipErrorInvalidValue;
   switch (epi) {
     case EPI_STORE: return spop_lds_width_t<T, EPI_STORE, 0>(g, op, batch, s);

@@ -53,6 +53,23 @@ def check_fields(label, got, ref, tol):
     return err
 
 
+def state_bar(ref_u, u0, stated, du_bar):
+    """Per-field bar of u after RK4 steps: the stated bar, or -- for a field
+    whose change over the steps is comparable to its size, such as a
+    momentum component that starts at zero -- the du/dt bar of that field
+    applied to the change: u(k) - u(0) is a weighted sum of right-hand
+    sides, so its relative error is bounded by theirs.  du_bar: per-field
+    du/dt bars (array) or one bar for every field."""
+    nv = ref_u[0].shape[1]
+    inc = np.zeros(nv)
+    size = np.zeros(nv)
+    for r, u in zip(ref_u, u0):
+        inc += np.sum((r - u) ** 2, axis=(0, 2))
+        size += np.sum(r ** 2, axis=(0, 2))
+    ratio = np.sqrt(inc / size)
+    return np.maximum(stated, np.broadcast_to(du_bar, ratio.shape) * ratio)
+
+
 def floor_tolerance(d, u, stated, unit_ratio=1.0, factor=4.0):
     """Tolerance for du/dt of one case: the stated bar, or `factor` times
     the FP64 rounding floor of the oracle (its relative L2 distance from a

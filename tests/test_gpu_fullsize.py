@@ -92,14 +92,16 @@ def test_cfg3_curved48_p4():
 # the stated bar or 4 x the field's FP64 floor x the unit-roundoff ratio
 # (2^29 for FP32, 2^37 for BF16x3).  Conservation: the state, update and
 # integrals stay FP64, but the divergence product no longer telescopes
-# exactly; its rounding (unit u) reaches the integrals through 40 stage
-# increments of dt = 2e-4 times flux derivatives about 10^3 times the state,
-# so the drift stays below 40 x 2e-4 x 1e3 x u (1.3e-4 x 2^-24 x 2^12 ...):
-# the bars are 1e-6 (FP32) and 1e-4 (BF16x3).  A uniform stream: the
-# products of constant data round at u relative to the flux derivatives,
-# which are about 10^3 times du/dt of the perturbed stream: bars 2^12 u.
-_REDUCED = {"fp32": (1e-5, C.FP32_OVER_FP64, 1e-6, 2.0 ** -12),
-            "bf16x3": (1e-4, C.BF16X3_OVER_FP64, 1e-4, 2.0 ** -4)}
+# exactly.  Its rounding (unit u: 2^-24, about 2^-16 for BF16x3) reaches
+# the integrals through 40 stage increments of dt = 7.5e-5 times flux
+# derivatives some 10^3 times the state, at most 40 x 7.5e-5 x 10^3 x u =
+# 3 u: the bars are 1e-6 (FP32) and 1e-4 (BF16x3).  A uniform stream: the
+# products of constant data round at u relative to the flux-derivative
+# terms, which are some 10^4 times du/dt of the perturbed stream (the same
+# amplification the FP64 floor of this case shows, 1.4e-11 / 2^-53): bars
+# 2^15 u.
+_REDUCED = {"fp32": (1e-5, C.FP32_OVER_FP64, 1e-6, 2.0 ** -9),
+            "bf16x3": (1e-4, C.BF16X3_OVER_FP64, 1e-4, 2.0 ** -1)}
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
@@ -130,9 +132,10 @@ def test_cfg3_curved48_p4_reduced_precision(prec):
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_curved12_p4_u_after_10_steps(prec):
     """The curved family of the 48^3 workload on 12^3 Q2 hexes, p=4: u after
-    its 10 RK4 steps (dt 2e-4, captured step graph) against the oracle's,
-    per field, at the stated bars (1e-12 FP64, 1e-5 FP32 and BF16x3
-    operator paths)."""
+    its 10 RK4 steps (dt 3e-4, captured step graph) against the oracle's at
+    the stated bars (1e-12 FP64, 1e-5 FP32 and BF16x3 operator paths), over
+    the whole state and per field (each field's bar widened, where its
+    change over the steps is large, by that field's du/dt bar)."""
     w = configs.curved_freestream_hexes(12, 4)
     d = Discretisation(w)
     u = d.initial_state(w)
@@ -143,10 +146,13 @@ def test_curved12_p4_u_after_10_steps(prec):
     if ref is None:
         ref = _ORACLE_U10["curved12"] = d.rk4(u, w.dt, w.nsteps)
     bar = 1e-12 if prec == "fp64" else 1e-5
+    ratio = {"fp64": 1.0, "fp32": C.FP32_OVER_FP64, "bf16x3": C.BF16X3_OVER_FP64}[prec]
+    _tol, ext, _floor = C.floor_tolerance(d, u, bar, ratio)
     err = C.rel_l2(s.unpack(t), ref)
     print(f"curved12 p4 {prec}: u({w.nsteps}) rel L2 {err:.2e}")
     assert err < bar
-    C.check_fields(f"curved12 p4 {prec} u({w.nsteps})", s.unpack(t), ref, bar)
+    C.check_fields(f"curved12 p4 {prec} u({w.nsteps})", s.unpack(t), ref,
+                   C.state_bar(ref, u, bar, ext.field_tol))
 
 
 _ORACLE_U10 = {}
