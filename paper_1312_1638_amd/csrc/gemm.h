@@ -49,14 +49,18 @@ template <int MBW, int NC> struct Chunk {
   static constexpr int KC = L >= 12 ? 1 : (16 / L > 4 ? 4 : 16 / L);
 };
 
-template <typename T, int MBW, int NC, int EPI, typename TB1, typename TB2, typename TC>
+// MULTI: a multi-block launch that reads each workgroup's block from g.slots
+// (a separate instantiation: slot loads through a generic pointer count as
+// divergent and would spread to the single-block kernel's addressing).
+template <typename T, int MBW, int NC, int EPI, typename TB1, typename TB2, typename TC,
+          bool MULTI = false>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   typedef typename Mma<T>::acc_t acc_t;
   constexpr int KC = Chunk<MBW, NC>::KC;
   const int lane = threadIdx.x & 63;
   // multi-block launch: this workgroup's block and its index within it
   int64_t wg = blockIdx.x;
-  if (g.slots) wg = take_slot(g, wg, sizeof(TB1), sizeof(TB2), sizeof(TC));
+  if constexpr (MULTI) wg = take_slot(g, wg, sizeof(TB1), sizeof(TB2), sizeof(TC));
   const int64_t gw = wg * 4 + (threadIdx.x >> 6);
   const int rg = (int)(gw % g.WM);
   const int64_t n0 = (gw / g.WM) * (16 * NC);
@@ -160,22 +164,30 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   X(1, 1) X(1, 2) X(1, 4) X(2, 1) X(2, 2) X(2, 4) X(3, 1) X(3, 2) X(3, 4) X(4, 1)       \
   X(4, 2) X(4, 4) X(6, 1) X(6, 2) X(6, 4) X(8, 1) X(8, 2) X(12, 1) X(12, 2)
 
-template <typename T, int MBW, int NC, int EPI>
-hipError_t launch_gemm_shape(const GemmArgs &g, int batch, hipStream_t s) {
-  // multi-block launch: every slot's workgroups
-  const int64_t wgs = g.slots ? g.nwg : gemm_workgroups(g.N, NC, g.WM);
-  dim3 grid((unsigned)wgs, batch), block(256);
+template <typename T, int MBW, int NC, int EPI, bool MULTI>
+void launch_gemm_kind(const GemmArgs &g, dim3 grid, hipStream_t s) {
   if constexpr (sizeof(T) == 8) {
-    gemm_kernel<T, MBW, NC, EPI, double, double, double><<<grid, block, 0, s>>>(g);
+    gemm_kernel<T, MBW, NC, EPI, double, double, double, MULTI><<<grid, 256, 0, s>>>(g);
   } else if constexpr (EPI == EPI_NEGDIV || EPI == EPI_RK) {
-    gemm_kernel<T, MBW, NC, EPI, float, float, double><<<grid, block, 0, s>>>(g);
+    gemm_kernel<T, MBW, NC, EPI, float, float, double, MULTI><<<grid, 256, 0, s>>>(g);
   } else {
     if (!g.b1_f32)
-      gemm_kernel<T, MBW, NC, EPI, double, double, float><<<grid, block, 0, s>>>(g);
+      gemm_kernel<T, MBW, NC, EPI, double, double, float, MULTI><<<grid, 256, 0, s>>>(g);
     else if (!g.b2_f32)
-      gemm_kernel<T, MBW, NC, EPI, float, double, float><<<grid, block, 0, s>>>(g);
+      gemm_kernel<T, MBW, NC, EPI, float, double, float, MULTI><<<grid, 256, 0, s>>>(g);
     else
-      gemm_kernel<T, MBW, NC, EPI, float, float, float><<<grid, block, 0, s>>>(g);
+      gemm_kernel<T, MBW, NC, EPI, float, float, float, MULTI><<<grid, 256, 0, s>>>(g);
+  }
+}
+
+template <typename T, int MBW, int NC, int EPI>
+hipError_t launch_gemm_shape(const GemmArgs &g, int batch, hipStream_t s) {
+  if (g.slots) {
+    // multi-block launch: every slot's workgroups
+    launch_gemm_kind<T, MBW, NC, EPI, true>(g, dim3((unsigned)g.nwg, batch), s);
+  } else {
+    const int64_t wgs = gemm_workgroups(g.N, NC, g.WM);
+    launch_gemm_kind<T, MBW, NC, EPI, false>(g, dim3((unsigned)wgs, batch), s);
   }
   return hipGetLastError();
 }

@@ -57,11 +57,14 @@ __global__ __launch_bounds__(256) void gradcoru_kernel(PointArgs a) {
   }
 }
 
-template <int D, int NS, typename TQ>
+// MULTI: a multi-block launch (each workgroup's block from a.slots), a
+// separate instantiation so that the slot loads, which count as divergent,
+// stay out of the single-block kernel.
+template <int D, int NS, typename TQ, bool MULTI = false>
 __global__ __launch_bounds__(256) void tflux_kernel(PointArgs a) {
   constexpr int NV = D + 2;
   int64_t wg = blockIdx.x;
-  if (a.slots) {
+  if constexpr (MULTI) {
     // multi-block launch: this workgroup's block and its index within it
     int k = 0;
     while (k + 1 < a.nslots && wg >= a.slots[k + 1].wg_begin) ++k;
@@ -150,17 +153,21 @@ hipError_t launch_gradcoru(const PointArgs &a, hipStream_t s) {
   return a.q_f32 ? gradcoru_t<float>(a, s) : gradcoru_t<double>(a, s);
 }
 
-template <typename TQ>
-static hipError_t tflux_t(const PointArgs &a, int ns, hipStream_t s) {
-  unsigned nb = a.slots ? (unsigned)a.nwg : blocks_for((int64_t)a.nupts * a.ld);
+template <typename TQ, bool MULTI>
+static hipError_t tflux_m(const PointArgs &a, int ns, unsigned nb, hipStream_t s) {
   if (a.ndims == 2) {
-    if (ns) tflux_kernel<2, 1, TQ><<<nb, 256, 0, s>>>(a);
-    else tflux_kernel<2, 0, TQ><<<nb, 256, 0, s>>>(a);
+    if (ns) tflux_kernel<2, 1, TQ, MULTI><<<nb, 256, 0, s>>>(a);
+    else tflux_kernel<2, 0, TQ, MULTI><<<nb, 256, 0, s>>>(a);
   } else {
-    if (ns) tflux_kernel<3, 1, TQ><<<nb, 256, 0, s>>>(a);
-    else tflux_kernel<3, 0, TQ><<<nb, 256, 0, s>>>(a);
+    if (ns) tflux_kernel<3, 1, TQ, MULTI><<<nb, 256, 0, s>>>(a);
+    else tflux_kernel<3, 0, TQ, MULTI><<<nb, 256, 0, s>>>(a);
   }
   return hipGetLastError();
+}
+template <typename TQ>
+static hipError_t tflux_t(const PointArgs &a, int ns, hipStream_t s) {
+  if (a.slots) return tflux_m<TQ, true>(a, ns, (unsigned)a.nwg, s);
+  return tflux_m<TQ, false>(a, ns, blocks_for((int64_t)a.nupts * a.ld), s);
 }
 hipError_t launch_tflux(const PointArgs &a, int ns, hipStream_t s) {
   return a.q_f32 ? tflux_t<float>(a, ns, s) : tflux_t<double>(a, ns, s);

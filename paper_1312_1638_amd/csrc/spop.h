@@ -48,8 +48,13 @@ __device__ inline TB load_row(__amdgpu_buffer_rsrc_t rs, uint32_t off, uint32_t 
 // OFF: every entry's B row comes from the precomputed byte offsets g.roff
 // (one buffer resource over both panels, the row offset as the instruction's
 // scalar offset): no scalar address arithmetic per entry.
+// MULTI (with OFF): a multi-block launch that reads each workgroup's block
+// from g.slots.  A separate instantiation: the slot table is read through a
+// generic pointer, whose loads the compiler takes as divergent, and in a
+// shared kernel that would turn every gather of the single-block launch into
+// a waterfall loop over lanes.
 template <typename T, int EPI, int W, typename TB1, typename TB2, typename TC, int DG, int F,
-          bool OFF = false>
+          bool OFF = false, bool MULTI = false>
 __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
                                                    const int32_t *__restrict__ colidx,
                                                    const double *__restrict__ vals, int rpg,
@@ -57,17 +62,16 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
   static_assert(!OFF || (EPI != EPI_ADDT && EPI != EPI_TFVJP && EPI != EPI_GRADT &&
                          EPI != EPI_GRADTF),
                 "precomputed gathers and multi-block launches: store, add, -1/J, RK only");
+  static_assert(!MULTI || OFF, "multi-block launches use the precomputed gathers");
   // multi-block launch (precomputed-gather variant): this workgroup's
   // block, its operator and its index within the block
   int64_t L = blockIdx.x;
-  if constexpr (OFF) {
-    if (g.slots) {
-      const LaunchSlot *sl = nullptr;
-      L = take_slot(g, L, sizeof(TB1), sizeof(TB2), sizeof(TC), &sl);
-      vals = sl->vals;
-      rpg = sl->rpg;
-      ngroups = sl->ngroups;
-    }
+  if constexpr (MULTI) {
+    const LaunchSlot *sl = nullptr;
+    L = take_slot(g, L, sizeof(TB1), sizeof(TB2), sizeof(TC), &sl);
+    vals = sl->vals;
+    rpg = sl->rpg;
+    ngroups = sl->ngroups;
   }
   // linear id L -> XCD L % 8; the j-th workgroup of an XCD takes row group
   // j % ngroups of column tile 8 (j / ngroups) + L % 8 (tiles padded to a
@@ -398,14 +402,14 @@ template <typename T, int EPI, int W, int F>
 void spop_multi_w(const GemmArgs &g, int batch, hipStream_t s) {
   dim3 grid((unsigned)g.nwg, batch);
   if constexpr (sizeof(T) == 8) {
-    spop_kernel<T, EPI, W, double, double, double, 0, F, true><<<grid, 256, 0, s>>>(g, nullptr, nullptr, 1, 1);
+    spop_kernel<T, EPI, W, double, double, double, 0, F, true, true><<<grid, 256, 0, s>>>(g, nullptr, nullptr, 1, 1);
   } else if constexpr (EPI == EPI_NEGDIV || EPI == EPI_RK) {
-    spop_kernel<T, EPI, W, float, float, double, 0, F, true><<<grid, 256, 0, s>>>(g, nullptr, nullptr, 1, 1);
+    spop_kernel<T, EPI, W, float, float, double, 0, F, true, true><<<grid, 256, 0, s>>>(g, nullptr, nullptr, 1, 1);
   } else {
     if (!g.b1_f32)
-      spop_kernel<T, EPI, W, double, double, float, 0, F, true><<<grid, 256, 0, s>>>(g, nullptr, nullptr, 1, 1);
+      spop_kernel<T, EPI, W, double, double, float, 0, F, true, true><<<grid, 256, 0, s>>>(g, nullptr, nullptr, 1, 1);
     else
-      spop_kernel<T, EPI, W, float, float, float, 0, F, true><<<grid, 256, 0, s>>>(g, nullptr, nullptr, 1, 1);
+      spop_kernel<T, EPI, W, float, float, float, 0, F, true, true><<<grid, 256, 0, s>>>(g, nullptr, nullptr, 1, 1);
   }
 }
 
