@@ -240,6 +240,25 @@ fr_status fr_rk_step_stash(fr_ctx *ctx, double *u, const double *dt_dev, double 
 fr_status fr_rk_step_adjoint_stash(fr_ctx *ctx, double *stash, const double *dt_dev,
                                    const double *lam_np1, double *lam_n, void *hip_stream);
 
+/* Adjoint of one checkpoint segment of RK4 steps (the checkpointed
+ * gradient of the time-stepping scheme of section 2 with the classical RK4
+ * scheme of Table 1): replays nsteps steps forward from u_seg0 (DEVICE,
+ * read only) while stashing every step into `stash` (DEVICE, caller-owned
+ * workspace of nsteps * fr_stash_len float64), then applies the step
+ * adjoints from the last step to the first:
+ *   lam_seg0 = (d u_{n0+nsteps} / d u_{n0})^T lam_end.
+ * lam_seg0 may alias lam_end; stash must overlap neither, nor u_seg0.  The
+ * whole segment runs as one HIP graph, captured on the first call with a
+ * given (u_seg0, dt_dev, nsteps, lam_end, lam_seg0, stash) and replayed on
+ * later calls with the same arguments (the context keeps the last four);
+ * callers that keep those buffers at fixed addresses pay the capture once.
+ * The stash contents are overwritten.  nsteps = 0 copies lam_end to
+ * lam_seg0.  FP64 contexts without boundary conditions
+ * (FR_EUNSUPPORTED otherwise); FR_EINVAL for null pointers or nsteps < 0. */
+fr_status fr_rk_segment_adjoint(fr_ctx *ctx, const double *u_seg0, const double *dt_dev,
+                                int32_t nsteps, const double *lam_end, double *lam_seg0,
+                                double *stash, void *hip_stream);
+
 /* Integrals of the state by quadrature at the solution points (paper's
  * validation section: sums of W J times the integrand).  kind must be 0:
  * out (DEVICE float64) [nproblems][nvars + 1] receives, per problem, the

@@ -6,12 +6,14 @@ the library's stashing step, which leaves every step's stage states and
 primal intermediates in device memory (~40 states per step for
 Navier-Stokes); the earlier segments run the captured step graph and keep
 only their starting state (a checkpoint every `ckpt` steps).  Backward:
-segments from last to first; a segment without a stash is first replayed
-from its checkpoint with the stashing step (into a reused buffer), then the
-hand-written RK4 step adjoint consumes the stash step by step in reverse with
-no recomputation.  The budget defaults to the free device memory less a
-reserve, so on a 288 GB device most segments are never replayed; budget 0
-replays every segment but the last.  Torch holds the tensors; all arithmetic
+segments from last to first; a segment without a stash is replayed from its
+checkpoint with the stashing step (into a reused buffer) and its adjoint run
+at once, both as one captured graph in the library (fr_rk_segment_adjoint);
+a resident stash is consumed by the hand-written RK4 step adjoint step by
+step in reverse.  Neither recomputes anything inside a step.  The budget
+defaults to the free device memory less a reserve, so on a 288 GB device
+most segments are never replayed; budget 0 replays every segment but the
+last.  Torch holds the tensors; all arithmetic
 runs in the HIP library.
 """
 from __future__ import annotations
@@ -22,35 +24,40 @@ import torch
 class FRSteps(torch.autograd.Function):
     @staticmethod
     def forward(ctx, u0, solver, dt, nsteps, ckpt, budget):
-        work = u0.detach().clone()
+        # the solver's own state buffer: the step graph captured for it on
+        # an earlier call is reused (a new address would be captured again)
+        work = solver.graph_state()
+        work.copy_(u0.detach())
         L = solver.stash_len()
         nseg = -(-nsteps // ckpt) if nsteps > 0 else 0
         resident = min(nseg, max(1, int(stash_segments(L, ckpt, budget, work.device))))
         first = nseg - resident            # segments first.. keep their stash
         ckpts, stashes = {}, {}
-        for n in range(nsteps):
-            seg, i = divmod(n, ckpt)
-            if i == 0:
-                if seg < first:
-                    ckpts[seg] = work.clone()
-                else:
-                    # a stash of stage states and primal intermediates per step,
-                    # written here and read by the step adjoints
-                    steps = min(ckpt, nsteps - n)
-                    stashes[seg] = torch.empty(steps * L, dtype=torch.float64, device=work.device)
-            if seg >= first:
+        for seg in range(nseg):
+            steps = min(ckpt, nsteps - seg * ckpt)
+            if seg < first:
+                # checkpoint, then the whole segment through the step graph
+                ckpts[seg] = work.clone()
+                solver.step(work, dt, steps)
+                continue
+            # a stash of stage states and primal intermediates per step,
+            # written here and read by the step adjoints
+            stashes[seg] = torch.empty(steps * L, dtype=torch.float64, device=work.device)
+            for i in range(steps):
                 solver.step_stash(work, dt, stashes[seg][i * L:(i + 1) * L])
-            else:
-                solver.step(work, dt, 1)
         ctx.solver, ctx.dt, ctx.nsteps, ctx.ckpt = solver, dt, nsteps, ckpt
         ctx.ckpts, ctx.stashes, ctx.nseg = ckpts, stashes, nseg
-        return work
+        return work.clone()
 
     @staticmethod
     def backward(ctx, lam_out):
         s, dt, ckpt = ctx.solver, ctx.dt, ctx.ckpt
-        lam = lam_out.detach().contiguous().clone()
-        work = torch.empty_like(lam)
+        # the cotangent and the replay start live in solver-owned buffers, so
+        # that the library's captured segment graphs see the same addresses
+        # on every segment and every call
+        lam = s.adjoint_state()
+        lam.copy_(lam_out.detach())
+        start = s.graph_state()
         L = s.stash_len()
         spare = None                         # replay buffer: a consumed full-length stash
         for seg in reversed(range(ctx.nseg)):
@@ -58,19 +65,20 @@ class FRSteps(torch.autograd.Function):
             n1 = min(ctx.nsteps, n0 + ckpt)
             if seg in ctx.stashes:
                 stash = ctx.stashes.pop(seg)
+                for i in reversed(range(n1 - n0)):
+                    s.rk_step_adjoint_stash(stash[i * L:(i + 1) * L], dt, lam, out=lam)
             else:
+                # replay from the checkpoint and run the segment's adjoint,
+                # one graph in the library
                 if spare is None:
                     spare = torch.empty(ckpt * L, dtype=torch.float64, device=lam.device)
                 stash = spare
-                work.copy_(ctx.ckpts.pop(seg))
-                for i in range(n1 - n0):
-                    s.step_stash(work, dt, stash[i * L:(i + 1) * L])
-            for i in reversed(range(n1 - n0)):
-                s.rk_step_adjoint_stash(stash[i * L:(i + 1) * L], dt, lam, out=lam)
+                start.copy_(ctx.ckpts.pop(seg))
+                s.segment_adjoint(start, dt, n1 - n0, lam, stash, out=lam)
             if spare is None and stash.numel() == ckpt * L:
                 spare = stash
         ctx.stashes, ctx.ckpts = None, None
-        return lam, None, None, None, None, None
+        return lam.clone(), None, None, None, None, None
 
 
 # Device memory left free when the stash budget is taken from what is free.

@@ -25,7 +25,7 @@ EXPORTS = ("fr_setup_mesh", "fr_setup_mesh_bc", "fr_get_layout", "fr_get_solutio
            "fr_rhs", "fr_rk_step", "fr_euler_step", "fr_dopri5_step", "fr_rhs_adjoint", "fr_rk_step_adjoint", "fr_integrate", "fr_integrate_noalloc",
            "fr_reference_operator", "fr_check_mesh", "fr_debug_stage", "fr_debug_scratch_len", "fr_bench_step",
            "fr_debug_gemm", "fr_measure_ceiling", "fr_bench_gemm", "fr_get_gemm_plan", "fr_integrate_grad", "fr_stash_len", "fr_rk_step_stash",
-           "fr_rk_step_adjoint_stash", "fr_debug_set_plan", "fr_debug_multi",
+           "fr_rk_step_adjoint_stash", "fr_rk_segment_adjoint", "fr_debug_set_plan", "fr_debug_multi",
            "fr_last_error", "fr_destroy")
 
 
@@ -96,6 +96,7 @@ def load_library(path: str = LIB_PATH):
         "fr_stash_len": [vp, ctypes.POINTER(i64)],
         "fr_rk_step_stash": [vp, dp, dp, dp, vp],
         "fr_rk_step_adjoint_stash": [vp, dp, dp, dp, dp, vp],
+        "fr_rk_segment_adjoint": [vp, dp, dp, i32, dp, dp, dp, vp],
         "fr_reference_operator": [i32, i32, i32, i32, dp, i64, ctypes.POINTER(i32),
                                   ctypes.POINTER(i32)],
         "fr_check_mesh": [ctypes.POINTER(FrConfig), i32, ctypes.POINTER(FrBlock), i64, vp,
@@ -301,6 +302,21 @@ class Solver:
     def empty(self):
         return self.torch.zeros(self.total_len, dtype=self.torch.float64, device="cuda")
 
+    def adjoint_state(self):
+        """A second solver-owned state buffer at a fixed address (the
+        cotangent of the checkpointed adjoint), like graph_state."""
+        if getattr(self, "_adjoint_state", None) is None:
+            self._adjoint_state = self.empty()
+        return self._adjoint_state
+
+    def graph_state(self):
+        """A state buffer owned by the solver, at one address for its life: the
+        library keeps the step graph captured for the state it last stepped,
+        so stepping this buffer again reuses the graph."""
+        if getattr(self, "_graph_state", None) is None:
+            self._graph_state = self.empty()
+        return self._graph_state
+
     def pack(self, arrays):
         """Per-block arrays [rho, alpha, n] -> device state tensor."""
         host = np.zeros(self.total_len)
@@ -426,6 +442,18 @@ class Solver:
         _check(self.L.fr_rk_step_adjoint_stash(self.ctx, stash.data_ptr(), d.data_ptr(),
                                                self._ptr(lam), self._ptr(out), self._stream()),
                self.ctx)
+        return out
+
+    def segment_adjoint(self, u0, dt, nsteps, lam, stash, out=None):
+        """(d u_{nsteps} / d u0)^T lam through a replay of nsteps steps from
+        u0 stashed into `stash` (nsteps * stash_len float64), as one graph."""
+        if out is None:
+            out = self.empty()
+        d = self.dt_tensor(dt)
+        assert stash.dtype == self.torch.float64 and stash.numel() >= nsteps * self.stash_len()
+        _check(self.L.fr_rk_segment_adjoint(self.ctx, self._ptr(u0), d.data_ptr(), nsteps,
+                                            self._ptr(lam), self._ptr(out), stash.data_ptr(),
+                                            self._stream()), self.ctx)
         return out
 
     def kinetic_energy_grad(self, u, out=None):

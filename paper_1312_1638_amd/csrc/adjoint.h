@@ -40,9 +40,15 @@ hipError_t launch_con_u_vjp(const AdjPairArgs &a, hipStream_t s);
 hipError_t launch_axpy_dt(int64_t len, int64_t ld, int64_t nelem, const int32_t *prob,
                           const double *dt, double c, const double *x, const double *y,
                           double *out, hipStream_t s);
+// RK4 step adjoint bookkeeping: acc = (first ? lam : acc) + w and
+// kb = ca dt lam + cb dt w.  With rcpdjac (the state's nvars fields per
+// point), kb is written already scaled for the right-hand side's adjoint:
+// -J^-1 kb (0 in padding), what the negscale kernel would make of it.  With
+// lcopy, lam is also copied there (lam and acc may then be one array).
 hipError_t launch_rk_adj(int64_t len, int64_t ld, int64_t nelem, const int32_t *prob,
                          const double *dt, double ca, double cb, const double *lam,
-                         const double *w, double *acc, double *kb, int first, hipStream_t s);
+                         const double *w, double *acc, double *kb, int first, int nvars,
+                         const double *rcpdjac, double *lcopy, hipStream_t s);
 
 hipError_t launch_ke_grad(int nvars, int ndims, int nupts, int64_t ld, int64_t nelem,
                           const double *wdjac, const double *u, double *g, hipStream_t s);

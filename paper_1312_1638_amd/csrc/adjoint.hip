@@ -285,27 +285,38 @@ hipError_t launch_axpy_dt(int64_t len, int64_t ld, int64_t nelem, const int32_t 
   return hipGetLastError();
 }
 
-// acc += w; kb = a dt lam + b dt w (RK4 step adjoint bookkeeping)
+// acc += w; kb = a dt lam + b dt w (RK4 step adjoint bookkeeping), kb
+// optionally scaled by -1/J for the next right-hand-side adjoint, lam
+// optionally copied (the step's first call, lam_{n+1} kept for later stages)
 __global__ __launch_bounds__(256) void rk_adj_kernel(int64_t len, int64_t ld, int64_t nelem,
                                                      const int32_t *prob, const double *dt,
                                                      double ca, double cb, const double *lam,
                                                      const double *w, double *acc, double *kb,
-                                                     int first) {
+                                                     int first, int nvars,
+                                                     const double *rcpdjac, double *lcopy) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= len) return;
-  const int64_t n = i % ld;
-  const double d = n < nelem ? dt[prob ? prob[n] : 0] : 0.0;
+  const int64_t row = i / ld, n = i - row * ld;
+  const bool live = n < nelem;
+  const double d = live ? dt[prob ? prob[n] : 0] : 0.0;
   const double wi = first ? 0.0 : w[i];
   const double l = lam[i];
+  if (lcopy) lcopy[i] = l;
   acc[i] = (first ? l : acc[i]) + wi;
-  if (kb) kb[i] = ca * d * l + cb * d * wi;
+  if (kb) {
+    const double kv = ca * d * l + cb * d * wi;
+    // row = point r times nvars plus the field
+    kb[i] = !rcpdjac ? kv : live ? -rcpdjac[(row / nvars) * ld + n] * kv : 0.0;
+  }
 }
 
 hipError_t launch_rk_adj(int64_t len, int64_t ld, int64_t nelem, const int32_t *prob,
                          const double *dt, double ca, double cb, const double *lam,
-                         const double *w, double *acc, double *kb, int first, hipStream_t s) {
+                         const double *w, double *acc, double *kb, int first, int nvars,
+                         const double *rcpdjac, double *lcopy, hipStream_t s) {
+  if (rcpdjac && nvars < 1) return hipErrorInvalidValue;
   rk_adj_kernel<<<nblk(len), 256, 0, s>>>(len, ld, nelem, prob, dt, ca, cb, lam, w, acc, kb,
-                                          first);
+                                          first, nvars, rcpdjac, lcopy);
   return hipGetLastError();
 }
 

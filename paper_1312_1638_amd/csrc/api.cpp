@@ -172,7 +172,7 @@ struct fr_ctx {
   } cur{};
   bool adj_ready = false, adj_tuned = false;
   double *d_ufb = nullptr, *d_ftb = nullptr, *d_qfb = nullptr, *d_lt = nullptr;
-  double *d_lc = nullptr, *d_kb = nullptr, *d_w = nullptr, *d_k = nullptr;
+  double *d_lc = nullptr, *d_w = nullptr, *d_k = nullptr;
   double *d_st[3] = {nullptr, nullptr, nullptr};
   // other steppers: forward Euler (one graph per step), DOPRI5 (slopes
   // k1..k7, the stage/new state y, per-problem error sums, DOF counts,
@@ -196,6 +196,19 @@ struct fr_ctx {
              atol == o.atol && rtol == o.rtol;
     }
   } dp_key{};
+  // checkpoint segments of the adjoint (fr_rk_segment_adjoint): the replay
+  // state and a few captured segment graphs, each keyed by its arguments
+  double *d_seg_u = nullptr;
+  struct SegGraph {
+    const double *u0, *dt, *lam_end;
+    double *lam0, *stash;
+    int nsteps;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    uint64_t used;
+  };
+  std::vector<SegGraph> seg_graphs;
+  uint64_t seg_clock = 0;
   std::vector<void *> allocs;
   // Euler in reduced precision: the deviation form (each element's state
   // less its reference, the state at its first solution point, before any
@@ -1071,8 +1084,7 @@ void ensure_adjoint(fr_ctx *c, hipStream_t s) {
   c->d_ufb = dev_alloc<double>(c, c->uf_len);
   c->d_ftb = dev_alloc<double>(c, c->ft_len);
   if (c->ns) c->d_qfb = dev_alloc<double>(c, c->qf_len);
-  for (double **p : {&c->d_lt, &c->d_lc, &c->d_kb, &c->d_w, &c->d_k, &c->d_st[0], &c->d_st[1],
-                     &c->d_st[2]})
+  for (double **p : {&c->d_lt, &c->d_lc, &c->d_w, &c->d_k, &c->d_st[0], &c->d_st[1], &c->d_st[2]})
     *p = dev_alloc<double>(c, c->total_len);
   for (auto &b : c->blocks) {
     const fr::RefOps &R = c->refs[b.ref];
@@ -1346,8 +1358,11 @@ void tune_adjoint_ops(fr_ctx *c, hipStream_t s) {
   hip_check(hipStreamSynchronize(s), "tune sync");
 }
 
+// lam_scaled: lam is c->d_lt already holding -J^-1 lam (written so by the
+// RK adjoint bookkeeping kernel), and the scaling kernel is skipped.
 void rhs_adjoint_chain(fr_ctx *c, const double *u, const double *lam, double *ulam,
-                       hipStream_t s, Primal pr = Primal{nullptr, nullptr, nullptr}) {
+                       hipStream_t s, Primal pr = Primal{nullptr, nullptr, nullptr},
+                       bool lam_scaled = false) {
   const int D = c->D, NV = c->NV;
   if (!c->adj_tuned) {
     c->adj_tuned = true;
@@ -1361,8 +1376,9 @@ void rhs_adjoint_chain(fr_ctx *c, const double *u, const double *lam, double *ul
   const double *ft = pr.q;
   for (auto &b : c->blocks) {
     const int64_t N = (int64_t)NV * b.ld;
-    hip_check(fr::launch_negscale(NV, b.Nu, b.ld, b.nelem, b.d_rcpdjac, lam + b.uoff,
-                                  c->d_lt + b.uoff, s), "negscale");
+    if (!lam_scaled)
+      hip_check(fr::launch_negscale(NV, b.Nu, b.ld, b.nelem, b.d_rcpdjac, lam + b.uoff,
+                                    c->d_lt + b.uoff, s), "negscale");
     // D~b = M3^T lt ; F~b = (M1 - M3 M2)^T lt (or, fused, the flux VJP of F~b)
     adj_gemm(c, b.t_m3, c->d_lt + b.uoff, nullptr, c->d_ufb + b.ufoff, N, fr::EPI_STORE, 1, 0, 0, s);
     if (tfvjp_fused(b))
@@ -1410,12 +1426,16 @@ void axpy_blocks(fr_ctx *c, const double *dt, double coef, const double *x, cons
               "axpy");
 }
 
+// The step adjoint's bookkeeping over every block: lam from c->d_lc, or on
+// the first call from lam_np1 (copied into c->d_lc on the way); kb goes
+// to c->d_lt scaled by -1/J, ready for the next right-hand-side adjoint.
 void rk_adj_blocks(fr_ctx *c, const double *dt, double ca, double cb, double *acc, int first,
-                   bool last, hipStream_t s) {
+                   bool last, hipStream_t s, const double *lam_np1 = nullptr) {
   for (auto &b : c->blocks)
     hip_check(fr::launch_rk_adj((int64_t)b.Nu * c->NV * b.ld, b.ld, b.nelem, b.d_prob, dt, ca, cb,
-                                c->d_lc + b.uoff, c->d_w + b.uoff, acc + b.uoff,
-                                last ? nullptr : c->d_kb + b.uoff, first, s),
+                                (lam_np1 ? lam_np1 : c->d_lc) + b.uoff, c->d_w + b.uoff,
+                                acc + b.uoff, last ? nullptr : c->d_lt + b.uoff, first, c->NV,
+                                b.d_rcpdjac, lam_np1 ? c->d_lc + b.uoff : nullptr, s),
               "rk adjoint update");
 }
 
@@ -1431,16 +1451,14 @@ void rk4_step_adjoint(fr_ctx *c, const double *u, const double *dt, const double
     axpy_blocks(c, dt, a[i], u, c->d_k, c->d_st[i], s);
     prev = c->d_st[i];
   }
-  hip_check(hipMemcpyAsync(c->d_lc, lam_np1, c->total_len * sizeof(double),
-                           hipMemcpyDeviceToDevice, s), "copy");
   // acc = lam; kb = dt/6 lam ; then per stage (from the last): w = J(u_s)^T kb,
   // acc += w, kb = b_{s-1} dt lam + a_s dt w
-  rk_adj_blocks(c, dt, 1.0 / 6, 0.0, lam_n, 1, false, s);
+  rk_adj_blocks(c, dt, 1.0 / 6, 0.0, lam_n, 1, false, s, lam_np1);
   const double *stages[4] = {c->d_st[2], c->d_st[1], c->d_st[0], u};
   static const double ca[3] = {1.0 / 3, 1.0 / 3, 1.0 / 6};
   static const double cb[3] = {1.0, 0.5, 0.5};
   for (int i = 0; i < 4; ++i) {
-    rhs_adjoint_chain(c, stages[i], c->d_kb, c->d_w, s);
+    rhs_adjoint_chain(c, stages[i], c->d_lt, c->d_w, s, Primal{nullptr, nullptr, nullptr}, true);
     if (i < 3) rk_adj_blocks(c, dt, ca[i], cb[i], lam_n, 0, false, s);
     else rk_adj_blocks(c, dt, 0.0, 0.0, lam_n, 0, true, s);
   }
@@ -1493,17 +1511,33 @@ void rk4_step_stash(fr_ctx *c, double *u, const double *dt, double *stash, hipSt
 void rk4_step_adjoint_stash(fr_ctx *c, double *stash, const double *dt, const double *lam_np1,
                             double *lam_n, hipStream_t s) {
   ensure_adjoint(c, s);
-  hip_check(hipMemcpyAsync(c->d_lc, lam_np1, c->total_len * sizeof(double),
-                           hipMemcpyDeviceToDevice, s), "copy");
-  rk_adj_blocks(c, dt, 1.0 / 6, 0.0, lam_n, 1, false, s);
+  rk_adj_blocks(c, dt, 1.0 / 6, 0.0, lam_n, 1, false, s, lam_np1);
   static const double ca[3] = {1.0 / 3, 1.0 / 3, 1.0 / 6};
   static const double cb[3] = {1.0, 0.5, 0.5};
   for (int i = 0; i < 4; ++i) {
     StashStage S = stash_stage(c, stash, 3 - i);
-    rhs_adjoint_chain(c, S.state, c->d_kb, c->d_w, s, Primal{S.uf, S.qf, S.q});
+    rhs_adjoint_chain(c, S.state, c->d_lt, c->d_w, s, Primal{S.uf, S.qf, S.q}, true);
     if (i < 3) rk_adj_blocks(c, dt, ca[i], cb[i], lam_n, 0, false, s);
     else rk_adj_blocks(c, dt, 0.0, 0.0, lam_n, 0, true, s);
   }
+}
+
+// Adjoint of a checkpoint segment: replay nsteps RK4 steps from u0 (into
+// the context's replay state) stashing every step, then the step adjoints
+// from the last step to the first: lam0 = (d u_{n0+nsteps} / d u_{n0})^T lam_end.
+void rk4_segment_adjoint(fr_ctx *c, const double *u0, const double *dt, int nsteps,
+                         const double *lam_end, double *lam0, double *stash, hipStream_t s) {
+  const int64_t L = 4 * stash_stage_len(c);
+  const size_t bytes = c->total_len * sizeof(double);
+  if (nsteps == 0) {
+    if (lam0 != lam_end)
+      hip_check(hipMemcpyAsync(lam0, lam_end, bytes, hipMemcpyDeviceToDevice, s), "copy");
+    return;
+  }
+  hip_check(hipMemcpyAsync(c->d_seg_u, u0, bytes, hipMemcpyDeviceToDevice, s), "copy");
+  for (int i = 0; i < nsteps; ++i) rk4_step_stash(c, c->d_seg_u, dt, stash + i * L, s);
+  for (int i = nsteps - 1; i >= 0; --i)
+    rk4_step_adjoint_stash(c, stash + i * L, dt, i == nsteps - 1 ? lam_end : lam0, lam0, s);
 }
 
 // One classical RK4 step of u in place: k_s = R(stage_s), with
@@ -1541,6 +1575,8 @@ void release_stepper_graphs(fr_ctx *c) {
   if (c->dp_exec) hipGraphExecDestroy(c->dp_exec);
   if (c->dp_graph) hipGraphDestroy(c->dp_graph);
   c->dp_exec = nullptr; c->dp_graph = nullptr; c->dp_key = fr_ctx::DpKey{};
+  for (auto &g : c->seg_graphs) release_graph_pair(g.graph, g.exec);
+  c->seg_graphs.clear();
 }
 
 // Steps captured into one graph when a call asks for that many or more.
@@ -2108,6 +2144,60 @@ fr_status fr_rk_step_adjoint_stash(fr_ctx *c, double *stash, const double *dt_de
   if (!stash || !dt_dev || !lam_np1 || !lam_n) return fail(c, FR_EINVAL, "bad stash adjoint arguments");
   try {
     rk4_step_adjoint_stash(c, stash, dt_dev, lam_np1, lam_n, (hipStream_t)hip_stream);
+  } catch (const Fail &f) {
+    return fail(c, f.st, f.msg);
+  }
+  return FR_OK;
+}
+
+// Captured segment graphs kept per context; the least recently used one
+// makes room for a new argument set.
+constexpr size_t kSegGraphs = 4;
+
+fr_status fr_rk_segment_adjoint(fr_ctx *c, const double *u_seg0, const double *dt_dev,
+                                int32_t nsteps, const double *lam_end, double *lam_seg0,
+                                double *stash, void *hip_stream) {
+  if (!c) return FR_EINVAL;
+  if (!u_seg0 || !dt_dev || !lam_end || !lam_seg0 || (nsteps > 0 && !stash) || nsteps < 0)
+    return fail(c, FR_EINVAL, "bad segment adjoint arguments");
+  if (c->prec != FR_FP64) return fail(c, FR_EUNSUPPORTED, "the adjoint is available for FP64 contexts");
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    if (nsteps == 0) {
+      rk4_segment_adjoint(c, u_seg0, dt_dev, 0, lam_end, lam_seg0, stash, s);
+      return FR_OK;
+    }
+    // everything that allocates, uploads or synchronises happens before
+    // the capture: adjoint operators, their tuning, the replay state
+    ensure_adjoint(c, s);
+    if (!c->adj_tuned) {
+      c->adj_tuned = true;
+      tune_adjoint_ops(c, s);
+    }
+    if (!c->d_seg_u) c->d_seg_u = dev_alloc<double>(c, c->total_len);
+    fr_ctx::SegGraph *hit = nullptr;
+    for (auto &g : c->seg_graphs)
+      if (g.u0 == u_seg0 && g.dt == dt_dev && g.lam_end == lam_end && g.lam0 == lam_seg0 &&
+          g.stash == stash && g.nsteps == nsteps)
+        hit = &g;
+    if (!hit) {
+      if (c->seg_graphs.size() >= kSegGraphs) {
+        auto old = std::min_element(c->seg_graphs.begin(), c->seg_graphs.end(),
+                                    [](const fr_ctx::SegGraph &a, const fr_ctx::SegGraph &b) {
+                                      return a.used < b.used;
+                                    });
+        release_graph_pair(old->graph, old->exec);
+        c->seg_graphs.erase(old);
+      }
+      fr_ctx::SegGraph g{u_seg0, dt_dev, lam_end, lam_seg0, stash, nsteps, nullptr, nullptr, 0};
+      capture(c, g.graph, g.exec, [&](hipStream_t cs) {
+        rk4_segment_adjoint(c, u_seg0, dt_dev, nsteps, lam_end, lam_seg0, stash, cs);
+      });
+      c->seg_graphs.push_back(g);
+      hit = &c->seg_graphs.back();
+    }
+    hit->used = ++c->seg_clock;
+    hip_check(hipGraphLaunch(hit->exec, s), "graph launch");
   } catch (const Fail &f) {
     return fail(c, f.st, f.msg);
   }
