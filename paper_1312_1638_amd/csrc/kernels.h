@@ -171,7 +171,7 @@ struct StagedOp {
   const int32_t *cstart = nullptr;
   const int32_t *cwidth = nullptr;
 };
-#define FR_LDS_WIDTHS(X) X(4) X(8) X(12)
+#define FR_LDS_WIDTHS(X) X(4) X(5) X(6) X(8) X(12)
 // output rows per wavefront (4 wavefronts split the M rows of a tile)
 #define FR_LDS_ROWS(X) X(4) X(8) X(16) X(24) X(32) X(40)
 #define FR_LDS_ROWS_MAX 40

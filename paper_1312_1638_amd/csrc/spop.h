@@ -23,27 +23,11 @@
 // tile's B rows then hit the XCD's L2 while they are still there.
 #pragma once
 
+#include "buffer.h"
 #include "kernels.h"
 #include "physics.h"
 
 namespace fr {
-
-// Word 3 of a buffer resource for untyped (raw) loads on CDNA: only a
-// non-zero data format (32-bit) is required; no swizzle, no stride.
-constexpr int kRawBufferWord3 = 0x00020000;
-
-// One value at byte offset `off` of the row whose address the resource `rs`
-// holds.  The row address is wave-uniform (scalar registers) and the offset
-// is the lane's, so a gather costs one instruction and no vector address
-// arithmetic.
-template <typename TB>
-__device__ inline TB load_row(__amdgpu_buffer_rsrc_t rs, uint32_t off, uint32_t soff = 0) {
-  if constexpr (sizeof(TB) == 8) {
-    return __builtin_bit_cast(TB, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, (int)soff, 0));
-  } else {
-    return __builtin_bit_cast(TB, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, (int)soff, 0));
-  }
-}
 
 // OFF: every entry's B row comes from the precomputed byte offsets g.roff
 // (one buffer resource over both panels, the row offset as the instruction's
@@ -344,8 +328,32 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
     }
     return;
   }
-#pragma unroll 2
-  for (int row = r0; row < r1; ++row) {
+  auto row_step = [&](int row) {
+    // RK4 update: the state and register values of this row are loaded
+    // before the gathers, so that their latency overlaps the product's
+    // instead of following it (the state is read unless this is the last
+    // stage, the register unless this is a first stage that is not also the
+    // last one, as in forward Euler; buffer loads from this row of each
+    // array, with an empty range where the stage does not read it: 0 comes back
+    // with no memory access and no branch, so nothing waits before the
+    // gathers are issued; readfirstlane keeps the uniform ranges in scalar
+    // registers, which a buffer resource must be in)
+    double u0v[F], accv[F];
+    if constexpr (EPI == EPI_RK) {
+      const __amdgpu_buffer_rsrc_t rso = __builtin_amdgcn_make_buffer_rsrc(
+          (void *)(g.out + (int64_t)row * g.ldc), 0,
+          __builtin_amdgcn_readfirstlane(g.rk.last ? 0 : -1), kRawBufferWord3);
+      const __amdgpu_buffer_rsrc_t rsa = __builtin_amdgcn_make_buffer_rsrc(
+          (void *)(g.acc + (int64_t)row * g.ldc), 0,
+          __builtin_amdgcn_readfirstlane(g.rk.first && !g.rk.last ? 0 : -1), kRawBufferWord3);
+#pragma unroll
+      for (int a = 0; a < F; ++a) {
+        // within one row of N < 2^29 columns: the byte offset fits 32 bits
+        const uint32_t off = (uint32_t)((t + a * fs) * (int64_t)sizeof(double));
+        u0v[a] = load_row<double>(rso, off);
+        accv[a] = load_row<double>(rsa, off);
+      }
+    }
     T acc[F];
     row_product(row, acc);
     double rj = 0;
@@ -366,15 +374,23 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
         } else {
           const double bdt = g.rk.b * dtv * kk;
           if (g.rk.last) {
-            g.out[idx] = g.acc[idx] + bdt;
+            g.out[idx] = accv[a] + bdt;
           } else {
-            const double u0 = g.out[idx];
-            g.acc[idx] = (g.rk.first ? u0 : g.acc[idx]) + bdt;
+            const double u0 = u0v[a];
+            g.acc[idx] = (g.rk.first ? u0 : accv[a]) + bdt;
             g.stage[idx] = u0 + g.rk.a_next * dtv * kk;
           }
         }
       }
     }
+  };
+  if constexpr (EPI == EPI_RK) {
+    // (readfirstlane is convergent: this loop is not unrolled)
+#pragma unroll 1
+    for (int row = r0; row < r1; ++row) row_step(row);
+  } else {
+#pragma unroll 2
+    for (int row = r0; row < r1; ++row) row_step(row);
   }
 }
 

@@ -3,15 +3,20 @@
 // spop_lds_f32.hip).
 //
 // A workgroup owns 64 state columns (one per lane) and all M rows of the
-// output.  The K rows of B are streamed through one LDS buffer in chunks of
-// kc rows: every wavefront loads whole 64-column rows of the chunk (coalesced,
-// all loads independent), then each wavefront accumulates its quarter of the
-// output rows (rows w, w + 4, ...) in registers from LDS, using the chunk's
-// ELL entries (wave-uniform, scalar loads).  HBM sees each input once and
-// each output once; no B row is fetched twice from outside the workgroup,
+// output.  The K rows of B are streamed through LDS in chunks of at most kc
+// rows.  Each wavefront loads every fourth row of a chunk into registers
+// with all its loads in flight at once (buffer loads whose range is empty
+// past the chunk's last row or the last column: no branches, no memory
+// access there), and the loads of chunk c + 1 are issued before chunk c is
+// used, so they overlap its arithmetic.  Each wavefront then accumulates its
+// quarter of the output rows (rows w, w + 4, ...) in registers from LDS,
+// using the chunk's ELL entries (wave-uniform, scalar loads; padding entries
+// have value 0 and a column inside the chunk).  HBM sees each input once and
+// each output once: no B row is fetched twice from outside the workgroup,
 // however many operator rows use it.
 #pragma once
 
+#include "buffer.h"
 #include "kernels.h"
 
 namespace fr {
@@ -25,13 +30,22 @@ __global__ __launch_bounds__(256) void spop_lds_kernel(GemmArgs g,
                                                        const int32_t *__restrict__ cwidth) {
   extern __shared__ __align__(16) unsigned char spop_smem[];
   T *lds = reinterpret_cast<T *>(spop_smem);
+  // rows of one chunk a wavefront loads: the launcher keeps kc x 64 values
+  // within 64 KB
+  constexpr int KCW = 65536 / (64 * (int)sizeof(T)) / 4;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t col = (int64_t)blockIdx.x * 64 + lane;
   const bool cvalid = col < g.N;
-  const TB1 *__restrict__ B1 = (const TB1 *)g.B1 + (int64_t)blockIdx.y * g.sB1;
-  const TB2 *__restrict__ B2 = (const TB2 *)g.B2;
-  const int K1 = g.K1, K = g.K1 + g.K2;
+  const char *B1 = (const char *)g.B1 + (int64_t)blockIdx.y * g.sB1 * (int64_t)sizeof(TB1);
+  const char *B2 = (const char *)g.B2;
+  const int K1 = g.K1;
+  // a row of B: its N live columns in bytes (N <= ldb < 2^29, checked by the
+  // launcher), this lane's byte offset in it
+  const int nb1 = (int)(g.N * (int64_t)sizeof(TB1)), nb2 = (int)(g.N * (int64_t)sizeof(TB2));
+  const uint32_t off1 = (uint32_t)(col * (int64_t)sizeof(TB1));
+  const uint32_t off2 = (uint32_t)(col * (int64_t)sizeof(TB2));
+  const int64_t rs1 = g.ldb1 * (int64_t)sizeof(TB1), rs2 = g.ldb2 * (int64_t)sizeof(TB2);
   // output slots: operator rows, or (gradient transform) points whose DG
   // rows d Nu + rho are accumulated together
   constexpr int RPS = EPI == EPI_GRADT ? DG : 1;
@@ -42,18 +56,40 @@ __global__ __launch_bounds__(256) void spop_lds_kernel(GemmArgs g,
 #pragma unroll
     for (int d = 0; d < RPS; ++d) acc[m][d] = 0;
 
-  for (int c = 0; c < nchunk; ++c) {
-    const int k0 = cstart[c];
-    const int kn = cstart[c + 1] - k0;
-    const int wc = cwidth[c];
-    for (int i = w; i < kn; i += 4) {
+  // rows w + 4 j of chunk c into v[j] (0 past the chunk and past column N)
+  auto load_chunk = [&](int c, T(&v)[KCW]) {
+    const int k0 = cstart[c], kn = cstart[c + 1] - k0;
+#pragma unroll
+    for (int j = 0; j < KCW; ++j) {
+      const int i = w + 4 * j;
       const int k = k0 + i;
-      T v = 0;
-      if (cvalid)
-        v = k < K1 ? (T)B1[(int64_t)k * g.ldb1 + col] : (T)B2[(int64_t)(k - K1) * g.ldb2 + col];
-      lds[i * 64 + lane] = v;
+      const bool in = i < kn;
+      if constexpr (sizeof(TB1) == sizeof(TB2)) {
+        const char *row = k < K1 ? B1 + (int64_t)k * rs1 : B2 + (int64_t)(k - K1) * rs2;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)row, 0, __builtin_amdgcn_readfirstlane(in ? nb1 : 0), kRawBufferWord3);
+        v[j] = (T)load_row<TB1>(rs, off1);
+      } else {
+        // panels of two element types: one of the two loads has an empty range
+        const __amdgpu_buffer_rsrc_t r1 = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(B1 + (int64_t)k * rs1), 0,
+            __builtin_amdgcn_readfirstlane(in && k < K1 ? nb1 : 0), kRawBufferWord3);
+        const __amdgpu_buffer_rsrc_t r2 = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(B2 + (int64_t)(k - K1) * rs2), 0,
+            __builtin_amdgcn_readfirstlane(in && k >= K1 ? nb2 : 0), kRawBufferWord3);
+        v[j] = (T)load_row<TB1>(r1, off1) + (T)load_row<TB2>(r2, off2);
+      }
     }
-    __syncthreads();
+  };
+  auto store_chunk = [&](int c, const T(&v)[KCW]) {
+    const int kn = cstart[c + 1] - cstart[c];
+#pragma unroll
+    for (int j = 0; j < KCW; ++j) {
+      const int i = w + 4 * j;
+      if (i < kn) lds[i * 64 + lane] = v[j];
+    }
+  };
+  auto compute = [&](int c) {
 #pragma unroll
     for (int m = 0; m < MR; ++m) {
       const int slot = w + 4 * m;
@@ -65,13 +101,21 @@ __global__ __launch_bounds__(256) void spop_lds_kernel(GemmArgs g,
           const double *__restrict__ cv = vals + ((int64_t)c * g.M + row) * W;
           T s = 0;
 #pragma unroll
-          for (int e = 0; e < W; ++e)
-            if (e < wc) s += (T)cv[e] * lds[ci[e] * 64 + lane];
+          for (int e = 0; e < W; ++e) s += (T)cv[e] * lds[ci[e] * 64 + lane];
           acc[m][d] += s;
         }
       }
     }
+  };
+
+  T v[KCW];
+  load_chunk(0, v);
+  for (int c = 0; c < nchunk; ++c) {
+    if (c > 0) __syncthreads();  // every wavefront is done with chunk c - 1
+    store_chunk(c, v);
     __syncthreads();
+    if (c + 1 < nchunk) load_chunk(c + 1, v);  // in flight while chunk c is used
+    compute(c);
   }
   if (!cvalid) return;
 
@@ -80,11 +124,11 @@ __global__ __launch_bounds__(256) void spop_lds_kernel(GemmArgs g,
   const bool live = n < g.nelem;
   double dtv = 0;
   if (EPI == EPI_RK && live) dtv = g.dt[g.prob ? g.prob[n] : 0];
+  if constexpr (EPI == EPI_GRADT) {
 #pragma unroll
-  for (int m = 0; m < MR; ++m) {
-    const int slot = w + 4 * m;
-    if (slot >= nslot) break;
-    if constexpr (EPI == EPI_GRADT) {
+    for (int m = 0; m < MR; ++m) {
+      const int slot = w + 4 * m;
+      if (slot >= nslot) break;
       TC *C = (TC *)g.C;
       const int64_t plane = (int64_t)g.Nu * g.ld, pt = (int64_t)slot * g.ld + n;
       if (live) {
@@ -100,7 +144,42 @@ __global__ __launch_bounds__(256) void spop_lds_kernel(GemmArgs g,
 #pragma unroll
         for (int j = 0; j < DG; ++j) C[(int64_t)(j * g.Nu + slot) * g.ldc + col] = (TC)acc[m][j];
       }
-    } else {
+    }
+    return;
+  }
+  // Outputs eight rows at a time, with every load they need (1/J; for the
+  // RK4 update the state, read unless this is the last stage, and the
+  // register, read unless this is a first stage that is not also the last)
+  // issued before the first is used: buffer loads whose range is empty
+  // where nothing is read, so no branch makes them wait one by one.
+  const bool scaled = EPI == EPI_NEGDIV || EPI == EPI_RK;
+  const int nrj = scaled ? (int)(g.nelem * (int64_t)sizeof(double)) : 0;
+  const int nro = EPI == EPI_RK && !g.rk.last ? -1 : 0;
+  const int nra = EPI == EPI_RK && !(g.rk.first && !g.rk.last) ? -1 : 0;
+  const uint32_t offc = (uint32_t)(col * (int64_t)sizeof(double));
+  const uint32_t offn = (uint32_t)(n * (int64_t)sizeof(double));
+  constexpr int G = MR < 8 ? MR : 8;
+  static_assert(MR % G == 0, "rows per wavefront in groups of eight");
+#pragma unroll
+  for (int m0 = 0; m0 < MR; m0 += G) {
+    if (w + 4 * m0 >= nslot) break;
+    double rjv[G], u0v[G], accv[G];
+    if constexpr (scaled) {
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        const int64_t r = w + 4 * (m0 + q);
+        rjv[q] = load_row<double>(uniform_rsrc(g.rcpdjac + r * g.ld, r < nslot ? nrj : 0), offn);
+        if constexpr (EPI == EPI_RK) {
+          u0v[q] = load_row<double>(uniform_rsrc(g.out + r * g.ldc, r < nslot ? nro : 0), offc);
+          accv[q] = load_row<double>(uniform_rsrc(g.acc + r * g.ldc, r < nslot ? nra : 0), offc);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      const int m = m0 + q;
+      const int slot = w + 4 * m;
+      if (slot >= nslot) break;
       const int64_t idx = (int64_t)slot * g.ldc + col;
       if (EPI == EPI_STORE) {
         ((TC *)g.C)[(int64_t)blockIdx.y * g.sC + idx] = (TC)acc[m][0];
@@ -108,16 +187,17 @@ __global__ __launch_bounds__(256) void spop_lds_kernel(GemmArgs g,
         TC *cp = (TC *)g.C + (int64_t)blockIdx.y * g.sC + idx;
         *cp = (TC)((double)*cp + (double)acc[m][0]);
       } else {
-        const double kk = live ? -g.rcpdjac[(int64_t)slot * g.ld + n] * (double)acc[m][0] : 0.0;
+        // padding columns: exactly 0 whatever they hold (even NaN)
+        const double kk = live ? -rjv[q] * (double)acc[m][0] : 0.0;
         if (EPI == EPI_NEGDIV) {
           g.out[idx] = kk;
         } else {
           const double bdt = g.rk.b * dtv * kk;
           if (g.rk.last) {
-            g.out[idx] = g.acc[idx] + bdt;
+            g.out[idx] = accv[q] + bdt;
           } else {
-            const double u0 = g.out[idx];
-            g.acc[idx] = (g.rk.first ? u0 : g.acc[idx]) + bdt;
+            const double u0 = u0v[q];
+            g.acc[idx] = (g.rk.first ? u0 : accv[q]) + bdt;
             g.stage[idx] = u0 + g.rk.a_next * dtv * kk;
           }
         }
