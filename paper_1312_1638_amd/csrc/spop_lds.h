@@ -89,33 +89,71 @@ __global__ __launch_bounds__(256) void spop_lds_kernel(GemmArgs g,
       if (i < kn) lds[i * 64 + lane] = v[j];
     }
   };
-  auto compute = [&](int c) {
+  // The ELL entries this wavefront uses in a chunk (its MR slots x RPS rows
+  // x W entries) are held across the lanes of a few registers, one entry
+  // per lane, loaded with vector loads (prefetched with the chunk's rows);
+  // the product reads each back with v_readlane at a compile-time lane.
+  // No scalar memory access sits between the LDS reads, which therefore
+  // stay in flight together.
+  constexpr int NE = MR * RPS * W;
+  constexpr int NEV = (NE + 63) / 64;
+  auto load_ell = [&](int c, uint32_t(&ec)[NEV], uint32_t(&el)[NEV], uint32_t(&eh)[NEV]) {
+#pragma unroll
+    for (int q = 0; q < NEV; ++q) {
+      const int j = lane + 64 * q;
+      const int m = j / (RPS * W), d = (j / W) % RPS, e = j % W;
+      const int slot = w + 4 * m;
+      const bool ok = j < NE && slot < nslot;
+      const int row = EPI == EPI_GRADT ? d * g.Nu + slot : slot;
+      const int64_t at = ok ? ((int64_t)c * g.M + row) * W + e : 0;
+      const uint64_t bits = __builtin_bit_cast(uint64_t, vals[at]);
+      ec[q] = ok ? (uint32_t)colidx[at] : 0u;
+      el[q] = ok ? (uint32_t)bits : 0u;
+      eh[q] = ok ? (uint32_t)(bits >> 32) : 0u;
+    }
+  };
+  auto compute = [&](const uint32_t(&ec)[NEV], const uint32_t(&el)[NEV],
+                     const uint32_t(&eh)[NEV]) {
+    // (slots past the last row hold zero entries: they are computed, with
+    // no branch between the rows, and never stored)
 #pragma unroll
     for (int m = 0; m < MR; ++m) {
-      const int slot = w + 4 * m;
-      if (slot < nslot) {
 #pragma unroll
-        for (int d = 0; d < RPS; ++d) {
-          const int row = EPI == EPI_GRADT ? d * g.Nu + slot : slot;
-          const int32_t *__restrict__ ci = colidx + ((int64_t)c * g.M + row) * W;
-          const double *__restrict__ cv = vals + ((int64_t)c * g.M + row) * W;
-          T s = 0;
+      for (int d = 0; d < RPS; ++d) {
+        T s = 0;
 #pragma unroll
-          for (int e = 0; e < W; ++e) s += (T)cv[e] * lds[ci[e] * 64 + lane];
-          acc[m][d] += s;
+        for (int e = 0; e < W; ++e) {
+          const int j = (m * RPS + d) * W + e;
+          const int k = __builtin_amdgcn_readlane((int)ec[j / 64], j % 64);
+          const uint64_t bits =
+              ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)eh[j / 64], j % 64) << 32) |
+              (uint32_t)__builtin_amdgcn_readlane((int)el[j / 64], j % 64);
+          s += (T)__builtin_bit_cast(double, bits) * lds[k * 64 + lane];
         }
+        acc[m][d] += s;
       }
     }
   };
 
   T v[KCW];
+  uint32_t ec[NEV], el[NEV], eh[NEV], nc_[NEV], nl[NEV], nh[NEV];
+  load_ell(0, ec, el, eh);
   load_chunk(0, v);
   for (int c = 0; c < nchunk; ++c) {
     if (c > 0) __syncthreads();  // every wavefront is done with chunk c - 1
     store_chunk(c, v);
     __syncthreads();
-    if (c + 1 < nchunk) load_chunk(c + 1, v);  // in flight while chunk c is used
-    compute(c);
+    if (c + 1 < nchunk) {  // in flight while chunk c is used
+      load_ell(c + 1, nc_, nl, nh);
+      load_chunk(c + 1, v);
+    }
+    compute(ec, el, eh);
+#pragma unroll
+    for (int q = 0; q < NEV; ++q) {
+      ec[q] = nc_[q];
+      el[q] = nl[q];
+      eh[q] = nh[q];
+    }
   }
   if (!cvalid) return;
 

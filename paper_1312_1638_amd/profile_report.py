@@ -185,6 +185,56 @@ def gemm_sweep():
                                        for ms, m, n, w, tf in res[-3:]), flush=True)
 
 
+# Dense triangle operators of the batched 512-problem vortex mesh (2-D,
+# 4 fields, element counts per order as in that mesh): interpolation M0
+# (Nf x Nu) and the divergence [M3 | M1'] (Nu x (Nf + 2 Nu)).
+TRI_CASES = [(p, n) for p, n in ((2, 115552), (3, 134900), (4, 129744))]
+BF16_LDS_SHAPES = [(1, 4, 64), (2, 4, 64), (3, 4, 64), (4, 4, 64), (6, 4, 64),
+                   (1, 2, 64), (2, 2, 64), (3, 2, 64), (4, 2, 64), (6, 2, 64), (8, 2, 64),
+                   (1, 1, 64), (2, 1, 64), (3, 1, 64), (4, 1, 64), (6, 1, 64), (8, 1, 64),
+                   (12, 1, 64), (1, 4, 128), (2, 4, 128), (1, 2, 128), (2, 2, 128),
+                   (3, 2, 128), (4, 2, 128), (1, 1, 128), (2, 1, 128), (4, 1, 128),
+                   (6, 1, 128), (8, 1, 128)]
+
+
+def tri_sweep():
+    """Best plan per precision for the dense triangle operators: FP64 and
+    FP32 matrix-core tiles, BF16x3 register and LDS-staged tiles."""
+    from . import binding as B
+    print("| operator | M x K | N | FP64 us (plan) | FP32 us (plan) | BF16x3 us (plan) | "
+          "BF16x3 / FP32 | FP32 GB/s |")
+    print("|---|---|---|---|---|---|---|---|")
+    for p, nel in TRI_CASES:
+        nu, nf = (p + 1) * (p + 2) // 2, 3 * (p + 1)
+        N = 4 * (-(-nel // 64) * 64)
+        for name, M, K1, K2 in (("M0", nf, nu, 0), ("div", nu, nf, 2 * nu)):
+            MB = -(-M // 16)
+            best = {}
+            for prec in ("fp64", "fp32", "bf16x3"):
+                plans = []
+                for mbw, nc in SWEEP_SHAPES:
+                    wm = -(-MB // mbw)
+                    if mbw * (wm - 1) < MB:
+                        plans.append((mbw, nc, wm))
+                if prec == "bf16x3":
+                    plans += [(mbw, tw, wm) for mbw, wm, tw in BF16_LDS_SHAPES
+                              if mbw * wm >= MB and mbw * (wm - 1) < MB]
+                res = []
+                for plan in plans:
+                    try:
+                        ms = B.bench_gemm(prec, M, K1, K2, N, plan, 1, 10)
+                    except B.FRError:
+                        continue
+                    res.append((ms, plan))
+                best[prec] = min(res)
+            es = {"fp64": 8, "fp32": 4}
+            gbs = ((K1 + K2) + M) * N * es["fp32"] / (best["fp32"][0] * 1e-3) / 1e9
+            print(f"| tri p={p} {name} | {M} x {K1 + K2} | {N} | "
+                  + " | ".join("%.1f (%s)" % (best[q][0] * 1e3, ",".join(map(str, best[q][1])))
+                               for q in ("fp64", "fp32", "bf16x3"))
+                  + f" | {best['bf16x3'][0] / best['fp32'][0]:.2f} | {gbs:.0f} |", flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -204,6 +254,7 @@ def main(argv=None):
     t.add_argument("--last", type=int, default=0)
     sub.add_parser("hash")
     sub.add_parser("gemm-sweep")
+    sub.add_parser("tri-sweep")
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         stats(args.dir)
@@ -213,6 +264,8 @@ def main(argv=None):
         traffic(args.fetch_dir, args.write_dir, args.workload, args.step, args.kernel, args.last)
     elif args.cmd == "gemm-sweep":
         gemm_sweep()
+    elif args.cmd == "tri-sweep":
+        tri_sweep()
     else:
         print(source_hash())
 
