@@ -334,8 +334,8 @@ void make_op(fr_ctx *c, GemmOp &op, const std::vector<double> &A, int M, int K1,
       op.sp.rpg = 16;
       op.sp.fields = 1;
       // chunked copy for the LDS-staged kernel: each panel split into chunks
-      // of at most kcmax rows of B (the LDS a workgroup may use, up to 64 KB,
-      // for 64 columns), aligned
+      // of at most kcmax rows of B (kStagedRows, or fewer where the device
+      // allows a workgroup less LDS for 64 columns), aligned
       // where possible to the operator's blocks (hint1 rows of panel 1, such
       // as the points of one face; hint2 rows of panel 2, such as one
       // direction of the transformed flux), so that every operator row has
@@ -346,8 +346,10 @@ void make_op(fr_ctx *c, GemmOp &op, const std::vector<double> &A, int M, int K1,
         if (hipGetDevice(&dev) == hipSuccess)
           hipDeviceGetAttribute(&maxshm, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
       }
-      // at most 64 KB, and what the device allows a workgroup
-      const int kcmax = std::max(16, std::min(65536, maxshm) / (64 * (c->prec == FR_FP64 ? 8 : 4)));
+      // at most kStagedRows rows (64 KB of FP64 values) and what the device
+      // allows a workgroup
+      const int kcmax = std::max(
+          16, std::min(fr::kStagedRows, maxshm / (64 * (c->prec == FR_FP64 ? 8 : 4))));
       std::vector<int> starts(1, 0);
       for (int pn = 0; pn < 2; ++pn) {
         const int rows = pn ? K2 : K1, hint = pn ? hint2 : hint1;

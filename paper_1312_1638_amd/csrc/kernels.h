@@ -172,6 +172,8 @@ struct StagedOp {
   const int32_t *cwidth = nullptr;
 };
 #define FR_LDS_WIDTHS(X) X(4) X(5) X(6) X(8) X(12)
+// most B rows of one LDS chunk, in every precision (32 per wavefront)
+constexpr int kStagedRows = 128;
 // output rows per wavefront (4 wavefronts split the M rows of a tile)
 #define FR_LDS_ROWS(X) X(4) X(8) X(16) X(24) X(32) X(40)
 #define FR_LDS_ROWS_MAX 40

@@ -4,7 +4,7 @@
 //
 // A workgroup owns 64 state columns (one per lane) and all M rows of the
 // output.  The K rows of B are streamed through LDS in chunks of at most kc
-// rows.  Each wavefront loads every fourth row of a chunk into registers
+// (<= kStagedRows) rows.  Each wavefront loads every fourth row of a chunk into registers
 // with all its loads in flight at once (buffer loads whose range is empty
 // past the chunk's last row or the last column: no branches, no memory
 // access there), and the loads of chunk c + 1 are issued before chunk c is
@@ -30,9 +30,9 @@ __global__ __launch_bounds__(256) void spop_lds_kernel(GemmArgs g,
                                                        const int32_t *__restrict__ cwidth) {
   extern __shared__ __align__(16) unsigned char spop_smem[];
   T *lds = reinterpret_cast<T *>(spop_smem);
-  // rows of one chunk a wavefront loads: the launcher keeps kc x 64 values
-  // within 64 KB
-  constexpr int KCW = 65536 / (64 * (int)sizeof(T)) / 4;
+  // rows of one chunk a wavefront loads: chunks hold at most kStagedRows
+  // rows (checked by the launcher), 64 KB of FP64 or 32 KB of FP32 values
+  constexpr int KCW = kStagedRows / 4;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t col = (int64_t)blockIdx.x * 64 + lane;
@@ -300,8 +300,7 @@ hipError_t spop_lds_width_t(const GemmArgs &g, const StagedOp &op, int batch, hi
 template <typename T>
 hipError_t spop_lds_prec(int epi, const GemmArgs &g, const StagedOp &op, int batch, hipStream_t s) {
   if (g.N <= 0) return hipSuccess;
-  if (op.kc < 1 || op.nchunk < 1 || !op.cstart || !op.cwidth ||
-      (int64_t)op.kc * 64 * sizeof(T) > 65536)
+  if (op.kc < 1 || op.kc > kStagedRows || op.nchunk < 1 || !op.cstart || !op.cwidth)
     return hipErrorInvalidValue;
   switch (epi) {
     case EPI_STORE: return spop_lds_width_t<T, EPI_STORE, 0>(g, op, batch, s);

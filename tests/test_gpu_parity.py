@@ -192,6 +192,28 @@ def test_fused_gradient_transform_fp32(variant):
     C.check_fields(f"tgv5_p3 fp32 {variant}", got, ext, ext.field_tol)
 
 
+@pytest.mark.parametrize("name", ["tgv3_p4", "curved4_p4", "mixed5_p4_euler"])
+def test_staged_kernel_fp32(name):
+    """FP32 with every sparse operator product forced onto the LDS-staged
+    kernel: du/dt, and u after 3 RK4 steps (the staged kernel's RK4
+    epilogue in the captured graph), against the oracle at the FP32 bars."""
+    w = C.SMALL[name]()
+    d, s, u = _both(w, "fp32")
+    _force_plans(s, w, "staged")
+    tol, ext, floor = C.floor_tolerance(d, u, 1e-5, C.FP32_OVER_FP64)
+    got = s.unpack(s.rhs(s.pack(u)))
+    err = C.rel_l2(got, ext)
+    t = s.pack(u)
+    s.step(t, 1e-4, 3)
+    ref_u = d.rk4(u, 1e-4, 3)
+    eu = C.rel_l2(s.unpack(t), ref_u)
+    print(f"{name} fp32 staged: rhs rel L2 {err:.3e} (tol {tol:.2e}), u(3) {eu:.3e}")
+    assert err < tol
+    C.check_fields(f"{name} fp32 staged rhs", got, ext, ext.field_tol)
+    C.check_fields(f"{name} fp32 staged u(3)", s.unpack(t), ref_u,
+                   C.state_bar(ref_u, u, 1e-5, ext.field_tol))
+
+
 @pytest.mark.parametrize("name", ["vortex1_p3", "tgv1_p3", "tgv1_p4_ns_fp32"])
 def test_single_element_periodic_mesh(name):
     """The degenerate mesh: one element whose faces pair with its own
