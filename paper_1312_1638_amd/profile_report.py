@@ -140,6 +140,18 @@ def traffic(fetch_dir, write_dir, workload, step, kernel, last=0):
           f"{fw:.4f} | {total:.0f} | {source_hash()} |")
 
 
+def counters(dirs, kernel, last=0):
+    """Every counter of one or more --pmc runs, averaged over the last
+    `last` dispatches of the kernels whose name contains `kernel`."""
+    print(f"| counter | per dispatch (`{kernel}`) | dispatches |")
+    print("|---|---|---|")
+    for d in dirs:
+        names = sorted({_col(r, "Counter_Name") for r in _csv_rows(d, "_counter_collection.csv")})
+        for c in names:
+            mean, n = _mean_for(_per_dispatch(d, c), kernel, last)
+            print(f"| {c} | {mean:.4g} | {n} |")
+
+
 def read_traffic_table(path, workload, step):
     """HBM bytes per launch for (workload, step) from a table written by
     `traffic`, or None if absent or taken on other library sources."""
@@ -252,6 +264,10 @@ def main(argv=None):
     t.add_argument("dir")
     t.add_argument("--kernel", required=True)
     t.add_argument("--last", type=int, default=0)
+    k = sub.add_parser("counters")
+    k.add_argument("dirs", nargs="+")
+    k.add_argument("--kernel", required=True)
+    k.add_argument("--last", type=int, default=0)
     sub.add_parser("hash")
     sub.add_parser("gemm-sweep")
     sub.add_parser("tri-sweep")
@@ -266,6 +282,8 @@ def main(argv=None):
         gemm_sweep()
     elif args.cmd == "tri-sweep":
         tri_sweep()
+    elif args.cmd == "counters":
+        counters(args.dirs, args.kernel, args.last)
     else:
         print(source_hash())
 
