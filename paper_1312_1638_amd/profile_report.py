@@ -154,15 +154,16 @@ def counters(dirs, kernel, last=0):
 
 def read_traffic_table(path, workload, step):
     """HBM bytes per launch for (workload, step) from a table written by
-    `traffic`, or None if absent or taken on other library sources."""
+    `traffic`: the row taken on the current library sources, or None (rows
+    of earlier sources stay in the table as a record)."""
     if not os.path.exists(path):
         return None
     h = source_hash()
     with open(path) as fh:
         for line in fh:
             cells = [c.strip() for c in line.strip().strip("|").split("|")]
-            if len(cells) == 10 and cells[0] == workload and cells[1] == step:
-                return float(cells[8]) if cells[9] == h else None
+            if len(cells) == 10 and cells[0] == workload and cells[1] == step and cells[9] == h:
+                return float(cells[8])
     return None
 
 
