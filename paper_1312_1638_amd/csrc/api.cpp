@@ -820,11 +820,21 @@ void run_step(fr_ctx *c, int st, const double *u, double *dudt, int epi, const f
       g.C = elem(c->cur.uf, b.ufoff, ts); g.ldc = N; g.c_f32 = f32;
       g.N = N;
       hip_check(launch_op(b.m0, gprec, fr::EPI_STORE, g, 1, s), "gemm M0");
+    } else if (st == 0) {
+      // deviation form (Navier-Stokes): the state's deviation and reference
+      hip_check(fr::launch_devstate(point_args(c, b, u), s), "deviation");
     } else if (st == 3) {
       fr::GemmArgs g = gemm_args(b.s3);
       g.ld = b.ld;
       g.B1 = elem(c->cur.qf, b.qfoff, ts); g.ldb1 = N; g.b1_f32 = f32;
-      g.B2 = u + b.uoff; g.ldb2 = N; g.b2_f32 = 0;
+      // the gradient of the state from its deviation in the deviation form
+      // (the reference is constant in the element)
+      if (c->devform) {
+        g.B2 = elem(c->d_udev, b.uoff, ts); g.ldb2 = N; g.b2_f32 = 1;
+      } else {
+        g.B2 = u + b.uoff; g.ldb2 = N; g.b2_f32 = 0;
+      }
+      g.uprim = u + b.uoff; g.devflux = c->devform ? 1 : 0;
       g.C = elem(c->cur.ft, b.ftoff, ts); g.ldc = N; g.c_f32 = f32;
       g.N = N;
       if (gradt_fused(c, b)) {
@@ -878,27 +888,33 @@ void run_step(fr_ctx *c, int st, const double *u, double *dudt, int epi, const f
 // Order of the steps: the deviation form computes the transformed flux
 // first, since it also writes the deviations step 1 interpolates.
 const std::vector<int> &chain_order(const fr_ctx *c) {
-  static const std::vector<int> plain{1, 2, 3, 4, 5, 6, 7, 8}, dev{6, 1, 7, 8};
-  return c->devform ? dev : plain;
+  // deviation form: Euler writes the state's deviation with the flux (step
+  // 6 first); Navier-Stokes needs it before step 1, from a pass of its own
+  // (step 0), and takes the flux after the gradient as usual
+  static const std::vector<int> plain{1, 2, 3, 4, 5, 6, 7, 8}, dev{6, 1, 7, 8},
+      dev_ns{0, 1, 2, 3, 4, 5, 6, 7, 8};
+  return !c->devform ? plain : c->ns ? dev_ns : dev;
 }
 
 // The right-hand-side chain in its order, up to and including step `stop`
-// (stop 0: nothing).
+// (stop < 0: nothing; 0 is the deviation pass of Navier-Stokes in the
+// deviation form).
 void rhs_chain(fr_ctx *c, const double *u, double *dudt, int epi, const fr::RkCoef *rk,
                const double *dt, hipStream_t s, int stop = 8) {
-  if (stop < 1) return;
+  if (stop < 0) return;
   for (int st : chain_order(c)) {
     run_step(c, st, u, dudt, epi, rk, dt, s);
     if (st == stop) break;
   }
 }
 
-// The steps that come before `step` in the chain's order (inputs of step).
+// The step just before `step` in the chain's order (the chain up to it
+// makes step's inputs); -1 if none.
 int step_before(const fr_ctx *c, int step) {
   const std::vector<int> &o = chain_order(c);
   for (size_t i = 0; i < o.size(); ++i)
-    if (o[i] == step) return i ? o[i - 1] : 0;
-  return 0;
+    if (o[i] == step) return i ? o[i - 1] : -1;
+  return -1;
 }
 
 // Time every instantiated plan of each operator product on this mesh (the
@@ -1867,7 +1883,7 @@ fr_status fr_setup_mesh_bc(const fr_config *cfg, int32_t nblocks, const fr_block
                                     : (void *)dev_alloc<float>(c.get(), c->qf_len);
     c->d_acc = dev_alloc<double>(c.get(), c->total_len);
     c->d_stage = dev_alloc<double>(c.get(), c->total_len);
-    c->devform = !c->ns && c->prec != FR_FP64;
+    c->devform = c->prec != FR_FP64;
     if (c->devform) {
       c->d_udev = dev_alloc<float>(c.get(), c->total_len);
       int64_t nref = 0;

@@ -65,7 +65,11 @@ struct GemmArgs {
   RkCoef rk;
   const double *smat; int D; int Nu;          // EPI_GRADT: S = adj J [D][D][Nu][ld]
   void *fout; double gamma, mu, prandtl;      // EPI_GRADTF: F~ (type TC, layout of C)
-  const double *uprim, *qprim;                // EPI_TFVJP: primal u and Q (Q null: Euler)
+  // EPI_TFVJP: primal u and Q (Q null: Euler); EPI_GRADTF: u (the FP64
+  // state, rows of ldb values), with devflux: F~ less S f(u_ref), u_ref the
+  // element's first solution point (deviation form)
+  const double *uprim, *qprim;
+  int devflux;
   // sparse-row kernel with precomputed gathers: roff[r * width + e] is the
   // byte offset, from rbase, of the B row of entry e of operator row r
   // (both panels), rbase + (batch slice) addressed through one 32-bit
@@ -265,6 +269,9 @@ inline int64_t point_workgroups(int nupts, int64_t ld) { return ((int64_t)nupts 
 hipError_t launch_gradcoru(const PointArgs &a, hipStream_t s);
 // S6: f~ = S f(u, q) (Euler reads no q, writes f~ into q's storage)
 hipError_t launch_tflux(const PointArgs &a, int navier_stokes, hipStream_t s);
+// Deviation form (Navier-Stokes, reduced precision): a.udev = u - u_ref and
+// a.uref = u_ref, the first solution point of each element (FP64).
+hipError_t launch_devstate(const PointArgs &a, hipStream_t s);
 
 struct PairArgs {
   int ndims, nvars;

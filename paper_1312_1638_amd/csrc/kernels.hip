@@ -57,6 +57,25 @@ __global__ __launch_bounds__(256) void gradcoru_kernel(PointArgs a) {
   }
 }
 
+// Deviation form (Navier-Stokes): u - u_ref at every solution point and the
+// element's reference state u_ref (its first solution point) at point 0.
+template <int NV, typename TQ>
+__global__ __launch_bounds__(256) void devstate_kernel(PointArgs a) {
+  const int64_t plane = (int64_t)a.nupts * a.ld;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= plane) return;
+  const int64_t r = t / a.ld, n = t - r * a.ld;
+  if (n >= a.nelem) return;
+  const int64_t base = r * NV * a.ld + n;
+  TQ *ud = (TQ *)a.udev;
+#pragma unroll
+  for (int al = 0; al < NV; ++al) {
+    const double ub = a.u[n + al * a.ld];
+    ud[base + al * a.ld] = (TQ)(a.u[base + al * a.ld] - ub);
+    if (r == 0) a.uref[al * a.ld + n] = ub;
+  }
+}
+
 // MULTI: a multi-block launch (each workgroup's block from a.slots), a
 // separate instantiation so that the slot loads, which count as divergent,
 // stay out of the single-block kernel.
@@ -94,18 +113,23 @@ __global__ __launch_bounds__(256) void tflux_kernel(PointArgs a) {
   TQ *qo = a.fout ? (TQ *)a.fout : q;
   double f[D][NV], p, v[D];
   inviscid_flux<D>(u, a.gamma, f, p, v);
-  if (!NS && a.udev) {
+  if (a.udev) {
     // deviation form: the element's reference state (its first solution
-    // point), u - u_ref for the interpolation, f(u) - f(u_ref) for F~
+    // point); F~ from f(u) - f(u_ref) (the inviscid flux of the reference:
+    // its viscous flux is zero); Euler also writes u - u_ref for the
+    // interpolation here (Navier-Stokes writes it in a pass of its own
+    // before step 1, which needs it before any flux)
     double ub[NV], fb[D][NV], pb, vb[D];
 #pragma unroll
     for (int al = 0; al < NV; ++al) ub[al] = a.u[n + al * a.ld];
     inviscid_flux<D>(ub, a.gamma, fb, pb, vb);
-    TQ *ud = (TQ *)a.udev;
+    if (!NS) {
+      TQ *ud = (TQ *)a.udev;
 #pragma unroll
-    for (int al = 0; al < NV; ++al) {
-      ud[base + al * a.ld] = (TQ)(u[al] - ub[al]);
-      if (r == 0) a.uref[al * a.ld + n] = ub[al];
+      for (int al = 0; al < NV; ++al) {
+        ud[base + al * a.ld] = (TQ)(u[al] - ub[al]);
+        if (r == 0) a.uref[al * a.ld + n] = ub[al];
+      }
     }
 #pragma unroll
     for (int j = 0; j < D; ++j)
@@ -169,6 +193,15 @@ static hipError_t tflux_t(const PointArgs &a, int ns, hipStream_t s) {
   if (a.slots) return tflux_m<TQ, true>(a, ns, (unsigned)a.nwg, s);
   return tflux_m<TQ, false>(a, ns, blocks_for((int64_t)a.nupts * a.ld), s);
 }
+hipError_t launch_devstate(const PointArgs &a, hipStream_t s) {
+  if (!a.udev || !a.uref) return hipErrorInvalidValue;
+  const unsigned nb = blocks_for((int64_t)a.nupts * a.ld);
+  if (a.nvars == 4) devstate_kernel<4, float><<<nb, 256, 0, s>>>(a);
+  else if (a.nvars == 5) devstate_kernel<5, float><<<nb, 256, 0, s>>>(a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 hipError_t launch_tflux(const PointArgs &a, int ns, hipStream_t s) {
   return a.q_f32 ? tflux_t<float>(a, ns, s) : tflux_t<double>(a, ns, s);
 }
@@ -206,7 +239,7 @@ __device__ __forceinline__ Side side_of(const PairArgs &a, const int32_t *blk, i
   return s;
 }
 
-// Deviation form (Euler, reduced precision): the reference state of the
+// Deviation form (reduced precision): the reference state of the
 // element of flux point i (index sigma NV ld + n within its block) and the
 // normal component of its flux, n . f(u_ref).
 template <int D>
@@ -228,6 +261,15 @@ __device__ __forceinline__ void side_reference(const PairArgs &a, const Side &S,
   }
 }
 
+// Deviation form: the reference state of the element of flux point i.
+template <int D>
+__device__ __forceinline__ void side_state(const PairArgs &a, const Side &S, int64_t i,
+                                           double ub[D + 2]) {
+  const double *r = a.uref + S.rbase + i % S.ld;
+#pragma unroll
+  for (int al = 0; al < D + 2; ++al) ub[al] = r[al * S.ld];
+}
+
 template <int D, bool MULTI, typename T>
 __global__ __launch_bounds__(256) void con_u_kernel(PairArgs a, unsigned nreal) {
   constexpr int NV = D + 2;
@@ -240,11 +282,20 @@ __global__ __launch_bounds__(256) void con_u_kernel(PairArgs a, unsigned nreal) 
   const T *uf = (const T *)a.uf;
   T *cf = (T *)a.cf;
   const double wl = 0.5 - a.beta, wr = 0.5 + a.beta;
+  // deviation form: U^f holds each side's deviation from its element's
+  // reference; the common solution is formed from the full states and
+  // stored on each side as that side's deviation
+  double rL[NV] = {}, rR[NV] = {};
+  if (a.uref) {
+    side_state<D>(a, L, iL, rL);
+    side_state<D>(a, R, iR, rR);
+  }
 #pragma unroll
   for (int al = 0; al < NV; ++al) {
-    const double c = wl * (double)uf[L.base + iL + al * L.ld] + wr * (double)uf[R.base + iR + al * R.ld];
-    cf[L.qbase + iL + al * L.ld] = (T)c;
-    cf[R.qbase + iR + al * R.ld] = (T)c;
+    const double c = wl * ((double)uf[L.base + iL + al * L.ld] + rL[al]) +
+                     wr * ((double)uf[R.base + iR + al * R.ld] + rR[al]);
+    cf[L.qbase + iL + al * L.ld] = (T)(c - rL[al]);
+    cf[R.qbase + iR + al * R.ld] = (T)(c - rR[al]);
   }
 }
 
@@ -267,7 +318,7 @@ __global__ __launch_bounds__(256) void comm_flux_kernel(PairArgs a, unsigned nre
 #pragma unroll
   for (int d = 0; d < D; ++d) n[d] = a.nrm[d * a.npairs + k];
   double fnL[NV], fnR[NV];
-  const bool dev = !NS && a.uref;
+  const bool dev = a.uref != nullptr;
   if (dev) {
     double ub[NV];
     side_reference<D>(a, L, iL, n, ub, fnL);
@@ -322,14 +373,18 @@ __global__ __launch_bounds__(256) void bc_con_u_kernel(PairArgs a) {
   const int64_t i = a.lidx[k];
   const T *uf = (const T *)a.uf;
   T *cf = (T *)a.cf;
-  double u[NV], ginv[NV], gldg[NV];
+  double u[NV], ginv[NV], gldg[NV], rL[NV] = {};
+  // deviation form: the full state for the ghosts, the common solution
+  // stored as the deviation from the element's reference
+  if (a.uref) side_state<D>(a, L, i, rL);
 #pragma unroll
-  for (int al = 0; al < NV; ++al) u[al] = (double)uf[L.base + i + al * L.ld];
+  for (int al = 0; al < NV; ++al) u[al] = (double)uf[L.base + i + al * L.ld] + rL[al];
   bool qzero;
   bc_ghosts<D>(u, a.bcpar + (int64_t)a.bcid[k] * FR_BC_NPAR, a.gamma, ginv, gldg, qzero);
   const double wl = 0.5 - a.beta, wr = 0.5 + a.beta;
 #pragma unroll
-  for (int al = 0; al < NV; ++al) cf[L.qbase + i + al * L.ld] = (T)(wl * u[al] + wr * gldg[al]);
+  for (int al = 0; al < NV; ++al)
+    cf[L.qbase + i + al * L.ld] = (T)(wl * u[al] + wr * gldg[al] - rL[al]);
 }
 
 template <int D, int NS, bool MULTI, typename T>
@@ -346,7 +401,7 @@ __global__ __launch_bounds__(256) void bc_comm_flux_kernel(PairArgs a) {
 #pragma unroll
   for (int d = 0; d < D; ++d) n[d] = a.nrm[d * a.npairs + k];
   double fn[NV];
-  const bool dev = !NS && a.uref;
+  const bool dev = a.uref != nullptr;
   if (dev) {
     double ub[NV];
     side_reference<D>(a, L, i, n, ub, fn);

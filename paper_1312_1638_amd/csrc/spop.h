@@ -293,8 +293,8 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
             q[jj][a] = (double)qv;
           }
         if constexpr (EPI == EPI_GRADTF) {
-          // the state of the point is panel 2 (u, rows rho of every field)
-          const double *__restrict__ up = (const double *)g.B2 + (int64_t)rho * ldb + t;
+          // the FP64 state of the point (rows rho of every field)
+          const double *__restrict__ up = g.uprim + (int64_t)rho * ldb + t;
           double u[F], f[DG][F], fv[DG][F], p, v[DG];
 #pragma unroll
           for (int a = 0; a < F; ++a) u[a] = up[a * fs];
@@ -304,6 +304,18 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
           for (int jj = 0; jj < DG; ++jj)
 #pragma unroll
             for (int a = 0; a < F; ++a) f[jj][a] -= fv[jj][a];
+          if (g.devflux) {
+            // deviation form: less the inviscid flux of the element's
+            // reference state (its first solution point)
+            double ub[F], fb[DG][F], pb, vb[DG];
+#pragma unroll
+            for (int a = 0; a < F; ++a) ub[a] = g.uprim[t + a * fs];
+            inviscid_flux<DG>(ub, g.gamma, fb, pb, vb);
+#pragma unroll
+            for (int jj = 0; jj < DG; ++jj)
+#pragma unroll
+              for (int a = 0; a < F; ++a) f[jj][a] -= fb[jj][a];
+          }
           TC *Fo = (TC *)g.fout;
 #pragma unroll
           for (int i = 0; i < DG; ++i)
@@ -483,8 +495,8 @@ void spop_launch_gradt(const GemmArgs &g, const SparseOp &sp, hipStream_t s) {
   dim3 grid((unsigned)(spop_tiles<F>(g) * ngroups), 1);
   if constexpr (sizeof(T) == 8)
     spop_kernel<T, EPI, W, double, double, double, DG, F><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
-  else  // FP32 contexts: C^f in FP32 scratch (panel 1), the FP64 state (panel 2)
-    spop_kernel<T, EPI, W, float, double, float, DG, F><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
+  else  // FP32 contexts: C^f and the state's deviation (deviation form), both FP32
+    spop_kernel<T, EPI, W, float, float, float, DG, F><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
 }
 
 template <int W, int DG, int F>
@@ -519,7 +531,8 @@ hipError_t spop_addt_t(const GemmArgs &g, const SparseOp &sp, hipStream_t s) {
 template <typename T, int F, int EPI = EPI_GRADT>
 hipError_t spop_gradt_t(const GemmArgs &g, const SparseOp &sp, hipStream_t s) {
   if ((g.D != 2 && g.D != 3) || g.Nu * g.D != g.M || !g.smat) return hipErrorInvalidValue;
-  if (sizeof(T) == 4 && (!g.b1_f32 || g.b2_f32 || !g.c_f32)) return hipErrorInvalidValue;
+  if (sizeof(T) == 4 && (!g.b1_f32 || !g.b2_f32 || !g.c_f32)) return hipErrorInvalidValue;
+  if (EPI == EPI_GRADTF && !g.uprim) return hipErrorInvalidValue;
   // all fields per thread: F is the field count D + 2
   constexpr int DG = F == 4 ? 2 : 3;
   if (F > 1 && g.D != DG) return hipErrorInvalidValue;

@@ -260,7 +260,8 @@ void spop_lds_types(const GemmArgs &g, const StagedOp &op, int batch, hipStream_
   } else if constexpr (EPI == EPI_NEGDIV || EPI == EPI_RK) {
     spop_lds_go<T, EPI, W, MR, float, float, double, DG>(g, op, batch, s);
   } else if constexpr (EPI == EPI_GRADT) {
-    spop_lds_go<T, EPI, W, MR, float, double, float, DG>(g, op, batch, s);
+    // C^f and the state's deviation (deviation form), both FP32
+    spop_lds_go<T, EPI, W, MR, float, float, float, DG>(g, op, batch, s);
   } else {
     if (!g.b1_f32) spop_lds_go<T, EPI, W, MR, double, double, float, DG>(g, op, batch, s);
     else if (!g.b2_f32) spop_lds_go<T, EPI, W, MR, float, double, float, DG>(g, op, batch, s);
@@ -311,7 +312,7 @@ hipError_t spop_lds_prec(int epi, const GemmArgs &g, const StagedOp &op, int bat
       return hipErrorInvalidValue;
     case EPI_GRADT:
       if (batch != 1 || !g.smat || g.Nu * g.D != g.M) return hipErrorInvalidValue;
-      if (sizeof(T) == 4 && (!g.b1_f32 || g.b2_f32 || !g.c_f32)) return hipErrorInvalidValue;
+      if (sizeof(T) == 4 && (!g.b1_f32 || !g.b2_f32 || !g.c_f32)) return hipErrorInvalidValue;
       if (g.D == 2) return spop_lds_width_t<T, EPI_GRADT, 2>(g, op, batch, s);
       if (g.D == 3) return spop_lds_width_t<T, EPI_GRADT, 3>(g, op, batch, s);
       return hipErrorInvalidValue;
