@@ -1376,11 +1376,24 @@ void tune_adjoint_ops(fr_ctx *c, hipStream_t s) {
   hip_check(hipStreamSynchronize(s), "tune sync");
 }
 
+// The RK4 reverse update that follows a stage's right-hand-side adjoint
+// (the step adjoint's bookkeeping): acc += w and, unless last, the next
+// stage's scaled cotangent -J^-1 (ca dt lam + cb dt w) into c->d_lt, with
+// lam = lam_{n+1} in c->d_lc.
+struct RkAdj {
+  const double *dt;
+  double ca, cb;
+  bool last;
+  double *acc;
+};
+
 // lam_scaled: lam is c->d_lt already holding -J^-1 lam (written so by the
 // RK adjoint bookkeeping kernel), and the scaling kernel is skipped.
+// ra: the RK4 reverse update to apply to the result w = ulam, fused into
+// the last product's epilogue where its plan is the sparse-row kernel.
 void rhs_adjoint_chain(fr_ctx *c, const double *u, const double *lam, double *ulam,
                        hipStream_t s, Primal pr = Primal{nullptr, nullptr, nullptr},
-                       bool lam_scaled = false) {
+                       bool lam_scaled = false, const RkAdj *ra = nullptr) {
   const int D = c->D, NV = c->NV;
   if (!c->adj_tuned) {
     c->adj_tuned = true;
@@ -1428,11 +1441,29 @@ void rhs_adjoint_chain(fr_ctx *c, const double *u, const double *lam, double *ul
   if (c->ns) hip_check(fr::launch_con_u_vjp(adj_pair_args(c), s), "con_u_vjp");
   for (auto &b : c->blocks) {
     const int64_t N = (int64_t)NV * b.ld;
-    if (c->ns)
-      adj_gemm(c, b.t_fin, c->d_ftb + b.ftoff, c->d_ufb + b.ufoff, ulam + b.uoff, N, fr::EPI_ADD,
-               1, 0, 0, s);
-    else
-      adj_gemm(c, b.t_m0, c->d_ufb + b.ufoff, nullptr, ulam + b.uoff, N, fr::EPI_ADD, 1, 0, 0, s);
+    const GemmOp &fin = c->ns ? b.t_fin : b.t_m0;
+    const double *B1 = c->ns ? c->d_ftb + b.ftoff : c->d_ufb + b.ufoff;
+    const double *B2 = c->ns ? c->d_ufb + b.ufoff : nullptr;
+    if (ra && fin.MBW == 0 && !(fin.WM & kPlanStaged)) {
+      // w = ulam + the product, then the RK4 reverse update, in one pass
+      fr::GemmArgs g = gemm_args(fin);
+      g.B1 = B1; g.ldb1 = N; g.B2 = B2; g.ldb2 = N;
+      g.C = ulam + b.uoff; g.ldc = N; g.N = N;
+      g.ld = b.ld; g.nelem = b.nelem; g.rcpdjac = b.d_rcpdjac;
+      g.dt = ra->dt; g.prob = b.d_prob;
+      g.rk.a_next = ra->ca; g.rk.b = ra->cb; g.rk.first = 0; g.rk.last = ra->last;
+      g.acc = ra->acc + b.uoff; g.stage = c->d_lc + b.uoff;
+      g.out = ra->last ? nullptr : c->d_lt + b.uoff;
+      hip_check(launch_op(fin, fr::PREC_F64, fr::EPI_RKADJ, g, 1, s), "adjoint gemm + RK update");
+      continue;
+    }
+    adj_gemm(c, fin, B1, B2, ulam + b.uoff, N, fr::EPI_ADD, 1, 0, 0, s);
+    if (ra)
+      hip_check(fr::launch_rk_adj((int64_t)b.Nu * NV * b.ld, b.ld, b.nelem, b.d_prob, ra->dt,
+                                  ra->ca, ra->cb, c->d_lc + b.uoff, ulam + b.uoff,
+                                  ra->acc + b.uoff, ra->last ? nullptr : c->d_lt + b.uoff, 0,
+                                  NV, b.d_rcpdjac, nullptr, s),
+                "rk adjoint update");
   }
 }
 
@@ -1476,9 +1507,9 @@ void rk4_step_adjoint(fr_ctx *c, const double *u, const double *dt, const double
   static const double ca[3] = {1.0 / 3, 1.0 / 3, 1.0 / 6};
   static const double cb[3] = {1.0, 0.5, 0.5};
   for (int i = 0; i < 4; ++i) {
-    rhs_adjoint_chain(c, stages[i], c->d_lt, c->d_w, s, Primal{nullptr, nullptr, nullptr}, true);
-    if (i < 3) rk_adj_blocks(c, dt, ca[i], cb[i], lam_n, 0, false, s);
-    else rk_adj_blocks(c, dt, 0.0, 0.0, lam_n, 0, true, s);
+    const RkAdj ra{dt, i < 3 ? ca[i] : 0.0, i < 3 ? cb[i] : 0.0, i == 3, lam_n};
+    rhs_adjoint_chain(c, stages[i], c->d_lt, c->d_w, s, Primal{nullptr, nullptr, nullptr}, true,
+                      &ra);
   }
 }
 
@@ -1534,9 +1565,8 @@ void rk4_step_adjoint_stash(fr_ctx *c, double *stash, const double *dt, const do
   static const double cb[3] = {1.0, 0.5, 0.5};
   for (int i = 0; i < 4; ++i) {
     StashStage S = stash_stage(c, stash, 3 - i);
-    rhs_adjoint_chain(c, S.state, c->d_lt, c->d_w, s, Primal{S.uf, S.qf, S.q}, true);
-    if (i < 3) rk_adj_blocks(c, dt, ca[i], cb[i], lam_n, 0, false, s);
-    else rk_adj_blocks(c, dt, 0.0, 0.0, lam_n, 0, true, s);
+    const RkAdj ra{dt, i < 3 ? ca[i] : 0.0, i < 3 ? cb[i] : 0.0, i == 3, lam_n};
+    rhs_adjoint_chain(c, S.state, c->d_lt, c->d_w, s, Primal{S.uf, S.qf, S.q}, true, &ra);
   }
 }
 

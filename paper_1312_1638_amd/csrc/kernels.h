@@ -27,6 +27,11 @@ enum GemmEpi {
                    // (Navier-Stokes): EPI_GRADT, then the transformed flux
                    // F~ = S f(u, Q) of the point from the stored Q and the
                    // state (panel 2) into fout; padding columns get 0
+  EPI_RKADJ = 8,   // sparse-row kernel (adjoint, FP64): w = C + acc is the
+                   // state cotangent of an RK stage; then the step adjoint's
+                   // bookkeeping: acc_reg += w and (unless rk.last) out =
+                   // -rcpdjac (rk.a_next dt lam + rk.b dt w), lam read from
+                   // `stage`; C is only read; padding columns of out get 0
   EPI_TFVJP = 7    // sparse-row kernel, every field of an element per thread
                    // (adjoint, FP64): the D rows d Nu + rho of one point are
                    // F~b; then fb = S^T F~b and the reverse of the flux,

@@ -75,11 +75,11 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
   const TB1 *__restrict__ B1 = B1b + t;
   const TB2 *__restrict__ B2 = (const TB2 *)g.B2 + t;
   int64_t n = 0;
-  if (EPI == EPI_NEGDIV || EPI == EPI_RK || GT || EPI == EPI_ADDT)
+  if (EPI == EPI_NEGDIV || EPI == EPI_RK || GT || EPI == EPI_ADDT || EPI == EPI_RKADJ)
     n = F == 1 ? t % g.ld : t;
   const bool live = n < g.nelem;
   double dtv = 0;
-  if (EPI == EPI_RK && live) dtv = g.dt[g.prob ? g.prob[n] : 0];
+  if ((EPI == EPI_RK || EPI == EPI_RKADJ) && live) dtv = g.dt[g.prob ? g.prob[n] : 0];
   const int K1 = g.K1;
   // both panels have the row stride ldb, and N <= ldb < 2^29 (checked by
   // the launcher): a row of B spans under 4 GiB
@@ -369,7 +369,8 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
     T acc[F];
     row_product(row, acc);
     double rj = 0;
-    if (EPI == EPI_NEGDIV || EPI == EPI_RK) rj = live ? g.rcpdjac[(int64_t)row * g.ld + n] : 0.0;
+    if (EPI == EPI_NEGDIV || EPI == EPI_RK || EPI == EPI_RKADJ)
+      rj = live ? g.rcpdjac[(int64_t)row * g.ld + n] : 0.0;
 #pragma unroll
     for (int a = 0; a < F; ++a) {
       const int64_t idx = (int64_t)row * g.ldc + t + a * fs;
@@ -378,6 +379,11 @@ __global__ __launch_bounds__(256) void spop_kernel(GemmArgs g,
       } else if (EPI == EPI_ADD) {
         TC *cp = (TC *)g.C + (int64_t)blockIdx.y * g.sC + idx;
         *cp = (TC)((double)*cp + (double)acc[a]);
+      } else if (EPI == EPI_RKADJ) {
+        const double w = (double)((const TC *)g.C)[idx] + (double)acc[a];
+        g.acc[idx] += w;
+        if (!g.rk.last)
+          g.out[idx] = live ? -rj * (g.rk.a_next * dtv * g.stage[idx] + g.rk.b * dtv * w) : 0.0;
       } else {
         // padding columns: exactly 0 whatever they hold (even NaN)
         const double kk = live ? -rj * (double)acc[a] : 0.0;
@@ -417,7 +423,7 @@ template <typename T, int EPI, int W, typename TB1, typename TB2, typename TC, i
 void spop_go(const GemmArgs &g, const SparseOp &sp, dim3 grid, int ngroups, hipStream_t s) {
   // precomputed gathers where both panels have one element size (the
   // epilogues without point data: store, add, -1/J, RK update)
-  constexpr bool off_ok = sizeof(TB1) == sizeof(TB2) && EPI != EPI_ADD;
+  constexpr bool off_ok = sizeof(TB1) == sizeof(TB2) && EPI != EPI_ADD && EPI != EPI_RKADJ;
   if (off_ok && g.roff)
     spop_kernel<T, EPI, W, TB1, TB2, TC, 0, F, off_ok><<<grid, 256, 0, s>>>(g, sp.colidx, sp.vals, sp.rpg, ngroups);
   else
@@ -613,6 +619,9 @@ hipError_t launch_spop_f(int prec, int epi, const GemmArgs &g, const SparseOp &s
       case EPI_NEGDIV: return spop_launch_t<double, EPI_NEGDIV, F>(g, sp, batch, s);
       case EPI_RK: return spop_launch_t<double, EPI_RK, F>(g, sp, batch, s);
       case EPI_ADD: return spop_launch_t<double, EPI_ADD, F>(g, sp, batch, s);
+      case EPI_RKADJ:
+        if (batch != 1 || !g.acc || !g.stage || !g.dt || !g.rcpdjac) return hipErrorInvalidValue;
+        return spop_launch_t<double, EPI_RKADJ, F>(g, sp, batch, s);
     }
   } else if (prec == PREC_F32) {
     switch (epi) {
