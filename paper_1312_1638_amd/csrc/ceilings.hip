@@ -23,13 +23,14 @@ __global__ __launch_bounds__(256) void mfma_loop_kernel(int iters, T seed, doubl
   if (s == 12345.678) sink[0] = s;  // never true for the seeds used; keeps the loop live
 }
 
-__global__ __launch_bounds__(256) void triad_kernel(const double4 *__restrict__ b,
-                                                    const double4 *__restrict__ c,
-                                                    double4 *__restrict__ a, double s, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    const double4 x = b[i], y = c[i];
-    a[i] = make_double4(x.x + s * y.x, x.y + s * y.y, x.z + s * y.z, x.w + s * y.w);
-  }
+// One double per thread over a grid that covers the arrays: on MI355X this
+// form streams faster (6.2 TB/s) than a grid-stride loop over 32-byte
+// elements (5.2-5.5 TB/s), and nontemporal hints only slow it.
+__global__ __launch_bounds__(256) void triad_kernel(const double *__restrict__ b,
+                                                    const double *__restrict__ c,
+                                                    double *__restrict__ a, double s, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) a[i] = b[i] + s * c[i];
 }
 
 // kind 0: HBM triad GB/s; 1: FP64 MFMA TFLOP/s; 2: FP32 MFMA TFLOP/s
@@ -40,14 +41,14 @@ hipError_t measure_ceiling(int kind, double *value, hipStream_t s) {
   if ((err = hipEventCreate(&e1)) != hipSuccess) return err;
   float ms = 0;
   if (kind == 0) {
-    const int64_t n = (int64_t)1 << 26;  // 64 Mi double4 = 2 GiB per array
-    double4 *a = nullptr, *b = nullptr, *c = nullptr;
-    if ((err = hipMalloc(&a, n * sizeof(double4))) != hipSuccess) return err;
-    if ((err = hipMalloc(&b, n * sizeof(double4))) != hipSuccess) { hipFree(a); return err; }
-    if ((err = hipMalloc(&c, n * sizeof(double4))) != hipSuccess) { hipFree(a); hipFree(b); return err; }
-    hipMemsetAsync(b, 0, n * sizeof(double4), s);
-    hipMemsetAsync(c, 0, n * sizeof(double4), s);
-    const unsigned grid = 256 * 8 * 4;
+    const int64_t n = (int64_t)1 << 28;  // 256 Mi doubles = 2 GiB per array
+    double *a = nullptr, *b = nullptr, *c = nullptr;
+    if ((err = hipMalloc(&a, n * sizeof(double))) != hipSuccess) return err;
+    if ((err = hipMalloc(&b, n * sizeof(double))) != hipSuccess) { hipFree(a); return err; }
+    if ((err = hipMalloc(&c, n * sizeof(double))) != hipSuccess) { hipFree(a); hipFree(b); return err; }
+    hipMemsetAsync(b, 0, n * sizeof(double), s);
+    hipMemsetAsync(c, 0, n * sizeof(double), s);
+    const unsigned grid = (unsigned)(n / 256);
     for (int w = 0; w < 2; ++w) triad_kernel<<<grid, 256, 0, s>>>(b, c, a, 0.5, n);
     hipEventRecord(e0, s);
     const int reps = 10;
@@ -55,7 +56,7 @@ hipError_t measure_ceiling(int kind, double *value, hipStream_t s) {
     hipEventRecord(e1, s);
     hipEventSynchronize(e1);
     hipEventElapsedTime(&ms, e0, e1);
-    *value = 3.0 * n * sizeof(double4) * reps / (ms * 1e-3) / 1e9;
+    *value = 3.0 * n * sizeof(double) * reps / (ms * 1e-3) / 1e9;
     hipFree(a); hipFree(b); hipFree(c);
   } else {
     double *sink = nullptr;
