@@ -260,3 +260,26 @@ def test_grouped_step_graphs_equal_single_steps(stepper):
     err = C.rel_l2(s.unpack(outs[0]), ref)
     print(f"{stepper}: 2 x 19 steps, grouped == single bitwise; rel L2 vs oracle {err:.2e}")
     assert err < 1e-12
+
+
+def test_zero_steps_leave_the_state_and_negative_counts_are_refused():
+    """RK4 and forward Euler with 0 steps leave the state bitwise as it was
+    (no graph is captured or launched); a negative count is refused with
+    FR_EINVAL before anything runs, and the state is still untouched."""
+    import torch
+    import paper_1312_1638_amd as P
+    w = C.SMALL["vortex7_p3"]()
+    d = Discretisation(w)
+    s = C.solver_for(w)
+    t = s.pack(C.perturbed(d, d.initial_state(w)))
+    ref = t.clone()
+    s.step(t, 1e-3, 0)
+    s.euler_step(t, 1e-3, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(t, ref)
+    for call in (s.step, s.euler_step):
+        with pytest.raises(P.FRError) as e:
+            call(t, 1e-3, -1)
+        assert e.value.status == P.binding.FR_EINVAL
+    torch.cuda.synchronize()
+    assert torch.equal(t, ref)

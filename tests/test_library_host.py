@@ -181,3 +181,28 @@ def test_block_too_large_is_rejected(ndims, etype, nelem):
     st = L.fr_check_mesh(ctypes.byref(cfg), 1, ctypes.byref(blk), 0, None, ctypes.byref(n))
     assert st == P.binding.FR_EINVAL
     assert "too large" in L.fr_last_error(None).decode()
+
+
+def _one_quad_block(nelem, etype="quad", ndims=2):
+    nodes = np.zeros((max(nelem, 1), 2 ** ndims, ndims))
+    return P.binding.FrBlock(etype=P.binding.ETYPE[etype], order=1, geom_order=1, correction=0,
+                             nelem=nelem, nodes=nodes.ctypes.data, problem=None), nodes
+
+
+@pytest.mark.parametrize("case", ["no blocks", "block without elements", "ndims 4",
+                                  "hex in 2-D", "quad in 3-D"])
+def test_degenerate_meshes_are_refused(case):
+    """Empty and inconsistent meshes are refused by the host check with
+    FR_EINVAL and a message, before anything is allocated."""
+    import ctypes
+    L = _lib()
+    ndims = {"ndims 4": 4, "hex in 2-D": 2, "quad in 3-D": 3}.get(case, 2)
+    etype = {"hex in 2-D": "hex", "quad in 3-D": "quad"}.get(case, "quad")
+    blk, _nodes = _one_quad_block(0 if case == "block without elements" else 1, etype,
+                                  3 if etype == "hex" else 2)
+    cfg = P.binding._config(ndims, "euler", "fp64", 1.4, 0.0, 0.72, 0.5, 0.1, 0, 1)
+    n = ctypes.c_int64()
+    nblocks = 0 if case == "no blocks" else 1
+    st = L.fr_check_mesh(ctypes.byref(cfg), nblocks, ctypes.byref(blk), 0, None, ctypes.byref(n))
+    assert st == P.binding.FR_EINVAL, (case, st)
+    assert L.fr_last_error(None).decode()
