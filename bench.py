@@ -567,7 +567,9 @@ def main():
         extra["adjoint"] = adjoint_ratio(P, configs, torch)
 
     line = {
-        "metric": "RHS DOF-updates/s",
+        # the headline is the FP64 rate; the FP32 and BF16-split legs and the
+        # adjoint/forward cost ratio are the "fp32", "bf16x3" and "adjoint" keys
+        "metric": "RHS DOF-updates/s FP64 vs FP32/BF16-split; adjoint/forward cost ratio",
         "value": value,
         "unit": "DOF-updates/s",
         "n_gpus": 1,
