@@ -46,6 +46,42 @@ def test_byte_model_of_the_fused_gradient_step():
     assert bench.step_model(S, 6, 8)[0] == 0   # step 6 costs nothing when fused
 
 
+def test_byte_model_of_the_rk4_divergence_step():
+    """The headline's dominant kernel, the divergence with the RK4 update of a
+    middle stage (bench step 9), curved 48^3 p=4 FP64: D~ (150 flux points)
+    and F~ (3 x 125 points) read per state column, 1/J per point, and four
+    state arrays (u and the register read, the register and the next stage
+    written): 4.645 GB per launch, the figure bench.py's roofline uses.
+    Step 8 (-1/J only) writes du/dt instead of the four arrays."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    class Blk:
+        etype, order = "hex", 4
+
+    class Mesh:
+        blocks = [Blk()]
+
+    class S:
+        ndims, nvars, system = 3, 5, "euler"
+        blocks = [dict(nelem=48 ** 3, nupts=125)]
+        mesh = Mesh()
+        nfpts = {("hex", 4): 150}
+        nnz = {("hex", 4): dict(M0=750, M3=750, M4p=1875, M6=750, M1p=1875)}
+        fused_gradt = [False]
+        fused_flux = [False]
+        npairs = 0
+
+    ne, nu = 48 ** 3, 125
+    cols = 5 * ne
+    byts9, flops9 = bench.step_model(S, 9, 8)
+    assert byts9 == cols * (150 + 3 * 125) * 8 + nu * ne * 8 + 4 * nu * cols * 8
+    assert byts9 == 4644864000
+    byts8, flops8 = bench.step_model(S, 8, 8)
+    assert byts8 == byts9 - 3 * nu * cols * 8 and flops8 == flops9
+    assert flops9 == 2.0 * (750 + 1875) * cols
+
+
 def test_sample_holds_the_edge_elements():
     """The sampled elements always include element 0, the last element, one
     in the last 256-column tile and both sides of the first XCD tile-group
