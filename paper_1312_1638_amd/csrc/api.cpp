@@ -722,6 +722,9 @@ void run_multi(fr_ctx *c, int st, const double *u, double *dudt, int epi, const 
   if (!multi_usable(c, st)) return;
   const int f32 = c->prec != FR_FP64;
   const int gprec = c->prec == FR_FP64 ? fr::PREC_F64 : fr::PREC_F32;
+  // the chain's epilogue (-1/J or the RK4 update) belongs to step 8; steps
+  // 1 and 5 store their products, as their launches per block do
+  const int sepi = st == 8 ? epi : fr::EPI_STORE;
   for (int fam = 0; fam < 2; ++fam) {
     MultiLaunch &ml = c->multi[st][fam];
     if (!ml.on) continue;
@@ -749,12 +752,12 @@ void run_multi(fr_ctx *c, int st, const double *u, double *dudt, int epi, const 
       }
     }
     if (fam == 0) {
-      hip_check(fr::launch_spop_multi(gprec, epi, g, ml.width, ml.fields, batch, s),
+      hip_check(fr::launch_spop_multi(gprec, sepi, g, ml.width, ml.fields, batch, s),
                 "multi-block sparse-row product");
     } else {
       // g.N is per slot; any positive value passes the launcher's empty check
       g.MBW = ml.MBW; g.NC = ml.NC; g.N = 1;
-      hip_check(fr::launch_gemm(gprec, epi, g, batch, s), "multi-block matrix-core product");
+      hip_check(fr::launch_gemm(gprec, sepi, g, batch, s), "multi-block matrix-core product");
     }
     for (int bi : ml.blocks) done[bi] = 1;
   }
@@ -1002,12 +1005,9 @@ void tune_op(fr_ctx *c, GemmOp &op, int step, BlockRT &b, hipStream_t s) {
   }
 }
 
-// One launch per kernel family over the blocks of a multi-block mesh is
-// switched off: with it, the set-up or the first right-hand side of a
-// 12-problem batched mesh (six blocks) made a GPU memory access fault whose
-// cause is not yet found.  The launches stay built but unused; multi-block
-// meshes launch per block.
-constexpr bool kMultiBlockLaunches = false;
+// One launch per kernel family over the blocks of a multi-block mesh, kept
+// by the set-up where it is not slower than a launch per block.
+constexpr bool kMultiBlockLaunches = true;
 
 // Mean time of step st over 5 launches (after 2), with the RK epilogue the
 // step graph uses for step 8 (dt = 0: values meaningless, traffic the same).
@@ -1081,8 +1081,7 @@ void autotune(fr_ctx *c, hipStream_t s) {
       tune_op(c, b.m5, 5, b, s);
     }
   }
-  // one launch per kernel family over several blocks: switched off (see
-  // kMultiBlockLaunches)
+  // one launch per kernel family over several blocks
   if (kMultiBlockLaunches) tune_multi(c, s);
   hip_check(hipStreamSynchronize(s), "tune sync");
 }
@@ -1925,10 +1924,8 @@ fr_status fr_setup_mesh_bc(const fr_config *cfg, int32_t nblocks, const fr_block
     c->cur = fr_ctx::Bufs{c->d_uf, c->d_qf, c->d_ft, c->d_uf, c->ns ? c->d_fto : c->d_ft,
                           c->d_stage};
     // precomputed row offsets of the sparse-row products of steps 1, 5 and 8
-    // (single-block meshes: on meshes of several blocks the precomputed-gather
-    // kernel is not used, as the multi-block launches built on it are off)
+    // (per block, and the multi-block launches' slots)
     for (auto &b : c->blocks) {
-      if (c->blocks.size() > 1) break;
       const int64_t rsu = (int64_t)NV * b.ld * 8, rst = (int64_t)NV * b.ld * (int64_t)c->tsize;
       // step 1 reads the state, or in the deviation form its FP32 deviation
       const int64_t rs0 = c->devform ? rst : rsu;

@@ -183,7 +183,11 @@ void launch_gemm_kind(const GemmArgs &g, dim3 grid, hipStream_t s) {
 template <typename T, int MBW, int NC, int EPI>
 hipError_t launch_gemm_shape(const GemmArgs &g, int batch, hipStream_t s) {
   if (g.slots) {
-    // multi-block launch: every slot's workgroups
+    // multi-block launch: every slot's workgroups (the -1/J and RK4
+    // epilogues write through out and the RK registers)
+    if ((EPI == EPI_NEGDIV || EPI == EPI_RK) && !g.out) return hipErrorInvalidValue;
+    if (EPI == EPI_RK && (!g.acc || !g.dt || (!g.rk.last && !g.stage))) return hipErrorInvalidValue;
+    if (EPI == EPI_STORE && !g.C) return hipErrorInvalidValue;
     launch_gemm_kind<T, MBW, NC, EPI, true>(g, dim3((unsigned)g.nwg, batch), s);
   } else {
     const int64_t wgs = gemm_workgroups(g.N, NC, g.WM);

@@ -451,6 +451,10 @@ template <int F>
 hipError_t launch_spop_multi_f(int prec, int epi, const GemmArgs &g, int width, int batch,
                                hipStream_t s) {
   if (!g.slots || g.nslots < 1 || g.nwg < 1) return hipErrorInvalidValue;
+  // the -1/J and RK4 epilogues write through out (and the RK registers)
+  if ((epi == EPI_NEGDIV || epi == EPI_RK) && !g.out) return hipErrorInvalidValue;
+  if (epi == EPI_RK && (!g.acc || !g.dt || (!g.rk.last && !g.stage))) return hipErrorInvalidValue;
+  if (epi == EPI_STORE && !g.C) return hipErrorInvalidValue;
   if (prec == PREC_F32 && epi == EPI_STORE && g.b1_f32 && !g.b2_f32 && g.B2)
     return hipErrorInvalidValue;  // panels of two element sizes
 #define FR_W(W_)                                                                     \

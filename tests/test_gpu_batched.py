@@ -76,9 +76,6 @@ def test_full_batch_sampled_problems():
         assert e_r < tol_r and e_u < 1e-12
 
 
-@pytest.mark.skip(reason="multi-block launches are switched off in the library: with them on, "
-                         "a 12-problem batched mesh made a GPU memory access fault whose cause "
-                         "is not yet found")
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_one_launch_per_kernel_family(prec):
     """Twelve problems in six element blocks (quads and triangles at p = 2, 3,
