@@ -50,7 +50,7 @@ def test_small_batch_rhs_steps_integrals():
 def test_full_batch_sampled_problems():
     """512 problems (~5.7e5 elements, 6 element blocks), 20 RK4 steps in the
     captured graph; 4 seeded problems re-run alone through the oracle."""
-    w = configs.CONFIGS["cfg4"]()
+    w = configs.CONFIGS["batched512"]()
     s = C.solver_for(w)
     u0 = [np.ascontiguousarray(np.transpose(w.ic(b, s.solution_points(b)), (1, 2, 0)))
           for b in range(len(w.mesh.blocks))]

@@ -66,25 +66,25 @@ def _uniform_stream(w, shape):
     return np.broadcast_to(cons[None, :, None], shape).copy()
 
 
-def test_cfg3_curved48_p4():
+def test_curved48_p4():
     """48^3 curved Q2 hexes, p=4, Euler (6.9e7 DOF): sampled du/dt within
     the stated 1e-12 of the long-double evaluation (whole sample and each
     field), mass, momentum and energy through 10 RK4 steps, and a uniform
     stream."""
-    w = configs.CONFIGS["cfg3"]()
+    w = configs.CONFIGS["curved48_p4"]()
     s = C.solver_for(w)
     u0 = _initial(s, w)
     t = s.pack(u0)
     err, tol, floor, r = _sampled_rhs(w, s, t, rings=1)
-    print(f"cfg3 sampled du/dt rel L2 {err:.2e} (oracle's FP64 floor {floor:.2e}, bar 1e-12)")
+    print(f"curved48_p4 sampled du/dt rel L2 {err:.2e} (oracle's FP64 floor {floor:.2e}, bar 1e-12)")
     assert err < 1e-12
     drift = _conserved(s, t, s.integrate(t).cpu().numpy()[0], lambda: s.step(t, w.dt, w.nsteps))
-    print(f"cfg3 integrals after {w.nsteps} steps: relative drift {drift:.2e}")
+    print(f"curved48_p4 integrals after {w.nsteps} steps: relative drift {drift:.2e}")
     assert drift < 1e-12
     # uniform stream: du/dt vanishes to round-off (free-stream preservation)
     ru = s.unpack(s.rhs(s.pack([_uniform_stream(w, u0[0].shape)])))[0]
     rel = np.abs(ru).max() / np.abs(r).max()
-    print(f"cfg3 uniform stream: max|du/dt| / max|du/dt(perturbed)| = {rel:.2e}")
+    print(f"curved48_p4 uniform stream: max|du/dt| / max|du/dt(perturbed)| = {rel:.2e}")
     assert rel < 1e-10
 
 
@@ -105,9 +105,9 @@ _REDUCED = {"fp32": (1e-5, C.FP32_OVER_FP64, 1e-6, 2.0 ** -9),
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-def test_cfg3_curved48_p4_reduced_precision(prec):
+def test_curved48_p4_reduced_precision(prec):
     stated, ratio, drift_bar, uni_bar = _REDUCED[prec]
-    w = configs.CONFIGS["cfg3"]()
+    w = configs.CONFIGS["curved48_p4"]()
     s = C.solver_for(w, prec)
     u0 = _initial(s, w)
     t = s.pack(u0)
@@ -115,16 +115,16 @@ def test_cfg3_curved48_p4_reduced_precision(prec):
     sample = _sample(w.mesh.blocks[0].nelem, 12, 33)
     tol, ext, floor = _patch_reference(w, sample, 1, stated, ratio)
     err = C.rel_l2([r[:, :, sample]], ext)
-    print(f"cfg3 {prec} sampled du/dt rel L2 {err:.2e} (FP64 floor {floor:.2e}, bar {tol:.2e})")
+    print(f"curved48_p4 {prec} sampled du/dt rel L2 {err:.2e} (FP64 floor {floor:.2e}, bar {tol:.2e})")
     assert err < tol
-    C.check_fields(f"cfg3 {prec} sampled du/dt", [r[:, :, sample]], ext, ext.field_tol)
+    C.check_fields(f"curved48_p4 {prec} sampled du/dt", [r[:, :, sample]], ext, ext.field_tol)
     drift = _conserved(s, t, s.integrate(t).cpu().numpy()[0], lambda: s.step(t, w.dt, w.nsteps))
-    print(f"cfg3 {prec} integrals after {w.nsteps} steps: relative drift {drift:.2e} "
+    print(f"curved48_p4 {prec} integrals after {w.nsteps} steps: relative drift {drift:.2e} "
           f"(bar {drift_bar:.0e})")
     assert drift < drift_bar
     ru = s.unpack(s.rhs(s.pack([_uniform_stream(w, u0[0].shape)])))[0]
     rel = np.abs(ru).max() / np.abs(r).max()
-    print(f"cfg3 {prec} uniform stream: max|du/dt| / max|du/dt(perturbed)| = {rel:.2e} "
+    print(f"curved48_p4 {prec} uniform stream: max|du/dt| / max|du/dt(perturbed)| = {rel:.2e} "
           f"(bar {uni_bar:.1e})")
     assert rel < uni_bar
 
@@ -158,27 +158,27 @@ def test_curved12_p4_u_after_10_steps(prec):
 _ORACLE_U10 = {}
 
 
-def test_cfg5_tgv24_sampled_rhs_and_conservation():
+def test_tgv24_p3_sampled_rhs_and_conservation():
     """24^3 hexes, p=3, Navier-Stokes: sampled du/dt (two-ring patches) and
     conservation through the 200 steps of the adjoint horizon."""
-    w = configs.CONFIGS["cfg5"]()
+    w = configs.CONFIGS["tgv24_p3"]()
     s = C.solver_for(w)
     t = s.pack(_initial(s, w))
     err, tol, floor, _ = _sampled_rhs(w, s, t, rings=2, nsample=8)
-    print(f"cfg5 sampled du/dt rel L2 {err:.2e} (floor {floor:.2e}, tol {tol:.2e})")
+    print(f"tgv24_p3 sampled du/dt rel L2 {err:.2e} (floor {floor:.2e}, tol {tol:.2e})")
     assert err < tol
     drift = _conserved(s, t, s.integrate(t).cpu().numpy()[0], lambda: s.step(t, w.dt, w.nsteps))
-    print(f"cfg5 integrals after {w.nsteps} steps: relative drift {drift:.2e}")
+    print(f"tgv24_p3 integrals after {w.nsteps} steps: relative drift {drift:.2e}")
     assert drift < 1e-12
 
 
-def test_cfg5_gradient_against_central_differences_32_directions():
+def test_tgv24_p3_gradient_against_central_differences_32_directions():
     """Gradient of E_k(u_200) with respect to u_0 (checkpoint every 20 steps)
     against central differences of the library's FP64 forward map along 32
     seeded directions, each scaled per field by that field's RMS."""
     import torch
     from paper_1312_1638_amd.autograd import KineticEnergy, integrate_steps
-    w = configs.CONFIGS["cfg5"]()
+    w = configs.CONFIGS["tgv24_p3"]()
     s = C.solver_for(w)
     u0h = _initial(s, w)
     u0 = s.pack(u0h)

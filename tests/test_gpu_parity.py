@@ -258,9 +258,9 @@ def test_padding_is_zero_and_inert():
     assert C.rel_l2(s.unpack(out), d.rhs(u)) < 1e-12
 
 
-def test_cfg1_rhs_and_100_steps():
+def test_vortex20_p3_rhs_and_100_steps():
     """Vortex, 20x20 quads, p=3: du/dt and u after 100 RK4 steps, dt=1e-3."""
-    w = configs.CONFIGS["cfg1"]()
+    w = configs.CONFIGS["vortex20_p3"]()
     d, s, u = _both(w, perturb=False)
     ref = d.rhs(u)
     t = s.pack(u)
@@ -270,18 +270,18 @@ def test_cfg1_rhs_and_100_steps():
     s.step(t, w.dt, 60)           # two replays of the captured step graph
     ref_u = d.rk4(u, w.dt, 100)
     e_u = C.rel_l2(s.unpack(t), ref_u)
-    print(f"cfg1: rhs {e_rhs:.3e}  u(100) {e_u:.3e}")
+    print(f"vortex20_p3: rhs {e_rhs:.3e}  u(100) {e_u:.3e}")
     assert e_rhs < 1e-12 and e_u < 1e-12
     _tol, ext, _floor = C.floor_tolerance(d, u, 1e-12)
-    C.check_fields("cfg1 rhs", got, ext, ext.field_tol)
-    C.check_fields("cfg1 u(100)", s.unpack(t), ref_u, C.state_bar(ref_u, u, 1e-12, ext.field_tol))
+    C.check_fields("vortex20_p3 rhs", got, ext, ext.field_tol)
+    C.check_fields("vortex20_p3 u(100)", s.unpack(t), ref_u, C.state_bar(ref_u, u, 1e-12, ext.field_tol))
 
 
-def test_cfg2_rhs_and_100_steps():
+def test_tgv16_p3_rhs_and_100_steps():
     """Taylor-Green, 16^3 hexes, p=3, Navier-Stokes: du/dt and u after the
     workload's 100 RK4 steps (dt 3e-4), in FP64 and on the FP32 operator
     path (FP64 state, update and reductions)."""
-    w = configs.CONFIGS["cfg2"]()
+    w = configs.CONFIGS["tgv16_p3"]()
     assert w.nsteps == 100
     d, s, u = _both(w, perturb=False)
     tol64, ext, floor = C.floor_tolerance(d, u, 1e-12)
@@ -294,7 +294,7 @@ def test_cfg2_rhs_and_100_steps():
     ref_u = u
     for k in range(0, w.nsteps, 20):          # the oracle, with a progress line per 20 steps
         ref_u = d.rk4(ref_u, w.dt, min(20, w.nsteps - k))
-        print(f"cfg2: oracle at step {min(k + 20, w.nsteps)}", flush=True)
+        print(f"tgv16_p3: oracle at step {min(k + 20, w.nsteps)}", flush=True)
     e_u = C.rel_l2(s.unpack(t), ref_u)
     s32 = C.solver_for(w, "fp32")
     t32 = s32.pack(u)
@@ -302,15 +302,15 @@ def test_cfg2_rhs_and_100_steps():
     e32 = C.rel_l2(g32, ext)
     s32.step(t32, w.dt, w.nsteps)
     e32u = C.rel_l2(s32.unpack(t32), ref_u)
-    print(f"cfg2: fp64 floor {floor:.2e} | rhs {e_rhs:.3e} (tol {tol64:.1e}) u(100) {e_u:.3e} | "
+    print(f"tgv16_p3: fp64 floor {floor:.2e} | rhs {e_rhs:.3e} (tol {tol64:.1e}) u(100) {e_u:.3e} | "
           f"fp32 rhs {e32:.3e} (tol {tol32:.1e}) u(100) {e32u:.3e}")
     assert e_rhs < tol64 and e_u < 1e-12
     assert e32 < tol32 and e32u < 1e-5
-    C.check_fields("cfg2 fp64 rhs", g64, ext, ext.field_tol)
-    C.check_fields("cfg2 fp64 u(100)", s.unpack(t), ref_u,
+    C.check_fields("tgv16_p3 fp64 rhs", g64, ext, ext.field_tol)
+    C.check_fields("tgv16_p3 fp64 u(100)", s.unpack(t), ref_u,
                    C.state_bar(ref_u, u, 1e-12, ext.field_tol))
-    C.check_fields("cfg2 fp32 rhs", g32, ext, ftol32)
-    C.check_fields("cfg2 fp32 u(100)", s32.unpack(t32), ref_u, C.state_bar(ref_u, u, 1e-5, ftol32))
+    C.check_fields("tgv16_p3 fp32 rhs", g32, ext, ftol32)
+    C.check_fields("tgv16_p3 fp32 u(100)", s32.unpack(t32), ref_u, C.state_bar(ref_u, u, 1e-5, ftol32))
 
 
 def test_rk_graph_replay_matches_single_steps():

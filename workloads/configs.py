@@ -266,9 +266,9 @@ def adjoint_tgv(n=24, order=3, nsteps=200, dt=2e-4, ckpt=20):
 
 
 CONFIGS = {
-    "cfg1": lambda: vortex_quads(20, 3),
-    "cfg2": lambda: taylor_green_hexes(16, 3),
-    "cfg3": lambda: curved_freestream_hexes(48, 4),
-    "cfg4": lambda: batched_vortices(512),
-    "cfg5": lambda: adjoint_tgv(24, 3),
+    "vortex20_p3": lambda: vortex_quads(20, 3),
+    "tgv16_p3": lambda: taylor_green_hexes(16, 3),
+    "curved48_p4": lambda: curved_freestream_hexes(48, 4),
+    "batched512": lambda: batched_vortices(512),
+    "tgv24_p3": lambda: adjoint_tgv(24, 3),
 }
